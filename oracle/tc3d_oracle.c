@@ -1,0 +1,463 @@
+/*
+ * tc3d_oracle.c -- plain CPU oracle (see tc3d_oracle.h).
+ *
+ * TEST INFRASTRUCTURE: only the test suite, the smoke check and the CPU
+ * baseline of the benchmark load this file's library. It is deliberately slow
+ * and literal: every step follows the paper's definitions in the paper's order,
+ * one shot at a time, with uint8 bits and FP64 arithmetic. No blocking, fusion
+ * or reordering beyond what the definitions state.
+ *
+ * Readings of points the paper leaves open (each also listed in the design
+ * notes of the repository):
+ *   - noise per cycle: every qubit flips with probability p, then every check
+ *     outcome flips with probability q (phenomenological model, Sections 3.1
+ *     and 4.1, p = q in all experiments);
+ *   - the syndrome is measured once per cycle; BP, flip and p-flip all act on
+ *     a working copy that is updated with the parity of every correction they
+ *     make; the accumulated correction is applied at the end of the cycle
+ *     (the schedule listed in Section 3.2);
+ *   - BP restarts from the priors every cycle and always runs the requested
+ *     number of iterations, then flips every bit with posterior < 0
+ *     (Section 4.1, "local" BP); a posterior of exactly 0 is not flipped;
+ *   - after the noisy cycles one more cycle may run with perfect measurements
+ *     (qubit noise still on unless disabled), decoded the same way;
+ *   - majority vote: a logical error on axis d is declared when at least half
+ *     of the L^2 parallel logical Z strings along d have odd parity (a tie
+ *     counts as a failure).
+ */
+#include "tc3d_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct tco_lattice {
+    int32_t L;
+    int64_t n_sites, n_edges, n_faces;
+    int32_t* face_edge; /* [n_faces][4]                               */
+    int32_t* edge_face; /* [n_edges][4]: the faces containing the edge  */
+    int32_t* edge_slot; /* [n_edges][4]: member index k inside that face */
+};
+
+/* ---------------------------------------------------------------- geometry */
+
+static int64_t site_of(int32_t L, int64_t x, int64_t y, int64_t z) {
+    x = ((x % L) + L) % L;
+    y = ((y % L) + L) % L;
+    z = ((z % L) + L) % L;
+    return x + (int64_t)L * (y + (int64_t)L * z);
+}
+
+/* Section 2: one qubit per edge of the cubic lattice, one Z check per face;
+ * a face check acts on the four edges of its boundary. */
+tco_lattice* tco_lattice_new(int32_t L) {
+    if (L < 2) return NULL;
+    tco_lattice* lat = (tco_lattice*)calloc(1, sizeof(tco_lattice));
+    lat->L = L;
+    lat->n_sites = (int64_t)L * L * L;
+    lat->n_edges = 3 * lat->n_sites;
+    lat->n_faces = 3 * lat->n_sites;
+    lat->face_edge = (int32_t*)malloc(sizeof(int32_t) * 4 * lat->n_faces);
+    lat->edge_face = (int32_t*)malloc(sizeof(int32_t) * 4 * lat->n_edges);
+    lat->edge_slot = (int32_t*)malloc(sizeof(int32_t) * 4 * lat->n_edges);
+    int32_t* fill = (int32_t*)calloc(lat->n_edges, sizeof(int32_t));
+    const int64_t N = lat->n_sites;
+    for (int32_t n = 0; n < 3; ++n) {
+        /* the two axes spanning a face with normal n, in increasing order */
+        int32_t a = (n == 0) ? 1 : 0;
+        int32_t b = (n == 2) ? 1 : 2;
+        for (int64_t z = 0; z < L; ++z)
+            for (int64_t y = 0; y < L; ++y)
+                for (int64_t x = 0; x < L; ++x) {
+                    int64_t c[3] = {x, y, z};
+                    int64_t v = site_of(L, x, y, z);
+                    int64_t f = n * N + v;
+                    int64_t ca[3] = {c[0], c[1], c[2]};
+                    int64_t cb[3] = {c[0], c[1], c[2]};
+                    ca[a] += 1; /* v + unit(a) */
+                    cb[b] += 1; /* v + unit(b) */
+                    int64_t m[4];
+                    m[0] = a * N + v;
+                    m[1] = a * N + site_of(L, cb[0], cb[1], cb[2]);
+                    m[2] = b * N + v;
+                    m[3] = b * N + site_of(L, ca[0], ca[1], ca[2]);
+                    for (int k = 0; k < 4; ++k) {
+                        lat->face_edge[4 * f + k] = (int32_t)m[k];
+                        int32_t j = fill[m[k]]++;
+                        if (j < 4) {
+                            lat->edge_face[4 * m[k] + j] = (int32_t)f;
+                            lat->edge_slot[4 * m[k] + j] = k;
+                        }
+                    }
+                }
+    }
+    free(fill);
+    return lat;
+}
+
+void tco_lattice_free(tco_lattice* lat) {
+    if (!lat) return;
+    free(lat->face_edge);
+    free(lat->edge_face);
+    free(lat->edge_slot);
+    free(lat);
+}
+
+int64_t tco_n_edges(const tco_lattice* lat) { return lat->n_edges; }
+
+void tco_incidence(const tco_lattice* lat, int32_t* face_edge, int32_t* edge_face,
+                   int32_t* edge_slot) {
+    if (face_edge) memcpy(face_edge, lat->face_edge, sizeof(int32_t) * 4 * lat->n_faces);
+    if (edge_face) memcpy(edge_face, lat->edge_face, sizeof(int32_t) * 4 * lat->n_edges);
+    if (edge_slot) memcpy(edge_slot, lat->edge_slot, sizeof(int32_t) * 4 * lat->n_edges);
+}
+
+/* ------------------------------------------------------------- randomness */
+
+/* Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 Philox
+ * S-box; each round multiplies words 0 and 2 by the two round multipliers,
+ * the high halves are mixed with the other two words and the key, and the
+ * key is advanced by the two Weyl increments between rounds. */
+void tco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+uint64_t tco_threshold(double prob) {
+    if (!(prob > 0.0)) return 0;
+    double t = floor(prob * 4294967296.0);
+    if (t > 4294967295.0) t = 4294967295.0;
+    return (uint64_t)t;
+}
+
+/* The uniform word of shot s is word (s mod 4) of the block at counter
+ * (site, cycle, s div 4, tag); key = (low, high) 32-bit halves of the seed. */
+uint32_t tco_uniform(uint64_t seed, uint32_t site, uint32_t cycle, uint64_t shot, uint32_t tag) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {site, cycle, (uint32_t)(shot / 4), tag};
+    uint32_t out[4];
+    tco_philox4x32_10(ctr, key, out);
+    return out[shot % 4];
+}
+
+/* A p-flip coin is one bit of the 64-bit word (r0 | r1 << 32) of the block at
+ * counter (edge, cycle, s div 64, 2 + sweep): bit s mod 64. It is 1 with
+ * probability exactly 1/2, matching "x < 0.5" for x uniform on (0,1) in the
+ * p-flip algorithm (Section 3.2). */
+int tco_coin(uint64_t seed, uint32_t edge, uint32_t cycle, uint32_t sweep, uint64_t shot) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {edge, cycle, (uint32_t)(shot / 64), 2u + sweep};
+    uint32_t out[4];
+    tco_philox4x32_10(ctr, key, out);
+    uint64_t w = (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+    return (int)((w >> (shot % 64)) & 1u);
+}
+
+/* ------------------------------------------------------------------ noise */
+
+/* Phenomenological noise (Sections 3.1, 4.1): independent bit flips with
+ * probability prob on every qubit (kind 0) or check outcome (kind 1). */
+void tco_sample_noise(const tco_lattice* lat, uint8_t* bits, int32_t kind, double prob,
+                      uint64_t seed, uint32_t cycle, uint64_t shot0, int64_t n_shots) {
+    int64_t n = (kind == 0) ? lat->n_edges : lat->n_faces;
+    uint64_t th = tco_threshold(prob);
+    for (int64_t s = 0; s < n_shots; ++s)
+        for (int64_t i = 0; i < n; ++i)
+            if ((uint64_t)tco_uniform(seed, (uint32_t)i, cycle, shot0 + (uint64_t)s,
+                                      (uint32_t)kind) < th)
+                bits[s * n + i] ^= 1u;
+}
+
+/* --------------------------------------------------------------- syndrome */
+
+/* Section 2: a Z check on a face reports the parity of X errors on its four
+ * boundary edges. */
+void tco_syndrome(const tco_lattice* lat, const uint8_t* err, uint8_t* syn, int64_t n_shots,
+                  int32_t xor_into) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    for (int64_t s = 0; s < n_shots; ++s) {
+        const uint8_t* e = err + s * n;
+        uint8_t* o = syn + s * m;
+        for (int64_t f = 0; f < m; ++f) {
+            uint8_t par = 0;
+            for (int k = 0; k < 4; ++k) par ^= e[lat->face_edge[4 * f + k]];
+            o[f] = xor_into ? (uint8_t)(o[f] ^ par) : par;
+        }
+    }
+}
+
+/* ---------------------------------------------------------- flip / p-flip */
+
+/* |UNSAT(b)|: unsatisfied checks among the four containing bit b. */
+static int unsat_count(const tco_lattice* lat, const uint8_t* syn, int64_t b) {
+    int u = 0;
+    for (int j = 0; j < 4; ++j) u += syn[lat->edge_face[4 * b + j]];
+    return u;
+}
+
+/* Apply a set of flips found in one parallel sweep: every flipped bit toggles
+ * the correction and the four checks containing it. */
+static void apply_flips(const tco_lattice* lat, const uint8_t* flips, uint8_t* syn,
+                        uint8_t* corr) {
+    for (int64_t b = 0; b < lat->n_edges; ++b) {
+        if (!flips[b]) continue;
+        corr[b] ^= 1u;
+        for (int j = 0; j < 4; ++j) syn[lat->edge_face[4 * b + j]] ^= 1u;
+    }
+}
+
+/* flip (Section 3.1), parallel version (Section 3.2): the rule "flip b when
+ * |SAT(b)| < |UNSAT(b)|" is evaluated on every bit against the same syndrome,
+ * then all selected bits are flipped at once. */
+void tco_flip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, int64_t n_shots) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    uint8_t* F = (uint8_t*)malloc(n);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        uint8_t* sy = syn + s * m;
+        for (int64_t b = 0; b < n; ++b) {
+            int unsat = unsat_count(lat, sy, b);
+            int sat = 4 - unsat;
+            F[b] = (uint8_t)(sat < unsat);
+        }
+        apply_flips(lat, F, sy, corr + s * n);
+    }
+    free(F);
+}
+
+/* p-flip (Section 3.2): as flip, and a bit with |SAT| = |UNSAT| flips when its
+ * coin is 1. All bits are evaluated against the same syndrome. */
+void tco_pflip_sweep_coins(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
+                           const uint8_t* coins) {
+    const int64_t n = lat->n_edges;
+    uint8_t* F = (uint8_t*)malloc(n);
+    for (int64_t b = 0; b < n; ++b) {
+        int unsat = unsat_count(lat, syn, b);
+        int sat = 4 - unsat;
+        if (sat < unsat)
+            F[b] = 1;
+        else if (sat == unsat)
+            F[b] = (uint8_t)(coins[b] != 0);
+        else
+            F[b] = 0;
+    }
+    apply_flips(lat, F, syn, corr);
+    free(F);
+}
+
+void tco_pflip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, uint64_t seed,
+                     uint32_t cycle, uint32_t sweep, uint64_t shot0, int64_t n_shots) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    uint8_t* coins = (uint8_t*)malloc(n);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        for (int64_t b = 0; b < n; ++b)
+            coins[b] = (uint8_t)tco_coin(seed, (uint32_t)b, cycle, sweep, shot0 + (uint64_t)s);
+        tco_pflip_sweep_coins(lat, syn + s * m, corr + s * n, coins);
+    }
+    free(coins);
+}
+
+/* flip as first stated (Section 3.1): one bit at a time. */
+int64_t tco_sequential_flip(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
+                            int64_t max_flips) {
+    int64_t flips = 0;
+    while (flips < max_flips) {
+        int64_t pick = -1;
+        for (int64_t b = 0; b < lat->n_edges && pick < 0; ++b) {
+            int unsat = unsat_count(lat, syn, b);
+            if (4 - unsat < unsat) pick = b;
+        }
+        if (pick < 0) break;
+        corr[pick] ^= 1u;
+        for (int j = 0; j < 4; ++j) syn[lat->edge_face[4 * pick + j]] ^= 1u;
+        ++flips;
+    }
+    return flips;
+}
+
+/* ---------------------------------------------------------------------- BP */
+
+/* One flooding iteration of sum-product BP in LLR form (Section 4.1).
+ *   E1  l0_i = ln(P(v_i=0)/P(v_i=1)); for the binary symmetric channel
+ *       l0 = ln((1-p)/p).
+ *   E3  variable-to-factor: M(i->f) = l0_i + sum over the other factors f'
+ *       of bit i of M(f'->i). At the first iteration there are no factor
+ *       messages yet and M(i->f) = l0_i.
+ *   E2  factor-to-variable: M(f->i) = (-1)^{s_f} 2 atanh(prod over the other
+ *       neighbours i' of f of tanh(M(i'->f)/2)).
+ *       Each check also has one measurement-error variable of degree 1
+ *       (Section 4.1, measurement errors); its message to f is always its
+ *       prior ln((1-q)/q), so its factor in the product is tanh of half that.
+ *   E4  posterior: l_i = l0_i + sum over all factors f of i of M(f->i). */
+void tco_bp_step(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
+                 double p_dec, double q_dec, const double* nu_in, double* nu_out,
+                 double* post) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    const double l0s = log((1.0 - p_dec) / p_dec);
+    const double lm = log((1.0 - q_dec) / q_dec); /* measurement variable prior */
+    double* mu = (double*)malloc(sizeof(double) * 4 * m);
+    /* E3 */
+    for (int64_t f = 0; f < m; ++f)
+        for (int k = 0; k < 4; ++k) {
+            int64_t i = lat->face_edge[4 * f + k];
+            double msg = llr0 ? llr0[i] : l0s;
+            if (nu_in)
+                for (int j = 0; j < 4; ++j) {
+                    int64_t g = lat->edge_face[4 * i + j];
+                    if (g == f) continue;
+                    msg += nu_in[4 * g + lat->edge_slot[4 * i + j]];
+                }
+            mu[4 * f + k] = msg;
+        }
+    /* E2 */
+    for (int64_t f = 0; f < m; ++f)
+        for (int k = 0; k < 4; ++k) {
+            double prod = tanh(lm / 2.0);
+            for (int kk = 0; kk < 4; ++kk)
+                if (kk != k) prod *= tanh(mu[4 * f + kk] / 2.0);
+            double sign = syn[f] ? -1.0 : 1.0;
+            nu_out[4 * f + k] = sign * 2.0 * atanh(prod);
+        }
+    /* E4 */
+    if (post)
+        for (int64_t i = 0; i < n; ++i) {
+            double l = llr0 ? llr0[i] : l0s;
+            for (int j = 0; j < 4; ++j)
+                l += nu_out[4 * lat->edge_face[4 * i + j] + lat->edge_slot[4 * i + j]];
+            post[i] = l;
+        }
+    free(mu);
+}
+
+/* Local BP (Section 4.1): a fixed number of iterations, then every bit whose
+ * posterior LLR is negative is flipped. */
+void tco_bp_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
+                   const double* llr0, double p_dec, double q_dec, int32_t iters,
+                   uint8_t* corr, double* post) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    double* nu_a = (double*)malloc(sizeof(double) * 4 * m);
+    double* nu_b = (double*)malloc(sizeof(double) * 4 * m);
+    double* l = (double*)malloc(sizeof(double) * n);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        const uint8_t* sy = syn + s * m;
+        const double* pr = llr0 ? llr0 + s * n : NULL;
+        double* cur = NULL;
+        for (int32_t it = 0; it < iters; ++it) {
+            double* next = (cur == nu_a) ? nu_b : nu_a;
+            tco_bp_step(lat, sy, pr, p_dec, q_dec, cur, next, l);
+            cur = next;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            double li = l[i];
+            if (iters <= 0) li = pr ? pr[i] : log((1.0 - p_dec) / p_dec);
+            corr[s * n + i] = (uint8_t)(li < 0.0);
+            if (post) post[s * n + i] = li;
+        }
+    }
+    free(nu_a);
+    free(nu_b);
+    free(l);
+}
+
+/* ------------------------------------------------------------------ readout */
+
+/* Section 2: a logical Z operator of qubit d is a string of the L edges along
+ * axis d through fixed values of the other two coordinates; the L^2 such
+ * strings are disjoint. A logical X error flips all of them. The readout is a
+ * majority vote over the strings' parities (Section 3.1, Fig. 1 caption). */
+void tco_logical_check(const tco_lattice* lat, const uint8_t* err, int64_t n_shots,
+                       uint8_t* mask, int32_t* odd) {
+    const int32_t L = lat->L;
+    const int64_t n = lat->n_edges, N = lat->n_sites;
+    for (int64_t s = 0; s < n_shots; ++s) {
+        const uint8_t* e = err + s * n;
+        uint8_t msk = 0;
+        for (int d = 0; d < 3; ++d) {
+            int32_t count = 0;
+            for (int64_t i = 0; i < L; ++i)
+                for (int64_t j = 0; j < L; ++j) {
+                    uint8_t par = 0;
+                    for (int64_t t = 0; t < L; ++t) {
+                        int64_t c[3];
+                        c[d] = t;
+                        c[(d + 1) % 3] = i;
+                        c[(d + 2) % 3] = j;
+                        par ^= e[d * N + site_of(L, c[0], c[1], c[2])];
+                    }
+                    count += par;
+                }
+            if (odd) odd[3 * s + d] = count;
+            if (2 * (int64_t)count >= (int64_t)L * L) msk |= (uint8_t)(1u << d);
+        }
+        mask[s] = msk;
+    }
+}
+
+/* --------------------------------------------------------------- experiment */
+
+/* Multi-cycle Monte Carlo (Sections 3.1, 3.2, 4.2): per cycle, noise, one
+ * syndrome measurement, BP (if enabled) whose correction also updates the
+ * working syndrome, the flip / p-flip schedule on that working syndrome, then
+ * the accumulated correction is applied and the residual carries over. */
+void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot0,
+                    int64_t n_shots, uint8_t* err, uint8_t* mask, int32_t* odd,
+                    uint8_t* trace) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    const int32_t cycles = prm->noisy_cycles + (prm->perfect_final ? 1 : 0);
+    uint8_t* syn = (uint8_t*)malloc(m);
+    uint8_t* corr = (uint8_t*)malloc(n);
+    uint8_t* cbp = (uint8_t*)malloc(n);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        const uint64_t shot = shot0 + (uint64_t)s;
+        uint8_t* e = err + s * n;
+        for (int32_t t = 0; t < cycles; ++t) {
+            const int noisy = t < prm->noisy_cycles;
+            const double pt = (noisy || prm->final_qubit_noise) ? prm->p : 0.0;
+            const double qt = noisy ? prm->q : 0.0;
+            tco_sample_noise(lat, e, 0, pt, prm->seed, (uint32_t)t, shot, 1);
+            tco_syndrome(lat, e, syn, 1, 0);
+            tco_sample_noise(lat, syn, 1, qt, prm->seed, (uint32_t)t, shot, 1);
+            memset(corr, 0, n);
+            if (prm->bp_iters > 0) {
+                tco_bp_decode(lat, syn, 1, NULL, prm->p_dec, prm->q_dec, prm->bp_iters, cbp,
+                              NULL);
+                for (int64_t i = 0; i < n; ++i) corr[i] = cbp[i];
+                tco_syndrome(lat, cbp, syn, 1, 1);
+            }
+            for (int32_t k = 0; k < prm->n_sweeps; ++k) {
+                if ((prm->pflip_mask >> k) & 1u)
+                    tco_pflip_sweep(lat, syn, corr, prm->seed, (uint32_t)t, (uint32_t)k, shot,
+                                    1);
+                else
+                    tco_flip_sweep(lat, syn, corr, 1);
+            }
+            for (int64_t i = 0; i < n; ++i) e[i] ^= corr[i];
+            if (trace) memcpy(trace + ((int64_t)t * n_shots + s) * n, e, n);
+        }
+        tco_logical_check(lat, e, 1, mask + s, odd ? odd + 3 * s : NULL);
+    }
+    free(syn);
+    free(corr);
+    free(cbp);
+}

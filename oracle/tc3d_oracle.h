@@ -1,0 +1,112 @@
+/*
+ * tc3d_oracle.h -- plain CPU oracle for shot-parallel Monte Carlo decoding of
+ * X errors on the L x L x L periodic 3D toric code (Scruby & Nemoto, "Local
+ * Probabilistic Decoding of a Quantum Code", Quantum 2023).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark may load this library. It shares no code, header,
+ * table or constant with the GPU library; the two meet only through the
+ * published definitions (the paper's equations and algorithms, and the
+ * Philox4x32-10 generator of Salmon, Moraes, Dror and Shaw, SC'11).
+ *
+ * Representation: one shot at a time, one uint8 (0 or 1) per qubit or check,
+ * FP64 belief propagation. Arrays of several shots are [shot][site].
+ *
+ * Geometry (Section 2): qubits on the 3L^3 edges, Z checks on the 3L^3 faces.
+ *   site  v = x + L*y + L*L*z                        (coordinates mod L)
+ *   edge  e(v,a) = a*L^3 + v      edge from v to v + unit(a)
+ *   face  f(v,n) = n*L^3 + v      unit square at corner v with normal n;
+ *         its spanning axes a < b (both != n) give the members, in order
+ *         k=0: e(v,a)   k=1: e(v+unit(b),a)   k=2: e(v,b)   k=3: e(v+unit(a),b)
+ */
+#ifndef TC3D_ORACLE_H
+#define TC3D_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tco_lattice tco_lattice;
+
+/* Run parameters of one Monte Carlo experiment (Sections 3-4). */
+typedef struct {
+    double p;                 /* qubit X-error probability per cycle           */
+    double q;                 /* check-outcome error probability per cycle      */
+    double p_dec;             /* BP prior: l0 = ln((1-p_dec)/p_dec)             */
+    double q_dec;             /* BP measurement-error prior                     */
+    int32_t noisy_cycles;     /* cycles with measurement noise                  */
+    int32_t perfect_final;    /* 1: one more cycle with q = 0                   */
+    int32_t final_qubit_noise;/* 1: that final cycle still adds qubit noise     */
+    int32_t bp_iters;         /* 0: no BP                                       */
+    int32_t n_sweeps;         /* number of flip / p-flip sweeps after BP        */
+    uint32_t pflip_mask;      /* bit k set: sweep k is p-flip, else flip        */
+    uint64_t seed;            /* Philox key                                     */
+} tco_params;
+
+tco_lattice* tco_lattice_new(int32_t L);
+void tco_lattice_free(tco_lattice* lat);
+int64_t tco_n_edges(const tco_lattice* lat);
+/* face_edge: [n_faces][4] member edges; edge_face/edge_slot: [n_edges][4] */
+void tco_incidence(const tco_lattice* lat, int32_t* face_edge, int32_t* edge_face,
+                   int32_t* edge_slot);
+
+/* Philox4x32-10 block function. */
+void tco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* floor(prob * 2^32) clamped to [0, 2^32-1]; a trial fires iff U < threshold. */
+uint64_t tco_threshold(double prob);
+/* Uniform 32-bit word of (site, cycle, shot, tag). */
+uint32_t tco_uniform(uint64_t seed, uint32_t site, uint32_t cycle, uint64_t shot, uint32_t tag);
+/* Coin of p-flip sweep `sweep` at (edge, cycle, shot). */
+int tco_coin(uint64_t seed, uint32_t edge, uint32_t cycle, uint32_t sweep, uint64_t shot);
+
+/* bits[s][i] ^= Bernoulli(prob); kind 0 = edges (qubits), 1 = faces (checks). */
+void tco_sample_noise(const tco_lattice* lat, uint8_t* bits, int32_t kind, double prob,
+                      uint64_t seed, uint32_t cycle, uint64_t shot0, int64_t n_shots);
+/* syn[s][f] = parity of the member edges of f (xor_into: syn ^= instead). */
+void tco_syndrome(const tco_lattice* lat, const uint8_t* err, uint8_t* syn, int64_t n_shots,
+                  int32_t xor_into);
+/* One parallel sweep of the flip rule; corr ^= F, syn ^= H F. */
+void tco_flip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, int64_t n_shots);
+/* One parallel sweep of p-flip with coins drawn from Philox. */
+void tco_pflip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, uint64_t seed,
+                     uint32_t cycle, uint32_t sweep, uint64_t shot0, int64_t n_shots);
+/* One parallel p-flip sweep of a single shot with explicit coins[n_edges]. */
+void tco_pflip_sweep_coins(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
+                           const uint8_t* coins);
+/* Sequential flip: flip the lowest-index bit with more unsatisfied than
+ * satisfied checks until none is left or max_flips is reached. One shot.
+ * Returns the number of flips made. */
+int64_t tco_sequential_flip(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
+                            int64_t max_flips);
+
+/* One flooding BP iteration of one shot (E2-E4 with measurement nodes).
+ * nu_in, nu_out: factor-to-variable messages [n_faces][4] (member order);
+ * nu_in == NULL means the first iteration (variable messages = priors).
+ * llr0: per-edge priors [n_edges] or NULL (then ln((1-p_dec)/p_dec)).
+ * post: posterior LLRs [n_edges] (may be NULL). */
+void tco_bp_step(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
+                 double p_dec, double q_dec, const double* nu_in, double* nu_out,
+                 double* post);
+/* iters >= 1 BP iterations per shot; corr[s][i] = [posterior < 0]. post is
+ * [n_shots][n_edges] or NULL; llr0 is [n_shots][n_edges] or NULL. */
+void tco_bp_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
+                   const double* llr0, double p_dec, double q_dec, int32_t iters,
+                   uint8_t* corr, double* post);
+
+/* Majority-vote readout over the L^2 logical Z strings of each axis.
+ * mask[s] bit d = logical X error on qubit d; odd[s][d] = odd strings. */
+void tco_logical_check(const tco_lattice* lat, const uint8_t* err, int64_t n_shots,
+                       uint8_t* mask, int32_t* odd);
+
+/* Whole experiment for shots shot0 .. shot0+n_shots-1. err: [n_shots][n_edges]
+ * residual error, in/out (zero for a fresh start). trace (NULL ok):
+ * [cycles][n_shots][n_edges] residual after each cycle. */
+void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot0,
+                    int64_t n_shots, uint8_t* err, uint8_t* mask, int32_t* odd,
+                    uint8_t* trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

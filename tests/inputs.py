@@ -1,0 +1,85 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU parity tests.
+
+This module holds no arithmetic of the decoding method: it draws random bit
+patterns and message arrays with numpy's seeded generators, converts between
+the oracle's unpacked [shot][site] uint8 layout and the GPU's bit-sliced
+[site][word] uint64 planes (bit i of word w is shot 64*w + i), and names
+lattice sites by their coordinates.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+# ----------------------------------------------------------------- naming
+def site(L, x, y, z):
+    return (x % L) + L * ((y % L) + L * (z % L))
+
+
+def edge(L, x, y, z, a):
+    """Index of the edge from (x,y,z) to (x,y,z)+unit(a)."""
+    return a * L ** 3 + site(L, x, y, z)
+
+
+def face(L, x, y, z, n):
+    """Index of the unit square at corner (x,y,z) with normal axis n."""
+    return n * L ** 3 + site(L, x, y, z)
+
+
+# ------------------------------------------------------------ random data
+def random_bits(seed: int, n_shots: int, n_sites: int, density: float) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return (rng.random((n_shots, n_sites)) < density).astype(np.uint8)
+
+
+def random_messages(seed: int, n_shots: int, n_faces: int, scale: float = 3.0) -> np.ndarray:
+    """Factor-to-variable message arrays [shot][face][4] in FP64."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, size=(n_shots, n_faces, 4))
+
+
+def random_llr(seed: int, n_shots: int, n_edges: int, lo: float = -2.0, hi: float = 6.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(n_shots, n_edges))
+
+
+# ------------------------------------------------------------ bit layout
+def n_words(n_shots: int) -> int:
+    return (n_shots + 63) // 64
+
+
+def pack(bits: np.ndarray) -> np.ndarray:
+    """[S][sites] uint8 -> [sites][W] uint64 (padding shots are zero)."""
+    S, n = bits.shape
+    W = n_words(S)
+    padded = np.zeros((W * 64, n), np.uint8)
+    padded[:S] = bits
+    # shot 64w+i -> bit i of word w
+    b = padded.reshape(W, 64, n).transpose(2, 0, 1).astype(np.uint64)  # [n][W][64]
+    shifts = np.arange(64, dtype=np.uint64)
+    return np.bitwise_or.reduce(b << shifts, axis=2)
+
+
+def unpack(words: np.ndarray, n_shots: int) -> np.ndarray:
+    """[sites][W] uint64 -> [S][sites] uint8."""
+    n, W = words.shape
+    shifts = np.arange(64, dtype=np.uint64)
+    b = ((words[:, :, None] >> shifts) & np.uint64(1)).astype(np.uint8)  # [n][W][64]
+    return b.reshape(n, W * 64).T[:n_shots].copy()
+
+
+def nu_to_gpu(nu: np.ndarray, L: int, s_pad: int) -> np.ndarray:
+    """Oracle messages [S][face][4] -> GPU layout [(normal*4+k)][site][s_pad]."""
+    S = nu.shape[0]
+    N = L ** 3
+    out = np.zeros((12, N, s_pad), np.float32)
+    r = nu.reshape(S, 3, N, 4)  # face = normal*N + site
+    out[:, :, :S] = r.transpose(1, 3, 2, 0).reshape(12, N, S)
+    return out
+
+
+def nu_from_gpu(g: np.ndarray, L: int, n_shots: int) -> np.ndarray:
+    """GPU layout [12][site][s_pad] -> oracle [S][face][4] (FP64)."""
+    N = L ** 3
+    r = np.asarray(g, np.float64).reshape(3, 4, N, -1)[:, :, :, :n_shots]
+    return r.transpose(3, 0, 2, 1).reshape(n_shots, 3 * N, 4).copy()

@@ -1,0 +1,226 @@
+"""Pins of the oracle's belief propagation (Section 4.1, E1-E4 with
+measurement-error variables) against closed forms and symmetries.
+
+Closed forms used (derived from E1-E4, not retyped from the oracle):
+  * tanh(l0/2) = 1 - 2p for l0 = ln((1-p)/p), and the measurement variable of
+    degree 1 contributes tanh(ln((1-q)/q)/2) = 1 - 2q to every check product;
+  * first iteration: every incoming message equals l0, so each check sends
+    (-1)^s nu1 with nu1 = 2 atanh((1-2q)(1-2p)^3) and the posterior of bit i
+    is l0 + (4 - 2 u_i) nu1, u_i = number of its unsatisfied checks;
+  * zero syndrome: by translation symmetry every message is one scalar,
+    nu_t = 2 atanh((1-2q) tanh((l0 + 3 nu_{t-1})/2)^3), nu_0 = 0, and every
+    posterior is l0 + 4 nu_T (the "3" is the exclusion of the receiving
+    check in E3, the "4" the full sum of E4).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import geom
+from inputs import edge, face, random_bits, random_llr, random_messages, site
+from oracle.oracle import Oracle
+
+
+def nu1(p, q):
+    return 2 * math.atanh((1 - 2 * q) * (1 - 2 * p) ** 3)
+
+
+@pytest.mark.parametrize("p,q", [(0.05, 0.05), (0.02, 0.04), (0.1, 0.01)])
+def test_first_iteration_closed_form(p, q):
+    o = Oracle(4)
+    err = random_bits(3, 3, o.n_edges, 0.1)
+    syn = o.syndrome(err)
+    syn ^= random_bits(4, 3, o.n_faces, 0.05)
+    _, ef, _ = o.incidence()
+    l0 = math.log((1 - p) / p)
+    for s in range(3):
+        nu, post = o.bp_step(syn[s], p, q)
+        u = syn[s][ef].sum(axis=1).astype(np.int64)
+        np.testing.assert_allclose(post, l0 + (4 - 2 * u) * nu1(p, q), rtol=0, atol=1e-12)
+        sign = np.where(syn[s] == 1, -1.0, 1.0)
+        np.testing.assert_allclose(nu, np.repeat(sign[:, None] * nu1(p, q), 4, axis=1), rtol=0, atol=1e-12)
+
+
+def test_measurement_factor_identity():
+    for q in (0.001, 0.02, 0.05, 0.3):
+        assert abs(math.tanh(0.5 * math.log((1 - q) / q)) - (1 - 2 * q)) < 1e-15
+
+
+def scalar_recursion(p, q, T):
+    l0 = math.log((1 - p) / p)
+    nu = 0.0
+    out = []
+    for _ in range(T):
+        nu = 2 * math.atanh((1 - 2 * q) * math.tanh((l0 + 3 * nu) / 2) ** 3)
+        out.append(nu)
+    return l0, out
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_zero_syndrome_scalar_recursion(L):
+    p = q = 0.05
+    o = Oracle(L)
+    syn = np.zeros(o.n_faces, np.uint8)
+    l0, ref = scalar_recursion(p, q, 20)
+    nu = None
+    for t in range(20):
+        nu, post = o.bp_step(syn, p, q, nu_in=nu)
+        np.testing.assert_allclose(nu, ref[t], rtol=1e-13)
+        np.testing.assert_allclose(post, l0 + 4 * ref[t], rtol=1e-13)
+    # decode helper agrees with the chained steps
+    _, post20 = o.bp_decode(syn[None], p, q, 20)
+    np.testing.assert_allclose(post20[0], l0 + 4 * ref[-1], rtol=1e-13)
+    # values at p = q = 0.05
+    assert abs(ref[0] - 1.571869802157) < 1e-11
+    assert abs(ref[1] - 2.918004664640) < 1e-11
+    assert abs(ref[19] - 2.944002333351) < 1e-11
+    assert abs(l0 + 4 * ref[19] - 14.720448312570) < 1e-10
+
+
+@pytest.mark.parametrize("pq", [0.02, 0.04, 0.05, 0.055, 0.06])
+def test_one_iteration_equals_flip_rule_below_crossover(pq):
+    """With l0 < 2 nu1, BP(T=1) flips exactly the bits with >= 3 unsatisfied
+    checks, i.e. the flip rule of Section 3.1."""
+    l0 = math.log((1 - pq) / pq)
+    assert l0 < 2 * nu1(pq, pq)
+    o = Oracle(5)
+    err = random_bits(11, 4, o.n_edges, 0.08)
+    syn = o.syndrome(err) ^ random_bits(12, 4, o.n_faces, 0.05)
+    corr, _ = o.bp_decode(syn, pq, pq, 1)
+    _, ef, _ = o.incidence()
+    for s in range(4):
+        u = syn[s][ef].sum(axis=1).astype(np.int64)
+        assert np.array_equal(corr[s], (u >= 3).astype(np.uint8))
+
+
+def test_one_iteration_differs_from_flip_above_crossover():
+    pq = 0.065
+    assert math.log((1 - pq) / pq) > 2 * nu1(pq, pq)
+    o = Oracle(4)
+    e = geom.bits_of(o.n_edges, [edge(4, 1, 1, 1, 0), edge(4, 1, 1, 1, 1)])  # share one face
+    syn = o.syndrome(e[None])
+    _, ef, _ = o.incidence()
+    u = syn[0][ef].sum(axis=1).astype(np.int64)
+    assert (u == 3).any()
+    corr, post = o.bp_decode(syn, pq, pq, 1)
+    assert (post[0][u == 3] > 0).all()  # u = 3 bits are no longer flipped
+
+
+def translate(L, arr, dx, dy, dz, per_site_axes=3):
+    """Move per-(axis, site) data by a lattice translation."""
+    N = L ** 3
+    out = np.empty_like(arr)
+    for a in range(per_site_axes):
+        for z, y, x in itertools.product(range(L), repeat=3):
+            out[..., a * N + site(L, x + dx, y + dy, z + dz)] = arr[..., a * N + site(L, x, y, z)]
+    return out
+
+
+def rotate(L, arr_edge_or_face):
+    """Cyclic axis permutation (x,y,z) -> (y,z,x): the point (x,y,z) goes to
+    (z,x,y) and axis a goes to a+1. Faces keep their corner and member set, so
+    the same map applies to face normals."""
+    N = L ** 3
+    out = np.empty_like(arr_edge_or_face)
+    for a in range(3):
+        for z, y, x in itertools.product(range(L), repeat=3):
+            out[..., ((a + 1) % 3) * N + site(L, z, x, y)] = \
+                arr_edge_or_face[..., a * N + site(L, x, y, z)]
+    return out
+
+
+def test_bp_commutes_with_translations_and_axis_rotation():
+    L = 4
+    o = Oracle(L)
+    err = random_bits(21, 1, o.n_edges, 0.1)
+    syn = (o.syndrome(err) ^ random_bits(22, 1, o.n_faces, 0.04))[0]
+    _, post = o.bp_decode(syn[None], 0.05, 0.05, 7)
+    syn_t = translate(L, syn, 1, 2, 3)
+    _, post_t = o.bp_decode(syn_t[None], 0.05, 0.05, 7)
+    np.testing.assert_allclose(post_t[0], translate(L, post[0], 1, 2, 3), rtol=1e-12, atol=1e-12)
+    syn_r = rotate(L, syn)
+    _, post_r = o.bp_decode(syn_r[None], 0.05, 0.05, 7)
+    np.testing.assert_allclose(post_r[0], rotate(L, post[0]), rtol=1e-12, atol=1e-12)
+
+
+def test_step_from_messages_uses_other_checks_only():
+    """E3 excludes the receiving check: a message change on check g reaches the
+    outgoing messages of g itself only through its other members."""
+    L = 3
+    o = Oracle(L)
+    syn = random_bits(5, 1, o.n_faces, 0.3)[0]
+    nu = random_messages(6, 1, o.n_faces)[0]
+    fe, ef, es = o.incidence()
+    out0, _ = o.bp_step(syn, 0.05, 0.05, nu_in=nu)
+    g = 17
+    nu2 = nu.copy()
+    nu2[g, :] += 5.0
+    out1, _ = o.bp_step(syn, 0.05, 0.05, nu_in=nu2)
+    np.testing.assert_array_equal(out0[g], out1[g])
+    # but checks sharing a bit with g do change
+    neigh = {f for i in fe[g] for f in ef[i]} - {g}
+    for f in neigh:
+        assert not np.allclose(out0[f], out1[f])
+
+
+def test_per_edge_priors_match_scalar_prior():
+    o = Oracle(3)
+    syn = random_bits(8, 2, o.n_faces, 0.2)
+    p = 0.07
+    llr0 = np.full((2, o.n_edges), math.log((1 - p) / p))
+    c1, p1 = o.bp_decode(syn, p, 0.05, 9, llr0=llr0)
+    c2, p2 = o.bp_decode(syn, p, 0.05, 9)
+    np.testing.assert_allclose(p1, p2, rtol=1e-14)
+    llr = random_llr(9, 2, o.n_edges)
+    _, p3 = o.bp_decode(syn, p, 0.05, 1, llr0=llr)
+    assert not np.allclose(p3, p2)
+
+
+def test_half_cube_posteriors_are_symmetric():
+    """The corner half-star and its complement have the same syndrome, so BP
+    cannot prefer either: all six star edges get one posterior and the
+    correction takes all of them or none (Section 4.1)."""
+    L = 6
+    o = Oracle(L)
+    st = geom.star(L, 2, 2, 2)
+    e = geom.bits_of(o.n_edges, [st[0], st[2], st[4]])
+    syn = o.syndrome(e[None])
+    for T in (2, 3, 10, 20, 30):
+        corr, post = o.bp_decode(syn, 0.05, 0.05, T)
+        vals = post[0][st]
+        assert np.ptp(vals) < 1e-9
+        c = set(np.flatnonzero(corr[0]))
+        assert c in (set(), set(st))
+        # residual is equivalent to the original error (differs by a stabiliser)
+        assert o.syndrome((e ^ corr[0])[None]).tolist() == syn.tolist()
+
+
+def test_bp_corrects_planar_two_by_two():
+    # Section 4.1: BP does not struggle with planar errors
+    L = 6
+    o = Oracle(L)
+    idx = [edge(L, 2 + i, 2 + j, 2, 2) for i in (0, 1) for j in (0, 1)]
+    e = geom.bits_of(o.n_edges, idx)
+    corr, _ = o.bp_decode(o.syndrome(e[None]), 0.05, 0.05, 20)
+    assert np.array_equal(corr[0], e)
+
+
+@pytest.mark.slow
+def test_L3_bp_returns_weight_one_and_two_errors():
+    o = Oracle(3)
+    n = o.n_edges
+    errs = [geom.bits_of(n, [i]) for i in range(n)]
+    errs += [geom.bits_of(n, [i, j]) for i, j in itertools.combinations(range(n), 2)]
+    err = np.array(errs)
+    corr, _ = o.bp_decode(o.syndrome(err), 0.05, 0.05, 20)
+    assert np.array_equal(corr, err)
+
+
+def test_L3_bp_returns_weight_one_errors():
+    o = Oracle(3)
+    n = o.n_edges
+    err = np.eye(n, dtype=np.uint8)
+    corr, _ = o.bp_decode(o.syndrome(err), 0.05, 0.05, 20)
+    assert np.array_equal(corr, err)

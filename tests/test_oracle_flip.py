@@ -1,0 +1,300 @@
+"""Pins of the oracle's flip and p-flip (Section 3) against the behaviour the
+paper states for its catalogue of low-weight errors (Figs. 2-4 and the
+surrounding text), against an independent set-based brute force, and against
+exhaustive enumeration on L = 3."""
+import itertools
+
+import numpy as np
+import pytest
+
+import geom
+from inputs import edge, random_bits
+from oracle.oracle import Oracle
+
+L = 6
+V = (2, 2, 2)
+
+
+def E(axis, sign=+1, at=V):
+    """+a = edge from `at` along a; -a = edge from at-unit(a) along a."""
+    p = list(at)
+    if sign < 0:
+        p[axis] -= 1
+    return edge(L, p[0], p[1], p[2], axis)
+
+
+X, Y, Z = 0, 1, 2
+STAR = [E(a, s) for a in range(3) for s in (+1, -1)]
+_MEMBERS = None
+
+
+def members():
+    global _MEMBERS
+    if _MEMBERS is None:
+        _MEMBERS = geom.face_members_by_points(L)
+    return _MEMBERS
+
+
+def bits(idx, n=3 * L ** 3):
+    return geom.bits_of(n, idx)
+
+
+def unsat_counts(err_bits):
+    """u_i from coordinates alone (independent of the oracle's tables)."""
+    unsat = [f for f, m in members().items() if sum(err_bits[i] for i in m) % 2]
+    u = np.zeros(err_bits.size, int)
+    for f in unsat:
+        for i in members()[f]:
+            u[i] += 1
+    return u, len(unsat)
+
+
+def oracle_sweep(o, err_bits, n=1):
+    syn = o.syndrome(err_bits[None])[0]
+    corr = np.zeros_like(err_bits)
+    for _ in range(n):
+        o.flip_sweep(syn[None], corr[None])
+    return err_bits ^ corr, syn
+
+
+def cleared(o, err_bits):
+    mask, odd = o.logical_check(err_bits[None])
+    return o.syndrome(err_bits[None]).sum() == 0 and odd.sum() == 0
+
+
+# ------------------------------------------------------------ Figs. 2, 4
+def test_corner_half_star_is_stuck_and_ties_are_the_star():
+    # Fig. 2a: three of the six qubits of an X stabiliser, each in two
+    # satisfied and two unsatisfied checks.
+    e = bits([E(X), E(Y), E(Z)])
+    u, w = unsat_counts(e)
+    assert w == 6
+    assert (u < 3).all()
+    assert set(np.flatnonzero(u == 2)) == set(STAR)
+    o = Oracle(L)
+    after, _ = oracle_sweep(o, e)
+    assert np.array_equal(after, e)
+
+
+def plane_block(cells, z=0):
+    return [edge(L, V[0] + i, V[1] + j, V[2] + z, Z) for i, j in cells]
+
+
+def test_planar_two_by_two_is_stuck_and_ties_are_its_support():
+    # Fig. 2b: four coplanar qubits, each in two satisfied and two unsatisfied
+    e_idx = plane_block([(0, 0), (1, 0), (0, 1), (1, 1)])
+    e = bits(e_idx)
+    u, w = unsat_counts(e)
+    assert w == 8
+    assert (u < 3).all()
+    assert set(np.flatnonzero(u == 2)) == set(e_idx)
+    after, _ = oracle_sweep(Oracle(L), e)
+    assert np.array_equal(after, e)
+
+
+def test_parallel_flip_swaps_the_two_u_shapes():
+    # Fig. 4: four qubits (two with errors, two without) see three unsatisfied
+    # checks; flipping them together rotates the error and keeps its weight.
+    o = Oracle(L)
+    e = bits([E(Z, -1), E(Z, +1), E(Y, +1)])
+    u, w = unsat_counts(e)
+    assert w == 8
+    assert set(np.flatnonzero(u >= 3)) == {E(X, -1), E(X, +1), E(Z, -1), E(Z, +1)}
+    once, _ = oracle_sweep(o, e)
+    assert set(np.flatnonzero(once)) == {E(X, -1), E(X, +1), E(Y, +1)}
+    assert unsat_counts(once)[1] == 8
+    twice, _ = oracle_sweep(o, e, n=2)
+    assert np.array_equal(twice, e)
+
+
+# ------------------------------------------------------------------ Fig. 3
+def test_fourth_face_makes_corner_correctable():
+    # Fig. 3a: an extra error on a fourth face of the cube
+    o = Oracle(L)
+    e = bits([E(X), E(Y), E(Z), E(X, -1)])
+    u, _ = unsat_counts(e)
+    assert set(np.flatnonzero(u >= 3)) == {E(Y, -1), E(Z, -1)}
+    after, _ = oracle_sweep(o, e)
+    assert set(np.flatnonzero(after)) == set(STAR)
+    assert cleared(o, after)
+
+
+def test_neighbouring_error_is_removed_and_corner_restored():
+    # Fig. 3b: flip corrects the additional error and restores the original
+    o = Oracle(L)
+    w = (V[0] - 1, V[1], V[2])
+    e = bits([E(X), E(Y), E(Z), E(Z, +1, at=w)])
+    after, _ = oracle_sweep(o, e)
+    assert set(np.flatnonzero(after)) == {E(X), E(Y), E(Z)}
+
+
+def test_two_cube_half_is_stuck():
+    # Fig. 3c: two more errors grow it into a five-qubit uncorrectable error
+    w = (V[0] - 1, V[1], V[2])
+    e = bits([E(X), E(Y), E(Z), E(Y, +1, at=w), E(Z, +1, at=w)])
+    u, wt = unsat_counts(e)
+    assert wt == 8
+    assert (u < 3).all()
+
+
+def test_planar_variants():
+    o = Oracle(L)
+    # Fig. 3d: three of the 2x2 are correctable (two sweeps)
+    e = bits(plane_block([(0, 0), (1, 0), (0, 1)]))
+    one, _ = oracle_sweep(o, e)
+    assert set(np.flatnonzero(one)) == set(plane_block([(0, 0)]))
+    two, _ = oracle_sweep(o, e, n=2)
+    assert two.sum() == 0
+    # Fig. 3e: one extra coplanar error is removed, restoring the 2x2
+    sq = plane_block([(0, 0), (1, 0), (0, 1), (1, 1)])
+    e = bits(sq + plane_block([(2, 0)]))
+    one, _ = oracle_sweep(o, e)
+    assert set(np.flatnonzero(one)) == set(sq)
+    # Fig. 3f: a 3x2 block is stuck
+    e = bits(plane_block([(i, j) for i in range(3) for j in range(2)]))
+    u, _ = unsat_counts(e)
+    assert (u < 3).all()
+
+
+def test_opposite_pair_flip_corrects_in_one_sweep():
+    # Section 3.2: errors on opposite faces of a cube; flip corrects them in
+    # one application, p-flip might flip the four error-free faces instead.
+    o = Oracle(L)
+    e = bits([E(X, +1), E(X, -1)])
+    u, _ = unsat_counts(e)
+    assert u[E(X, +1)] == 4 and u[E(X, -1)] == 4
+    assert set(np.flatnonzero(u == 2)) == {E(Y, 1), E(Y, -1), E(Z, 1), E(Z, -1)}
+    after, _ = oracle_sweep(o, e)
+    assert after.sum() == 0
+
+
+# ------------------------------------------- p-flip: exhaustive over coins
+def py_sweep(err, coins):
+    """Independent parallel sweep on coordinates: u >= 3 flips, u == 2 flips
+    when its coin is set."""
+    u, _ = unsat_counts(err)
+    F = (u >= 3) | ((u == 2) & (coins != 0))
+    return err ^ F.astype(np.uint8)
+
+
+def py_cleared(err):
+    if unsat_counts(err)[1]:
+        return False
+    return all(err[geom.string(L, d, 0, 0)].sum() % 2 == 0 for d in range(3))
+
+
+CASES = {
+    # name: (support, [(number of flip sweeps after P, cleared outcomes)], n ties)
+    "corner": ([E(X), E(Y), E(Z)], [(0, 2), (1, 44), (2, 44)], 6),
+    "ushape": ([E(Z, -1), E(Z, +1), E(Y, +1)], [(0, 0), (1, 2)], 2),
+    "planar": (plane_block([(0, 0), (1, 0), (0, 1), (1, 1)]), [(0, 1), (1, 11), (2, 15)], 4),
+    "opposite": ([E(X, +1), E(X, -1)], [(0, 1), (1, 12)], 4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_pflip_clearing_probabilities_by_enumeration(name):
+    support, expect, n_ties = CASES[name]
+    o = Oracle(L)
+    e0 = bits(support)
+    u, _ = unsat_counts(e0)
+    ties = np.flatnonzero(u == 2)
+    assert len(ties) == n_ties
+    for n_flip, want in expect:
+        got_oracle = got_py = 0
+        for pattern in itertools.product((0, 1), repeat=len(ties)):
+            coins = np.zeros(e0.size, np.uint8)
+            coins[ties] = pattern
+            # oracle
+            syn = o.syndrome(e0[None])[0]
+            corr = np.zeros_like(e0)
+            o.pflip_sweep_coins(syn, corr, coins)
+            for _ in range(n_flip):
+                o.flip_sweep(syn[None], corr[None])
+            got_oracle += bool(cleared(o, e0 ^ corr))
+            # independent brute force
+            r = py_sweep(e0, coins)
+            for _ in range(n_flip):
+                r = py_sweep(r, np.zeros_like(coins))
+            got_py += bool(py_cleared(r))
+        assert got_oracle == got_py == want, (n_flip, got_oracle, got_py, want)
+
+
+def test_pflip_clears_corner_that_flip_cannot():
+    """p-flip corrects the half-stabiliser with finite probability; flip never."""
+    o = Oracle(L)
+    e0 = bits([E(X), E(Y), E(Z)])
+    n = 256
+    err = np.tile(e0, (n, 1))
+    syn = o.syndrome(err)
+    corr = np.zeros_like(err)
+    o.pflip_sweep(syn, corr, seed=1, cycle=0, sweep=0)
+    o.flip_sweep(syn, corr)
+    ok = sum(cleared(o, err[s] ^ corr[s]) for s in range(n))
+    assert 0.5 < ok / n < 0.9  # 44/64 ~ 0.69 in expectation
+    syn = o.syndrome(err)
+    corr = np.zeros_like(err)
+    for _ in range(5):
+        o.flip_sweep(syn, corr)
+    assert corr.sum() == 0
+
+
+# ---------------------------------------------------------- sequential flip
+def test_sequential_flip_strictly_lowers_syndrome_weight():
+    o = Oracle(5)
+    for seed in range(5):
+        syn = random_bits(100 + seed, 1, o.n_faces, 0.15)[0]
+        corr = np.zeros(o.n_edges, np.uint8)
+        w = syn.sum()
+        while o.sequential_flip(syn, corr, max_flips=1) == 1:
+            assert syn.sum() <= w - 2
+            w = syn.sum()
+        # stopped: no bit has more unsatisfied than satisfied checks
+        fe, ef, _ = o.incidence()
+        assert (syn[ef].sum(axis=1) <= 2).all()
+
+
+def test_sequential_flip_corrects_u_shape():
+    # Section 3.2: the Fig. 4 error is correctable for the sequential version
+    o = Oracle(L)
+    e = bits([E(Z, -1), E(Z, +1), E(Y, +1)])
+    syn = o.syndrome(e[None])[0]
+    corr = np.zeros_like(e)
+    o.sequential_flip(syn, corr)
+    assert syn.sum() == 0 and cleared(o, e ^ corr)
+
+
+# --------------------------------------------------------------- L = 3 brute
+def test_L3_low_weight_errors_are_corrected_by_one_parallel_sweep():
+    o = Oracle(3)
+    n = o.n_edges
+    errs = [bits([i], n) for i in range(n)]
+    errs += [bits([i, j], n) for i, j in itertools.combinations(range(n), 2)]
+    err = np.array(errs)
+    syn = o.syndrome(err)
+    # minimum weight: no other error of weight <= 2 has the same syndrome
+    keys = {}
+    for s in range(err.shape[0]):
+        k = syn[s].tobytes()
+        assert k not in keys
+        keys[k] = s
+    corr = np.zeros_like(err)
+    o.flip_sweep(syn, corr)
+    assert np.array_equal(corr, err)
+    assert syn.sum() == 0
+
+
+def test_L3_corners_and_u_shapes_defeat_iterated_parallel_flip():
+    o = Oracle(3)
+    n = o.n_edges
+    for x, y, z in itertools.product(range(3), repeat=3):
+        st = geom.star(3, x, y, z)  # +x,-x,+y,-y,+z,-z
+        corner = [st[0], st[2], st[4]]
+        ushape = [st[5], st[4], st[2]]
+        for sup in (corner, ushape):
+            e = bits(sup, n)
+            syn = o.syndrome(e[None])
+            corr = np.zeros((1, n), np.uint8)
+            for _ in range(8):
+                o.flip_sweep(syn, corr)
+            assert syn.sum() > 0
