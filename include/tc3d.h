@@ -1,0 +1,215 @@
+/*
+ * tc3d.h -- C ABI of a shot-parallel Monte Carlo decoder for X errors on the
+ * L x L x L periodic 3D toric code under phenomenological noise, running on
+ * AMD Instinct MI355X (gfx950). The method is the p-BP decoder of
+ * T. R. Scruby and K. Nemoto, "Local Probabilistic Decoding of a Quantum
+ * Code", Quantum (2023): belief propagation followed by a schedule of flip and
+ * p-flip sweeps, applied every code cycle, with a majority-vote readout.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Geometry (Section 2 of the paper): qubits on the 3L^3 edges, Z checks on
+ * the 3L^3 faces of the periodic cubic lattice.
+ *   site  v = x + L*y + L*L*z, coordinates taken mod L
+ *   edge  e(v,a) = a*L^3 + v        the edge from v to v + unit(a)
+ *   face  f(v,n) = n*L^3 + v        the unit square at corner v with normal n;
+ *         with a < b its two spanning axes, its member edges are, in order,
+ *         k=0: e(v,a)   k=1: e(v+unit(b),a)   k=2: e(v,b)   k=3: e(v+unit(a),b)
+ * Shots are bit-sliced: a bit plane is a row-major uint64 array [rows][W]
+ * with rows = 3L^3 (edges or faces) and W = ceil(n_shots/64) words per row;
+ * bit i of word w belongs to shot 64*w + i. Bits of padding shots (64*W >
+ * n_shots) are computed like any other shot and ignored by the readout.
+ * Per-shot float arrays are [rows][S_pad] with S_pad = 64*W.
+ *
+ * Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
+ * 64-bit seed (key word 0 = low half, word 1 = high half).
+ *   qubit noise of edge i, cycle t, shot s: word (s mod 4) of the block at
+ *     counter (i, t, s div 4, 0); it fires when that word < floor(p * 2^32);
+ *   check-outcome noise of face f: the same with counter word 3 = 1;
+ *   p-flip coin of edge i, cycle t, sweep k, shot s: bit (s mod 64) of
+ *     (r0 | r1 << 32) where r is the block at counter (i, t, s div 64, 2 + k).
+ * Shot indices must stay below 2^34.
+ *
+ * Memory: every pointer is caller-owned device memory (for example a torch
+ * tensor's data pointer). The library never allocates or frees device memory;
+ * entry points that need scratch space take a workspace pointer and its size,
+ * which must be at least what the matching *_workspace_bytes call returns.
+ * Device pointers must be 8-byte aligned (EALIGN otherwise), workspaces
+ * 256-byte aligned.
+ *
+ * Execution: every call is asynchronous on `stream` (a hipStream_t; NULL is
+ * the default stream) except tc3d_run_cycles_timed, which blocks. Calls
+ * return TC3D_OK, or a negative TC3D_E* code for invalid arguments or a failed
+ * launch; faults during execution surface at the caller's next
+ * synchronisation. No exception crosses the ABI. The library keeps no mutable
+ * global state, so concurrent calls on different buffers are safe.
+ */
+#ifndef TC3D_H
+#define TC3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TC3D_OK = 0,
+    TC3D_EINVAL = -1,     /* bad size, probability, flag or lattice          */
+    TC3D_EALIGN = -2,     /* misaligned pointer                              */
+    TC3D_EHIP = -3,       /* a HIP launch or runtime call failed             */
+    TC3D_EWORKSPACE = -4  /* workspace missing or smaller than required      */
+};
+
+/* Lattice sizes. A plain value; build it with tc3d_make_lattice. */
+typedef struct {
+    int32_t L;
+    int32_t reserved;   /* zero */
+    int64_t n_sites;    /* L^3   */
+    int64_t n_edges;    /* 3 L^3 */
+    int64_t n_faces;    /* 3 L^3 */
+} tc3d_lattice;
+
+/* Section 2: the [[3L^3, 3, L]] code on the L^3 torus. 3 <= L <= 512. */
+int tc3d_make_lattice(int32_t L, tc3d_lattice* out);
+
+/* Phenomenological noise (Sections 3.1 and 4.1): XOR an independent
+ * Bernoulli(prob) bit into every entry of a plane. kind 0: edge plane (qubit
+ * X errors, counter word 3 = 0); kind 1: face plane (check-outcome errors,
+ * counter word 3 = 1). The plane covers shots shot0 .. shot0 + 64*W - 1 with
+ * W = ceil(n_shots/64); shot0 must be a multiple of 64. 0 <= prob <= 1. */
+int tc3d_sample_noise(const tc3d_lattice* lat, uint64_t* plane, int32_t kind, double prob,
+                      uint64_t seed, uint32_t cycle, uint64_t shot0, int64_t n_shots,
+                      void* stream);
+
+/* Section 2: the Z-check syndrome. syn[f] = XOR of err over the four member
+ * edges of face f, for every word. xor_into != 0 XORs the result into syn
+ * instead of overwriting it (used to update a working syndrome with the
+ * parity of a correction). err and syn are [3L^3][n_words]; they must not
+ * overlap. */
+int tc3d_syndrome(const tc3d_lattice* lat, const uint64_t* err, uint64_t* syn,
+                  int64_t n_words, int32_t xor_into, void* stream);
+
+/* Scratch needed by one flip or p-flip sweep: one edge plane. */
+size_t tc3d_sweep_workspace_bytes(const tc3d_lattice* lat, int64_t n_words);
+
+/* flip (Section 3.1) in its parallel form (Section 3.2): every qubit with
+ * more unsatisfied than satisfied checks (3 or 4 of its 4) is flipped, all
+ * decided against the same syndrome. corr ^= F and syn ^= H F, in place. */
+int tc3d_flip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* p-flip (Section 3.2): as flip, and a qubit with exactly 2 of 4 checks
+ * unsatisfied flips when its coin (see Randomness; cycle and sweep index
+ * select the counter) is 1, i.e. with probability 1/2. shot0: shot of bit 0
+ * of word 0, a multiple of 64. */
+int tc3d_pflip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
+                     uint64_t seed, uint32_t cycle, uint32_t sweep, uint64_t shot0, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Scratch of tc3d_bp_decode: two message buffers of 12 L^3 S_pad floats. */
+size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
+
+/* Local belief propagation (Section 4.1, equations for the LLR, the factor
+ * and variable messages and the posterior), flooding schedule, with one
+ * measurement-error variable per check whose constant message contributes the
+ * factor meas_factor = tanh(ln((1-q)/q)/2) = 1 - 2q to every check product.
+ * Runs exactly `iters` >= 1 iterations in FP32, then corr_out (an edge plane,
+ * overwritten) gets bit 1 where the posterior LLR is < 0.
+ *   syn       face plane [3L^3][W], W = ceil(n_shots/64)
+ *   llr0      per-edge priors [3L^3][S_pad] in nats, or NULL to use
+ *             llr0_scalar = ln((1-p)/p) on every edge
+ *   post_out  posterior LLRs [3L^3][S_pad], or NULL
+ * 0 <= meas_factor < 1; llr0_scalar finite. */
+int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                   const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
+                   uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes, void* stream);
+
+/* One flooding BP iteration, for inspection and parity checks. Message
+ * arrays are FP32 [12][L^3][S_pad]: row (4n + k) * L^3 + v holds the message
+ * from face f(v,n) to its member edge k. nu_in == NULL means the first
+ * iteration (every variable-to-check message equals its prior). post_out
+ * (NULL ok) receives the posterior computed from nu_out, [3L^3][S_pad]. */
+int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                 const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
+                 float* nu_out, float* post_out, void* stream);
+
+/* Majority-vote readout (Section 3.1 and Fig. 1 caption): for each axis d,
+ * count the L^2 disjoint logical Z strings along d (the L d-edges through
+ * fixed other coordinates) whose error parity is odd; the shot has a logical
+ * X error on qubit d when that count is at least L^2/2 (a tie counts as a
+ * failure). mask_out[s] bit d records it; odd_out (NULL ok) is
+ * [n_shots][3] int32 counts. err is an edge plane [3L^3][ceil(n_shots/64)]. */
+int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_shots,
+                       uint8_t* mask_out, int32_t* odd_out, void* stream);
+
+/* One Monte Carlo experiment. */
+typedef struct {
+    double p;                  /* qubit X-error probability per cycle           */
+    double q;                  /* check-outcome error probability per cycle      */
+    double p_dec;              /* BP prior: llr0 = ln((1-p_dec)/p_dec)           */
+    double q_dec;              /* BP measurement prior: factor 1 - 2 q_dec      */
+    int32_t noisy_cycles;      /* cycles with check-outcome noise                */
+    int32_t perfect_final;     /* 1: one more cycle with perfect measurements   */
+    int32_t final_qubit_noise; /* 1: that cycle still adds qubit noise          */
+    int32_t bp_iters;          /* BP iterations per cycle; 0 disables BP         */
+    int32_t n_sweeps;          /* flip / p-flip sweeps per cycle (0..32)        */
+    uint32_t pflip_mask;       /* bit k set: sweep k is p-flip, else flip       */
+    uint64_t seed;             /* Philox key                                     */
+    uint64_t shot0;            /* first shot index, a multiple of 64            */
+    int64_t n_shots;           /* shots in this call                             */
+    int64_t batch_shots;       /* shots decoded together (multiple of 64);
+                                  0 picks a size that keeps the workspace near
+                                  24 GiB                                         */
+} tc3d_run_params;
+
+size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);
+
+/* The whole decoding experiment of Sections 3-4 for shots shot0 ..
+ * shot0 + n_shots - 1. For each cycle t = 0 .. cycles-1 (cycles =
+ * noisy_cycles + perfect_final): qubit noise (probability p; 0 in the perfect
+ * cycle unless final_qubit_noise), syndrome measurement with check-outcome
+ * noise (q; 0 in the perfect cycle), BP if bp_iters > 0 whose correction also
+ * updates the working syndrome, then the flip / p-flip sweeps on the working
+ * syndrome, then the accumulated correction is applied and the residual error
+ * carries over. Finally the majority-vote readout of the residual.
+ *   err_state  edge plane [3L^3][ceil(n_shots/64)], in/out (zero to start)
+ *   mask_out   [n_shots] uint8, odd_out [n_shots][3] int32 or NULL
+ * bp_iters > 0 needs 0 < p_dec < 0.5 and 0 < q_dec < 0.5. */
+int tc3d_run_cycles(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err_state,
+                    uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Kernel classes reported by tc3d_run_cycles_timed. */
+enum {
+    TC3D_K_BP_ITER = 0,   /* one BP iteration that reads and writes messages */
+    TC3D_K_BP_FIRST = 1,  /* a BP iteration whose inputs are implied by the syndrome */
+    TC3D_K_BP_POST = 2,   /* posterior + hard decision                      */
+    TC3D_K_NOISE = 3,     /* qubit noise                                     */
+    TC3D_K_SYNDROME = 4,  /* syndrome measurement / working-syndrome update */
+    TC3D_K_SWEEP = 5,     /* flip / p-flip decision pass                    */
+    TC3D_K_APPLY = 6,     /* plane XOR / clear                               */
+    TC3D_K_READOUT = 7,   /* majority vote                                   */
+    TC3D_K_COUNT = 8
+};
+
+typedef struct {
+    double ms[TC3D_K_COUNT];        /* summed HIP-event durations per class */
+    int64_t launches[TC3D_K_COUNT]; /* launches per class                   */
+    double total_ms;                /* first to last event of the call      */
+} tc3d_timing;
+
+/* tc3d_run_cycles with a HIP event recorded on `stream` before and after
+ * every kernel launch; blocks until the work is done and fills *timing. */
+int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
+                          uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
+                          size_t ws_bytes, void* stream, tc3d_timing* timing);
+
+/* Human-readable text of a return code. */
+const char* tc3d_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

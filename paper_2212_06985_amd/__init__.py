@@ -1,0 +1,229 @@
+"""Shot-parallel Monte Carlo decoding of the 3D toric code on AMD MI355X.
+
+A thin ctypes binding of libtc3d.so (include/tc3d.h): every function takes
+torch tensors that live on the GPU, passes their data pointers and the current
+HIP stream to the C ABI, and raises on a non-zero return code. All work runs
+in the library's HIP kernels; there is no CPU fallback. Build the library with
+``python -m paper_2212_06985_amd.build`` (or ``__graft_entry__.build()``).
+
+Layouts (see the header): bit planes are int64 tensors [3 L^3][ceil(S/64)]
+holding uint64 words, bit i of word w = shot 64 w + i; per-shot floats are
+[rows][64 ceil(S/64)].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "Lattice", "RunParams", "Timing", "Tc3dError", "lib", "make_lattice", "sample_noise",
+    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "bp_workspace_bytes",
+    "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
+    "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtc3d.so")
+
+KERNEL_CLASSES = ["bp_iter", "bp_first", "bp_post", "noise", "syndrome", "sweep", "apply",
+                  "readout"]
+
+
+class Tc3dError(RuntimeError):
+    pass
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_sites", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("n_faces", ctypes.c_int64)]
+
+
+class RunParams(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_double), ("q", ctypes.c_double),
+        ("p_dec", ctypes.c_double), ("q_dec", ctypes.c_double),
+        ("noisy_cycles", ctypes.c_int32), ("perfect_final", ctypes.c_int32),
+        ("final_qubit_noise", ctypes.c_int32), ("bp_iters", ctypes.c_int32),
+        ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64), ("shot0", ctypes.c_uint64),
+        ("n_shots", ctypes.c_int64), ("batch_shots", ctypes.c_int64),
+    ]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
+                ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: {"ms": self.ms[i], "launches": int(self.launches[i])}
+                for i, k in enumerate(KERNEL_CLASSES)}
+
+
+_lib = None
+
+
+def lib():
+    """Load libtc3d.so; fail loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2212_06985_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, i64, u64, f32, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                             ctypes.c_int64, ctypes.c_uint64, ctypes.c_float,
+                                             ctypes.c_double, ctypes.c_size_t)
+    lat, prm = ctypes.POINTER(Lattice), ctypes.POINTER(RunParams)
+    sigs = {
+        "tc3d_make_lattice": (ctypes.c_int, [i32, lat]),
+        "tc3d_sample_noise": (ctypes.c_int, [lat, vp, i32, f64, u64, u32, u64, i64, vp]),
+        "tc3d_syndrome": (ctypes.c_int, [lat, vp, vp, i64, i32, vp]),
+        "tc3d_sweep_workspace_bytes": (sz, [lat, i64]),
+        "tc3d_flip_sweep": (ctypes.c_int, [lat, vp, vp, i64, vp, sz, vp]),
+        "tc3d_pflip_sweep": (ctypes.c_int, [lat, vp, vp, i64, u64, u32, u32, u64, vp, sz, vp]),
+        "tc3d_bp_workspace_bytes": (sz, [lat, i64]),
+        "tc3d_bp_decode": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, i32, vp, vp, vp, sz, vp]),
+        "tc3d_bp_step": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, vp, vp, vp, vp]),
+        "tc3d_logical_check": (ctypes.c_int, [lat, vp, i64, vp, vp, vp]),
+        "tc3d_run_workspace_bytes": (sz, [lat, prm]),
+        "tc3d_run_cycles": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp]),
+        "tc3d_run_cycles_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp,
+                                                 ctypes.POINTER(Timing)]),
+        "tc3d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------- marshalling
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise Tc3dError(f"{what}: {lib().tc3d_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def n_words(n_shots: int) -> int:
+    return (int(n_shots) + 63) // 64
+
+
+def make_lattice(L: int) -> Lattice:
+    lat = Lattice()
+    _check(lib().tc3d_make_lattice(int(L), ctypes.byref(lat)), "make_lattice")
+    return lat
+
+
+def alloc_plane(lat: Lattice, n_shots: int, device="cuda"):
+    import torch
+    return torch.zeros((lat.n_edges, n_words(n_shots)), dtype=torch.int64, device=device)
+
+
+def alloc_workspace(nbytes: int, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sample_noise(lat, plane, kind, prob, seed, cycle, shot0, n_shots, stream=None):
+    _check(lib().tc3d_sample_noise(ctypes.byref(lat), _ptr(plane), int(kind), float(prob),
+                                   int(seed), int(cycle), int(shot0), int(n_shots),
+                                   _stream(stream)), "sample_noise")
+
+
+def syndrome(lat, err, syn, nw, xor_into=False, stream=None):
+    _check(lib().tc3d_syndrome(ctypes.byref(lat), _ptr(err), _ptr(syn), int(nw),
+                               1 if xor_into else 0, _stream(stream)), "syndrome")
+
+
+def sweep_workspace_bytes(lat, nw) -> int:
+    return int(lib().tc3d_sweep_workspace_bytes(ctypes.byref(lat), int(nw)))
+
+
+def flip_sweep(lat, syn, corr, nw, ws, stream=None):
+    _check(lib().tc3d_flip_sweep(ctypes.byref(lat), _ptr(syn), _ptr(corr), int(nw), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)), "flip_sweep")
+
+
+def pflip_sweep(lat, syn, corr, nw, seed, cycle, sweep, shot0, ws, stream=None):
+    _check(lib().tc3d_pflip_sweep(ctypes.byref(lat), _ptr(syn), _ptr(corr), int(nw), int(seed),
+                                  int(cycle), int(sweep), int(shot0), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)),
+           "pflip_sweep")
+
+
+def bp_workspace_bytes(lat, n_shots) -> int:
+    return int(lib().tc3d_bp_workspace_bytes(ctypes.byref(lat), int(n_shots)))
+
+
+def bp_decode(lat, syn, n_shots, llr0, llr0_scalar, meas_factor, iters, corr_out, post_out, ws,
+              stream=None):
+    _check(lib().tc3d_bp_decode(ctypes.byref(lat), _ptr(syn), int(n_shots), _ptr(llr0),
+                                float(llr0_scalar), float(meas_factor), int(iters),
+                                _ptr(corr_out), _ptr(post_out), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)), "bp_decode")
+
+
+def bp_step(lat, syn, n_shots, llr0, llr0_scalar, meas_factor, nu_in, nu_out, post_out=None,
+            stream=None):
+    _check(lib().tc3d_bp_step(ctypes.byref(lat), _ptr(syn), int(n_shots), _ptr(llr0),
+                              float(llr0_scalar), float(meas_factor), _ptr(nu_in), _ptr(nu_out),
+                              _ptr(post_out), _stream(stream)), "bp_step")
+
+
+def logical_check(lat, err, n_shots, mask_out, odd_out=None, stream=None):
+    _check(lib().tc3d_logical_check(ctypes.byref(lat), _ptr(err), int(n_shots), _ptr(mask_out),
+                                    _ptr(odd_out), _stream(stream)), "logical_check")
+
+
+def run_workspace_bytes(lat, prm: RunParams) -> int:
+    n = int(lib().tc3d_run_workspace_bytes(ctypes.byref(lat), ctypes.byref(prm)))
+    if n == 0:
+        raise Tc3dError("run_workspace_bytes: invalid lattice or parameters")
+    return n
+
+
+def run_cycles(lat, prm: RunParams, err_state, mask_out, odd_out, ws, stream=None):
+    _check(lib().tc3d_run_cycles(ctypes.byref(lat), ctypes.byref(prm), _ptr(err_state),
+                                 _ptr(mask_out), _ptr(odd_out), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)), "run_cycles")
+
+
+def run_cycles_timed(lat, prm: RunParams, err_state, mask_out, odd_out, ws,
+                     stream=None) -> Timing:
+    t = Timing()
+    _check(lib().tc3d_run_cycles_timed(ctypes.byref(lat), ctypes.byref(prm), _ptr(err_state),
+                                       _ptr(mask_out), _ptr(odd_out), _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream),
+                                       ctypes.byref(t)), "run_cycles_timed")
+    return t
+
+
+def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,
+                    shot0=0, p_dec=None, q_dec=None, perfect_final=1, final_qubit_noise=1,
+                    batch_shots=0) -> RunParams:
+    return RunParams(p=p, q=q, p_dec=p if p_dec is None else p_dec,
+                     q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
+                     perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
+                     bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
+                     shot0=shot0, n_shots=n_shots, batch_shots=batch_shots)
+
+
+__all__.append("make_run_params")

@@ -1,0 +1,436 @@
+// C ABI (include/tc3d.h): argument checks, workspace carving, the BP
+// iteration schedule and the multi-cycle driver. Every step of the decoding
+// path runs in the kernels of tc3d_bits.hip and tc3d_bp.hip.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "tc3d_internal.hpp"
+
+namespace tc3d {
+
+// ------------------------------------------------------------------- timer
+Timer::~Timer() {
+    for (auto& s : slots_) {
+        if (s.start) (void)hipEventDestroy(s.start);
+        if (s.stop) (void)hipEventDestroy(s.stop);
+    }
+    if (first_) (void)hipEventDestroy(first_);
+    if (last_) (void)hipEventDestroy(last_);
+}
+
+int Timer::drain(Slot& s) {
+    if (!s.pending) return TC3D_OK;
+    if (hipEventSynchronize(s.stop) != hipSuccess) return TC3D_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s.start, s.stop) != hipSuccess) return TC3D_EHIP;
+    ms_[s.kclass] += ms;
+    launches_[s.kclass] += 1;
+    s.pending = false;
+    return TC3D_OK;
+}
+
+int Timer::begin(int kclass) {
+    constexpr size_t kSlots = 512;
+    if (!first_) {
+        if (hipEventCreate(&first_) != hipSuccess || hipEventCreate(&last_) != hipSuccess)
+            return TC3D_EHIP;
+        if (hipEventRecord(first_, stream_) != hipSuccess) return TC3D_EHIP;
+    }
+    if (slots_.size() < kSlots) {
+        Slot s;
+        if (hipEventCreate(&s.start) != hipSuccess || hipEventCreate(&s.stop) != hipSuccess)
+            return TC3D_EHIP;
+        slots_.push_back(s);
+    }
+    cur_ = (int)(next_ % slots_.size());
+    next_++;
+    Slot& s = slots_[cur_];
+    int rc = drain(s);  // reuse: wait for the launch recorded kSlots launches ago
+    if (rc) return rc;
+    s.kclass = kclass;
+    if (hipEventRecord(s.start, stream_) != hipSuccess) return TC3D_EHIP;
+    return TC3D_OK;
+}
+
+int Timer::end() {
+    Slot& s = slots_[cur_];
+    if (hipEventRecord(s.stop, stream_) != hipSuccess) return TC3D_EHIP;
+    s.pending = true;
+    return TC3D_OK;
+}
+
+int Timer::finish(tc3d_timing* out) {
+    if (first_ && hipEventRecord(last_, stream_) != hipSuccess) return TC3D_EHIP;
+    for (auto& s : slots_) {
+        int rc = drain(s);
+        if (rc) return rc;
+    }
+    memset(out, 0, sizeof(*out));
+    for (int k = 0; k < TC3D_K_COUNT; ++k) {
+        out->ms[k] = ms_[k];
+        out->launches[k] = launches_[k];
+    }
+    if (first_) {
+        if (hipEventSynchronize(last_) != hipSuccess) return TC3D_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, first_, last_) != hipSuccess) return TC3D_EHIP;
+        out->total_ms = ms;
+    }
+    return TC3D_OK;
+}
+
+int before_launch(const Ctx& c, int kclass) {
+    return c.timer ? c.timer->begin(kclass) : TC3D_OK;
+}
+
+int after_launch(const Ctx& c) {
+    if (hipGetLastError() != hipSuccess) return TC3D_EHIP;
+    return c.timer ? c.timer->end() : TC3D_OK;
+}
+
+namespace {
+
+constexpr int32_t kMaxL = 512;
+constexpr int kMaxSweeps = 32;
+
+bool lattice_ok(const tc3d_lattice* lat) {
+    if (!lat || lat->L < 3 || lat->L > kMaxL) return false;
+    const int64_t N = (int64_t)lat->L * lat->L * lat->L;
+    return lat->n_sites == N && lat->n_edges == 3 * N && lat->n_faces == 3 * N;
+}
+
+Geo geo_of(const tc3d_lattice* lat) { return Geo{lat->L, (int)lat->n_sites}; }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int64_t words_of(int64_t shots) { return (shots + 63) / 64; }
+
+uint32_t threshold_of(double prob) {
+    if (!(prob > 0.0)) return 0;
+    const double t = floor(prob * 4294967296.0);
+    return t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t plane_bytes(const tc3d_lattice* lat, int64_t nw) {
+    return round_up((size_t)lat->n_edges * (size_t)nw * 8, 256);
+}
+
+size_t nu_bytes(const tc3d_lattice* lat, int64_t n_shots) {
+    return round_up((size_t)12 * (size_t)lat->n_sites * (size_t)(64 * words_of(n_shots)) * 4,
+                    256);
+}
+
+// BP schedule (Section 4.1): `iters` flooding iterations, then the hard
+// decision. With a scalar prior the first iteration's messages are
+// (-1)^s * nu1 for every check, so they are not stored: the second iteration
+// reads them straight from the syndrome.
+int bp_run(const Ctx& c, Geo g, BpArgs a, int32_t iters, float* buf0, float* buf1, Plane corr,
+           float* post) {
+    int rc;
+    int mode;
+    const float* cur = nullptr;
+    float* bufs[2] = {buf0, buf1};
+    int nb = 0;
+    if (!a.llr0) {
+        const double t = tanh(0.5 * (double)a.l0);
+        a.nu1 = (float)(2.0 * atanh((double)a.K * t * t * t));
+        mode = NU_SIGMA;
+    } else {
+        rc = launch_bp_iter(c, g, a, NU_ZERO, nullptr, bufs[nb], TC3D_K_BP_FIRST);
+        if (rc) return rc;
+        cur = bufs[nb];
+        nb ^= 1;
+        mode = NU_LOAD;
+    }
+    for (int32_t it = 2; it <= iters; ++it) {
+        rc = launch_bp_iter(c, g, a, mode, cur, bufs[nb],
+                            mode == NU_SIGMA ? TC3D_K_BP_FIRST : TC3D_K_BP_ITER);
+        if (rc) return rc;
+        cur = bufs[nb];
+        nb ^= 1;
+        mode = NU_LOAD;
+    }
+    return launch_bp_post(c, g, a, mode, cur, corr, post);
+}
+
+bool prob_ok(double p) { return p >= 0.0 && p <= 1.0; }
+
+int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
+    if (!lattice_ok(lat) || !prm) return TC3D_EINVAL;
+    if (!(prm->p >= 0.0 && prm->p < 0.5) || !(prm->q >= 0.0 && prm->q < 0.5)) return TC3D_EINVAL;
+    if (prm->noisy_cycles < 0 || prm->n_sweeps < 0 || prm->n_sweeps > kMaxSweeps ||
+        prm->bp_iters < 0 || prm->n_shots < 0 || prm->batch_shots < 0)
+        return TC3D_EINVAL;
+    if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
+    if (prm->shot0 % 64 != 0 || prm->batch_shots % 64 != 0) return TC3D_EINVAL;
+    if (prm->shot0 + (uint64_t)prm->n_shots >= (1ull << 34)) return TC3D_EINVAL;
+    if (prm->bp_iters > 0 && !(prm->p_dec > 0.0 && prm->p_dec < 0.5 && prm->q_dec > 0.0 &&
+                               prm->q_dec < 0.5))
+        return TC3D_EINVAL;
+    return TC3D_OK;
+}
+
+// Words decoded together.
+int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm) {
+    const int64_t W = words_of(prm->n_shots);
+    if (W == 0) return 0;
+    if (prm->batch_shots > 0) return std::min<int64_t>(W, prm->batch_shots / 64);
+    const size_t per_word = 3 * plane_bytes(lat, 1) +
+                            (prm->bp_iters > 0 ? 2 * nu_bytes(lat, 64) : 0);
+    const size_t budget = (size_t)24 << 30;
+    return std::max<int64_t>(1, std::min<int64_t>(W, (int64_t)(budget / per_word)));
+}
+
+size_t run_ws_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t* nb_out) {
+    const int64_t nb = batch_words(lat, prm);
+    if (nb_out) *nb_out = nb;
+    if (nb == 0) return 256;
+    size_t b = 3 * plane_bytes(lat, nb);  // syn, corr, flips
+    if (prm->bp_iters > 0) b += 2 * nu_bytes(lat, 64 * nb);
+    return b;
+}
+
+int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
+             uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes, const Ctx& c) {
+    int rc = check_run(lat, prm);
+    if (rc) return rc;
+    if (prm->n_shots == 0) return TC3D_OK;
+    if (!err || !mask) return TC3D_EINVAL;
+    if (!aligned(err, 8) || (odd && !aligned(odd, 4))) return TC3D_EALIGN;
+    int64_t nb = 0;
+    const size_t need = run_ws_bytes(lat, prm, &nb);
+    if (!ws || ws_bytes < need) return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
+    const Geo g = geo_of(lat);
+    const int64_t W = words_of(prm->n_shots);
+    const int64_t rows = lat->n_edges;
+    char* base = (char*)ws;
+    uint64_t* syn = (uint64_t*)base;
+    uint64_t* corr = (uint64_t*)(base + plane_bytes(lat, nb));
+    uint64_t* flips = (uint64_t*)(base + 2 * plane_bytes(lat, nb));
+    float* nu0 = nullptr;
+    float* nu1 = nullptr;
+    if (prm->bp_iters > 0) {
+        nu0 = (float*)(base + 3 * plane_bytes(lat, nb));
+        nu1 = (float*)((char*)nu0 + nu_bytes(lat, 64 * nb));
+    }
+    const int32_t cycles = prm->noisy_cycles + prm->perfect_final;
+    const uint32_t th_p = threshold_of(prm->p), th_q = threshold_of(prm->q);
+    const float l0 = (float)log((1.0 - prm->p_dec) / prm->p_dec);
+    const float K = (float)(1.0 - 2.0 * prm->q_dec);
+    for (int64_t w0 = 0; w0 < W; w0 += nb) {
+        const int64_t bw = std::min(nb, W - w0);
+        const uint64_t gword0 = prm->shot0 / 64 + (uint64_t)w0;
+        const Plane E{err + w0, W}, S{syn, bw}, C{corr, bw}, F{flips, bw};
+        const CPlane cE{err + w0, W}, cS{syn, bw}, cC{corr, bw}, cF{flips, bw};
+        for (int32_t t = 0; t < cycles; ++t) {
+            const bool noisy = t < prm->noisy_cycles;
+            const uint32_t tp = (noisy || prm->final_qubit_noise) ? th_p : 0u;
+            const uint32_t tq = noisy ? th_q : 0u;
+            if ((rc = launch_noise(c, g, E, bw, gword0, 0u, (uint32_t)t, tp, prm->seed))) return rc;
+            if ((rc = launch_syndrome(c, g, cE, S, bw, 0, tq, gword0, (uint32_t)t, prm->seed)))
+                return rc;
+            if (prm->bp_iters > 0) {
+                BpArgs a{cS, nullptr, l0, K, 0.f, bw, 64 * bw};
+                if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
+                if ((rc = launch_syndrome(c, g, cC, S, bw, 1, 0u, 0, 0, 0))) return rc;
+            } else {
+                if ((rc = launch_clear(c, C, rows, bw))) return rc;
+            }
+            for (int32_t k = 0; k < prm->n_sweeps; ++k) {
+                const int pf = (int)((prm->pflip_mask >> k) & 1u);
+                if ((rc = launch_sweep_decide(c, g, cS, C, F, bw, pf, gword0, (uint32_t)t,
+                                              (uint32_t)k, prm->seed)))
+                    return rc;
+                if ((rc = launch_syndrome(c, g, cF, S, bw, 1, 0u, 0, 0, 0))) return rc;
+            }
+            if ((rc = launch_xor(c, E, cC, rows, bw))) return rc;
+        }
+        const int64_t shots_b = std::min<int64_t>(64 * bw, prm->n_shots - 64 * w0);
+        if ((rc = launch_readout(c, g, cE, shots_b, mask + 64 * w0, odd ? odd + 3 * 64 * w0 : nullptr)))
+            return rc;
+    }
+    return TC3D_OK;
+}
+
+}  // namespace
+}  // namespace tc3d
+
+using namespace tc3d;
+
+extern "C" {
+
+int tc3d_make_lattice(int32_t L, tc3d_lattice* out) {
+    if (!out || L < 3 || L > kMaxL) return TC3D_EINVAL;
+    const int64_t N = (int64_t)L * L * L;
+    out->L = L;
+    out->reserved = 0;
+    out->n_sites = N;
+    out->n_edges = 3 * N;
+    out->n_faces = 3 * N;
+    return TC3D_OK;
+}
+
+int tc3d_sample_noise(const tc3d_lattice* lat, uint64_t* plane, int32_t kind, double prob,
+                      uint64_t seed, uint32_t cycle, uint64_t shot0, int64_t n_shots,
+                      void* stream) {
+    if (!lattice_ok(lat) || (kind != 0 && kind != 1) || !prob_ok(prob) || n_shots < 0 ||
+        shot0 % 64 != 0 || shot0 + (uint64_t)n_shots >= (1ull << 34))
+        return TC3D_EINVAL;
+    if (n_shots == 0) return TC3D_OK;
+    if (!plane) return TC3D_EINVAL;
+    if (!aligned(plane, 8)) return TC3D_EALIGN;
+    const int64_t nw = words_of(n_shots);
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return launch_noise(c, geo_of(lat), Plane{plane, nw}, nw, shot0 / 64, (uint32_t)kind, cycle,
+                        threshold_of(prob), seed);
+}
+
+int tc3d_syndrome(const tc3d_lattice* lat, const uint64_t* err, uint64_t* syn,
+                  int64_t n_words, int32_t xor_into, void* stream) {
+    if (!lattice_ok(lat) || n_words < 0) return TC3D_EINVAL;
+    if (n_words == 0) return TC3D_OK;
+    if (!err || !syn) return TC3D_EINVAL;
+    if (!aligned(err, 8) || !aligned(syn, 8)) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return launch_syndrome(c, geo_of(lat), CPlane{err, n_words}, Plane{syn, n_words}, n_words,
+                           xor_into ? 1 : 0, 0u, 0, 0, 0);
+}
+
+size_t tc3d_sweep_workspace_bytes(const tc3d_lattice* lat, int64_t n_words) {
+    if (!lattice_ok(lat) || n_words < 0) return 0;
+    return plane_bytes(lat, n_words);
+}
+
+static int sweep_common(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
+                        int pflip, uint64_t seed, uint32_t cycle, uint32_t sweep, uint64_t shot0,
+                        void* ws, size_t ws_bytes, void* stream) {
+    if (!lattice_ok(lat) || n_words < 0 || shot0 % 64 != 0) return TC3D_EINVAL;
+    if (n_words == 0) return TC3D_OK;
+    if (!syn || !corr) return TC3D_EINVAL;
+    if (!aligned(syn, 8) || !aligned(corr, 8)) return TC3D_EALIGN;
+    if (!ws || ws_bytes < plane_bytes(lat, n_words)) return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    const Geo g = geo_of(lat);
+    uint64_t* F = (uint64_t*)ws;
+    int rc = launch_sweep_decide(c, g, CPlane{syn, n_words}, Plane{corr, n_words},
+                                 Plane{F, n_words}, n_words, pflip, shot0 / 64, cycle, sweep, seed);
+    if (rc) return rc;
+    return launch_syndrome(c, g, CPlane{F, n_words}, Plane{syn, n_words}, n_words, 1, 0u, 0, 0, 0);
+}
+
+int tc3d_flip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
+                    void* ws, size_t ws_bytes, void* stream) {
+    return sweep_common(lat, syn, corr, n_words, 0, 0, 0, 0, 0, ws, ws_bytes, stream);
+}
+
+int tc3d_pflip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
+                     uint64_t seed, uint32_t cycle, uint32_t sweep, uint64_t shot0, void* ws,
+                     size_t ws_bytes, void* stream) {
+    return sweep_common(lat, syn, corr, n_words, 1, seed, cycle, sweep, shot0, ws, ws_bytes,
+                        stream);
+}
+
+size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots) {
+    if (!lattice_ok(lat) || n_shots < 0) return 0;
+    return 2 * nu_bytes(lat, n_shots);
+}
+
+static bool bp_scalars_ok(float l0, float K) {
+    return isfinite(l0) && K >= 0.0f && K < 1.0f;
+}
+
+int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                   const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
+                   uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes,
+                   void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0 || iters < 1 || !bp_scalars_ok(llr0_scalar, meas_factor))
+        return TC3D_EINVAL;
+    if (n_shots == 0) return TC3D_OK;
+    if (!syn || !corr_out) return TC3D_EINVAL;
+    if (!aligned(syn, 8) || !aligned(corr_out, 8) || (llr0 && !aligned(llr0, 4)) ||
+        (post_out && !aligned(post_out, 4)))
+        return TC3D_EALIGN;
+    const size_t half = nu_bytes(lat, n_shots);
+    if (!ws || ws_bytes < 2 * half) return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
+    const int64_t nw = words_of(n_shots);
+    const Ctx c{(hipStream_t)stream, nullptr};
+    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw};
+    float* b0 = (float*)ws;
+    float* b1 = (float*)((char*)ws + half);
+    return bp_run(c, geo_of(lat), a, iters, b0, b1, Plane{corr_out, nw}, post_out);
+}
+
+int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                 const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
+                 float* nu_out, float* post_out, void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0 || !bp_scalars_ok(llr0_scalar, meas_factor))
+        return TC3D_EINVAL;
+    if (n_shots == 0) return TC3D_OK;
+    if (!syn || !nu_out || nu_in == nu_out) return TC3D_EINVAL;
+    if (!aligned(syn, 8) || !aligned(nu_out, 4) || (nu_in && !aligned(nu_in, 4)) ||
+        (llr0 && !aligned(llr0, 4)) || (post_out && !aligned(post_out, 4)))
+        return TC3D_EALIGN;
+    const int64_t nw = words_of(n_shots);
+    const Ctx c{(hipStream_t)stream, nullptr};
+    const Geo g = geo_of(lat);
+    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw};
+    int rc = launch_bp_iter(c, g, a, nu_in ? NU_LOAD : NU_ZERO, nu_in, nu_out,
+                            nu_in ? TC3D_K_BP_ITER : TC3D_K_BP_FIRST);
+    if (rc || !post_out) return rc;
+    // posterior of the new state; no correction plane (the store is skipped)
+    return launch_bp_post(c, g, a, NU_LOAD, nu_out, Plane{nullptr, nw}, post_out);
+}
+
+int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_shots,
+                       uint8_t* mask_out, int32_t* odd_out, void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0) return TC3D_EINVAL;
+    if (n_shots == 0) return TC3D_OK;
+    if (!err || !mask_out) return TC3D_EINVAL;
+    if (!aligned(err, 8) || (odd_out && !aligned(odd_out, 4))) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return launch_readout(c, geo_of(lat), CPlane{err, words_of(n_shots)}, n_shots, mask_out,
+                          odd_out);
+}
+
+size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm) {
+    if (check_run(lat, prm)) return 0;
+    return run_ws_bytes(lat, prm, nullptr);
+}
+
+int tc3d_run_cycles(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err_state,
+                    uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
+                    void* stream) {
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return run_impl(lat, prm, err_state, mask_out, odd_out, ws, ws_bytes, c);
+}
+
+int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
+                          uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
+                          size_t ws_bytes, void* stream, tc3d_timing* timing) {
+    if (!timing) return TC3D_EINVAL;
+    Timer tm((hipStream_t)stream);
+    const Ctx c{(hipStream_t)stream, &tm};
+    int rc = run_impl(lat, prm, err_state, mask_out, odd_out, ws, ws_bytes, c);
+    int rc2 = tm.finish(timing);
+    return rc ? rc : rc2;
+}
+
+const char* tc3d_strerror(int code) {
+    switch (code) {
+        case TC3D_OK: return "ok";
+        case TC3D_EINVAL: return "invalid argument";
+        case TC3D_EALIGN: return "misaligned pointer";
+        case TC3D_EHIP: return "HIP launch or runtime error";
+        case TC3D_EWORKSPACE: return "workspace missing or too small";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

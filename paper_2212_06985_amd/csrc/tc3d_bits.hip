@@ -1,0 +1,210 @@
+// Bit-sliced kernels: 64 shots per uint64 word, one work item per
+// (lattice row, word). Noise (Sections 3.1, 4.1), syndrome (Section 2),
+// flip / p-flip decisions (Sections 3.1, 3.2) and the majority-vote readout.
+#include "tc3d_device.hpp"
+#include "tc3d_internal.hpp"
+
+namespace tc3d {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_noise(uint64_t* __restrict__ plane, int64_t ld,
+                                                  int64_t rows, int64_t nw, uint64_t word0,
+                                                  uint32_t tag, uint32_t cycle, uint32_t th,
+                                                  uint32_t k0, uint32_t k1) {
+    const int64_t G = gridDim.x;
+    const int64_t blk = xcd_block(blockIdx.x, G);
+    const int64_t idx = blk * kBlock + threadIdx.x;
+    if (idx >= rows * nw) return;
+    const int64_t row = idx / nw, w = idx - row * nw;
+    const uint64_t bits = bernoulli_word((uint32_t)row, cycle, word0 + (uint64_t)w, tag, th, k0, k1);
+    plane[row * ld + w] ^= bits;
+}
+
+// dst[f] (=|^=) XOR of src over the four members of face f, optionally with
+// check-outcome noise (tag 1) XORed in.
+__global__ __launch_bounds__(kBlock) void k_syndrome(const uint64_t* __restrict__ src,
+                                                     int64_t ld_src, uint64_t* __restrict__ dst,
+                                                     int64_t ld_dst, int64_t nw, int L, int N,
+                                                     int xor_into, uint32_t th, uint64_t word0,
+                                                     uint32_t cycle, uint32_t k0, uint32_t k1) {
+    const int64_t G = gridDim.x;
+    const int64_t blk = xcd_block(blockIdx.x, G);
+    const int64_t idx = blk * kBlock + threadIdx.x;
+    const int64_t rows = 3 * (int64_t)N;
+    if (idx >= rows * nw) return;
+    const int64_t f = idx / nw, w = idx - f * nw;
+    const int n = (int)(f / N), v = (int)(f - (int64_t)n * N);
+    int m[4];
+    face_members(n, coord_of(v, L), L, N, m);
+    uint64_t s = src[m[0] * ld_src + w] ^ src[m[1] * ld_src + w] ^ src[m[2] * ld_src + w] ^
+                 src[m[3] * ld_src + w];
+    if (th) s ^= bernoulli_word((uint32_t)f, cycle, word0 + (uint64_t)w, 1u, th, k0, k1);
+    uint64_t* o = dst + f * ld_dst + w;
+    *o = xor_into ? (*o ^ s) : s;
+}
+
+// Decision pass of one sweep. a..d: the four checks of the edge, one bit per
+// shot. At least 3 of 4 unsatisfied -> flip; exactly 2 -> flip if p-flip and
+// the coin is 1. corr ^= F; F stored for the check update.
+__global__ __launch_bounds__(kBlock) void k_sweep(const uint64_t* __restrict__ syn, int64_t ld_s,
+                                                  uint64_t* __restrict__ corr, int64_t ld_c,
+                                                  uint64_t* __restrict__ fpl, int64_t ld_f,
+                                                  int64_t nw, int L, int N, int pflip,
+                                                  uint64_t word0, uint32_t cycle, uint32_t sweep,
+                                                  uint32_t k0, uint32_t k1) {
+    const int64_t G = gridDim.x;
+    const int64_t blk = xcd_block(blockIdx.x, G);
+    const int64_t idx = blk * kBlock + threadIdx.x;
+    const int64_t rows = 3 * (int64_t)N;
+    if (idx >= rows * nw) return;
+    const int64_t e = idx / nw, w = idx - e * nw;
+    const int ax = (int)(e / N), v = (int)(e - (int64_t)ax * N);
+    int f[4];
+    edge_faces(ax, coord_of(v, L), L, N, f);
+    const uint64_t a = syn[f[0] * ld_s + w], b = syn[f[1] * ld_s + w];
+    const uint64_t c = syn[f[2] * ld_s + w], d = syn[f[3] * ld_s + w];
+    const uint64_t ab = a & b, cd = c & d;
+    uint64_t F = (ab & (c | d)) | (cd & (a | b));
+    if (pflip) {
+        const uint64_t eq2 = ((a ^ b) & (c ^ d)) | (ab & ~(c | d)) | (cd & ~(a | b));
+        F |= eq2 & coin_word((uint32_t)e, cycle, word0 + (uint64_t)w, sweep, k0, k1);
+    }
+    corr[e * ld_c + w] ^= F;
+    fpl[e * ld_f + w] = F;
+}
+
+__global__ __launch_bounds__(kBlock) void k_xor(uint64_t* __restrict__ dst, int64_t ld_d,
+                                                const uint64_t* __restrict__ src, int64_t ld_s,
+                                                int64_t rows, int64_t nw) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= rows * nw) return;
+    const int64_t r = idx / nw, w = idx - r * nw;
+    dst[r * ld_d + w] ^= src[r * ld_s + w];
+}
+
+__global__ __launch_bounds__(kBlock) void k_clear(uint64_t* __restrict__ dst, int64_t ld,
+                                                  int64_t rows, int64_t nw) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= rows * nw) return;
+    const int64_t r = idx / nw, w = idx - r * nw;
+    dst[r * ld + w] = 0;
+}
+
+// One wavefront per word: every lane is one shot of that word. For each axis
+// d the wave walks the L^2 logical Z strings along d, XORs the L words of a
+// string (a wave-uniform load) and each lane counts the strings whose bit is
+// odd; the lane then writes its shot's mask byte and counts.
+__global__ __launch_bounds__(64) void k_readout(const uint64_t* __restrict__ err, int64_t ld,
+                                                int L, int N, int64_t n_shots,
+                                                uint8_t* __restrict__ mask,
+                                                int32_t* __restrict__ odd) {
+    const int64_t nw = (n_shots + 63) / 64;
+    const int64_t w = blockIdx.x;
+    if (w >= nw) return;
+    const int lane = threadIdx.x;
+    const int64_t LL = (int64_t)L * L;
+    uint32_t bits = 0;
+    int count[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // stride between consecutive edges of a string, and of the two other axes
+        const int64_t step = d == 0 ? 1 : (d == 1 ? L : LL);
+        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        const int64_t s1 = d1 == 0 ? 1 : (d1 == 1 ? L : LL);
+        const int64_t s2 = d2 == 0 ? 1 : (d2 == 1 ? L : LL);
+        const uint64_t* base = err + (int64_t)d * N * ld + w;
+        int cnt = 0;
+        for (int i = 0; i < L; ++i)
+            for (int j = 0; j < L; ++j) {
+                const uint64_t* row = base + (i * s1 + j * s2) * ld;
+                uint64_t par = 0;
+                for (int t = 0; t < L; ++t) par ^= row[t * step * ld];
+                cnt += (int)((par >> lane) & 1u);
+            }
+        count[d] = cnt;
+        if (2 * (int64_t)cnt >= LL) bits |= 1u << d;
+    }
+    const int64_t shot = w * 64 + lane;
+    if (shot >= n_shots) return;
+    mask[shot] = (uint8_t)bits;
+    if (odd) {
+        odd[shot * 3 + 0] = count[0];
+        odd[shot * 3 + 1] = count[1];
+        odd[shot * 3 + 2] = count[2];
+    }
+}
+
+inline int64_t blocks_for(int64_t items) { return (items + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+int launch_noise(const Ctx& c, Geo g, Plane plane, int64_t nw, uint64_t word0, uint32_t tag,
+                 uint32_t cycle, uint32_t th, uint64_t seed) {
+    if (th == 0 || nw == 0) return TC3D_OK;
+    const int64_t rows = 3 * (int64_t)g.N;
+    int rc = before_launch(c, TC3D_K_NOISE);
+    if (rc) return rc;
+    k_noise<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(
+        plane.p, plane.ld, rows, nw, word0, tag, cycle, th, (uint32_t)seed,
+        (uint32_t)(seed >> 32));
+    return after_launch(c);
+}
+
+int launch_syndrome(const Ctx& c, Geo g, CPlane src, Plane dst, int64_t nw, int xor_into,
+                    uint32_t th_meas, uint64_t word0, uint32_t cycle, uint64_t seed) {
+    if (nw == 0) return TC3D_OK;
+    const int64_t rows = 3 * (int64_t)g.N;
+    int rc = before_launch(c, TC3D_K_SYNDROME);
+    if (rc) return rc;
+    k_syndrome<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(
+        src.p, src.ld, dst.p, dst.ld, nw, g.L, g.N, xor_into, th_meas, word0, cycle,
+        (uint32_t)seed, (uint32_t)(seed >> 32));
+    return after_launch(c);
+}
+
+int launch_sweep_decide(const Ctx& c, Geo g, CPlane syn, Plane corr, Plane fplane, int64_t nw,
+                        int pflip, uint64_t word0, uint32_t cycle, uint32_t sweep,
+                        uint64_t seed) {
+    if (nw == 0) return TC3D_OK;
+    const int64_t rows = 3 * (int64_t)g.N;
+    int rc = before_launch(c, TC3D_K_SWEEP);
+    if (rc) return rc;
+    k_sweep<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(
+        syn.p, syn.ld, corr.p, corr.ld, fplane.p, fplane.ld, nw, g.L, g.N, pflip, word0, cycle,
+        sweep, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return after_launch(c);
+}
+
+int launch_xor(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw) {
+    if (nw == 0 || rows == 0) return TC3D_OK;
+    int rc = before_launch(c, TC3D_K_APPLY);
+    if (rc) return rc;
+    k_xor<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(
+        dst.p, dst.ld, src.p, src.ld, rows, nw);
+    return after_launch(c);
+}
+
+int launch_clear(const Ctx& c, Plane dst, int64_t rows, int64_t nw) {
+    if (nw == 0 || rows == 0) return TC3D_OK;
+    int rc = before_launch(c, TC3D_K_APPLY);
+    if (rc) return rc;
+    k_clear<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(dst.p, dst.ld,
+                                                                                   rows, nw);
+    return after_launch(c);
+}
+
+int launch_readout(const Ctx& c, Geo g, CPlane err, int64_t n_shots, uint8_t* mask,
+                   int32_t* odd) {
+    if (n_shots == 0) return TC3D_OK;
+    const int64_t nw = (n_shots + 63) / 64;
+    int rc = before_launch(c, TC3D_K_READOUT);
+    if (rc) return rc;
+    k_readout<<<dim3((unsigned)nw), dim3(64), 0, c.stream>>>(err.p, err.ld, g.L, g.N, n_shots,
+                                                             mask, odd);
+    return after_launch(c);
+}
+
+}  // namespace tc3d

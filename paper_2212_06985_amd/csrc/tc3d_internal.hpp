@@ -1,0 +1,110 @@
+// Internal launch interface shared by the kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "tc3d.h"
+
+namespace tc3d {
+
+// Optional per-launch HIP-event timing (used by tc3d_run_cycles_timed).
+class Timer {
+  public:
+    explicit Timer(hipStream_t s) : stream_(s) {}
+    ~Timer();
+    int begin(int kclass);  // records the start event of the next launch
+    int end();              // records its stop event
+    int finish(tc3d_timing* out);  // waits for all events and sums them
+
+  private:
+    struct Slot {
+        hipEvent_t start = nullptr, stop = nullptr;
+        int kclass = -1;
+        bool pending = false;
+    };
+    int drain(Slot& s);
+    hipStream_t stream_;
+    std::vector<Slot> slots_;
+    size_t next_ = 0;
+    int cur_ = -1;
+    hipEvent_t first_ = nullptr, last_ = nullptr;
+    double ms_[TC3D_K_COUNT] = {};
+    int64_t launches_[TC3D_K_COUNT] = {};
+};
+
+struct Ctx {
+    hipStream_t stream;
+    Timer* timer;  // nullptr: no timing
+};
+
+// A bit plane view: rows x nw words, row stride ld words.
+struct Plane {
+    uint64_t* p;
+    int64_t ld;
+};
+struct CPlane {
+    const uint64_t* p;
+    int64_t ld;
+};
+
+struct Geo {
+    int L;
+    int N;  // L^3
+};
+
+// ---------------------------------------------------------------- bit planes
+// plane[row][w] ^= Bernoulli bits of (row, cycle, global word word0 + w, tag).
+int launch_noise(const Ctx& c, Geo g, Plane plane, int64_t nw, uint64_t word0, uint32_t tag,
+                 uint32_t cycle, uint32_t th, uint64_t seed);
+// dst (faces) = / ^= H src (edges), optionally XOR check-outcome noise.
+int launch_syndrome(const Ctx& c, Geo g, CPlane src, Plane dst, int64_t nw, int xor_into,
+                    uint32_t th_meas, uint64_t word0, uint32_t cycle, uint64_t seed);
+// F = flip (pflip=0) or p-flip decisions; corr ^= F; F written to fplane.
+int launch_sweep_decide(const Ctx& c, Geo g, CPlane syn, Plane corr, Plane fplane, int64_t nw,
+                        int pflip, uint64_t word0, uint32_t cycle, uint32_t sweep,
+                        uint64_t seed);
+// dst ^= src over rows x nw.
+int launch_xor(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw);
+// dst = 0 over rows x nw.
+int launch_clear(const Ctx& c, Plane dst, int64_t rows, int64_t nw);
+// Majority-vote readout of n_shots shots of an edge plane.
+int launch_readout(const Ctx& c, Geo g, CPlane err, int64_t n_shots, uint8_t* mask,
+                   int32_t* odd);
+
+// ----------------------------------------------------------------------- BP
+enum NuMode { NU_ZERO = 0, NU_SIGMA = 1, NU_LOAD = 2 };
+
+struct BpArgs {
+    CPlane syn;          // face plane
+    const float* llr0;   // [3N][S_pad] or nullptr
+    float l0;            // scalar prior when llr0 == nullptr
+    float K;             // measurement factor 1 - 2q
+    float nu1;           // first-iteration message magnitude (NU_SIGMA only)
+    int64_t nw;          // words in the batch
+    int64_t s_pad;       // 64 * nw
+};
+
+// One iteration: nu_out = BP(nu_in) where the incoming state is given by mode.
+int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu_in,
+                   float* nu_out, int kclass);
+// Posterior from the state (mode, nu); corr (edge plane) = [posterior < 0];
+// post (may be null) = posterior floats.
+int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
+                   float* post);
+
+// Wrappers around hipGetLastError / timers for the launchers.
+int after_launch(const Ctx& c);
+int before_launch(const Ctx& c, int kclass);
+
+// Blocks over (work items) rounded so that a workgroup index maps onto the 8
+// XCDs in contiguous chunks: logical block of hardware block b.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+    const int64_t j = b & 7, i = b >> 3;
+    const int64_t q = G >> 3, r = G & 7;
+    return j < r ? j * (q + 1) + i : r * (q + 1) + (j - r) * q + i;
+}
+
+}  // namespace tc3d

@@ -52,20 +52,19 @@ def pack(bits: np.ndarray) -> np.ndarray:
     """[S][sites] uint8 -> [sites][W] uint64 (padding shots are zero)."""
     S, n = bits.shape
     W = n_words(S)
-    padded = np.zeros((W * 64, n), np.uint8)
-    padded[:S] = bits
-    # shot 64w+i -> bit i of word w
-    b = padded.reshape(W, 64, n).transpose(2, 0, 1).astype(np.uint64)  # [n][W][64]
-    shifts = np.arange(64, dtype=np.uint64)
-    return np.bitwise_or.reduce(b << shifts, axis=2)
+    padded = np.zeros((n, W * 64), np.uint8)
+    padded[:, :S] = bits.T
+    # little bit order: shot 64w+i -> bit i of word w (little-endian words)
+    by = np.packbits(padded, axis=1, bitorder="little")  # [n][W*8] bytes
+    return np.ascontiguousarray(by).view(np.uint64).reshape(n, W)
 
 
 def unpack(words: np.ndarray, n_shots: int) -> np.ndarray:
     """[sites][W] uint64 -> [S][sites] uint8."""
     n, W = words.shape
-    shifts = np.arange(64, dtype=np.uint64)
-    b = ((words[:, :, None] >> shifts) & np.uint64(1)).astype(np.uint8)  # [n][W][64]
-    return b.reshape(n, W * 64).T[:n_shots].copy()
+    by = np.ascontiguousarray(words).view(np.uint8).reshape(n, W * 8)
+    b = np.unpackbits(by, axis=1, bitorder="little")  # [n][W*64]
+    return np.ascontiguousarray(b[:, :n_shots].T)
 
 
 def nu_to_gpu(nu: np.ndarray, L: int, s_pad: int) -> np.ndarray:

@@ -1,0 +1,111 @@
+"""The C-ABI library loads and exports every entry point that include/tc3d.h
+declares; size queries and argument checks that launch nothing behave as
+documented. No GPU needed: nothing here launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2212_06985_amd as tc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tc3d.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc3d_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tc.LIB_PATH):
+        import paper_2212_06985_amd.build as b
+        b.build()
+    return tc.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+    for name in ("tc3d_make_lattice", "tc3d_sample_noise", "tc3d_syndrome", "tc3d_bp_decode",
+                 "tc3d_flip_sweep", "tc3d_pflip_sweep", "tc3d_run_cycles",
+                 "tc3d_logical_check"):
+        assert name in syms
+
+
+def test_make_lattice(lib):
+    lat = tc.make_lattice(6)
+    assert (lat.L, lat.n_sites, lat.n_edges, lat.n_faces) == (6, 216, 648, 648)
+    bad = tc.Lattice()
+    for L in (0, 2, 513, -4):
+        assert lib.tc3d_make_lattice(L, ctypes.byref(bad)) == -1
+    assert lib.tc3d_make_lattice(8, None) == -1
+
+
+def test_workspace_sizes(lib):
+    lat = tc.make_lattice(12)
+    # one edge plane per sweep, rounded to 256 bytes
+    assert tc.sweep_workspace_bytes(lat, 3) == ((5184 * 3 * 8 + 255) // 256) * 256
+    # two FP32 message buffers of 12 L^3 S_pad
+    assert tc.bp_workspace_bytes(lat, 100) == 2 * 12 * 1728 * 128 * 4
+    prm = tc.make_run_params(0.05, 0.05, 12, 20, 6, 0b001001, n_shots=1000, batch_shots=512)
+    need = tc.run_workspace_bytes(lat, prm)
+    assert need == 3 * ((5184 * 8 * 8 + 255) // 256) * 256 + 2 * 12 * 1728 * 512 * 4
+    corrupt = tc.make_lattice(12)
+    corrupt.n_edges = 7
+    assert lib.tc3d_sweep_workspace_bytes(ctypes.byref(corrupt), 3) == 0
+
+
+def test_invalid_parameters_are_rejected_before_any_launch(lib):
+    lat = tc.make_lattice(6)
+    cases = [
+        dict(p=0.6),                       # probability out of range
+        dict(shot0=10),                    # not a multiple of 64
+        dict(batch_shots=100),             # not a multiple of 64
+        dict(n_sweeps=40),                 # too many sweeps
+        dict(p_dec=0.0),                   # BP prior must be in (0, 0.5)
+        dict(q_dec=0.5),
+        dict(perfect_final=2),
+    ]
+    for over in cases:
+        kw = dict(p=0.02, q=0.02, noisy_cycles=6, bp_iters=20, n_sweeps=5, pflip_mask=4,
+                  n_shots=100)
+        kw.update({k: v for k, v in over.items() if k in kw})
+        prm = tc.make_run_params(**kw)
+        for k, v in over.items():
+            setattr(prm, k, v)
+        assert lib.tc3d_run_workspace_bytes(ctypes.byref(lat), ctypes.byref(prm)) == 0, over
+        rc = lib.tc3d_run_cycles(ctypes.byref(lat), ctypes.byref(prm), None, None, None, None, 0,
+                                 None)
+        assert rc == -1, over
+    # stage entry points
+    assert lib.tc3d_sample_noise(ctypes.byref(lat), None, 2, 0.1, 1, 0, 0, 64, None) == -1
+    assert lib.tc3d_sample_noise(ctypes.byref(lat), None, 0, 1.5, 1, 0, 0, 64, None) == -1
+    assert lib.tc3d_sample_noise(ctypes.byref(lat), None, 0, 0.1, 1, 0, 32, 64, None) == -1
+    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 1.0, 20, None, None, None,
+                              0, None) == -1  # meas_factor must be < 1
+    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 0, None, None, None,
+                              0, None) == -1  # iters >= 1
+    # empty calls are no-ops
+    assert lib.tc3d_syndrome(ctypes.byref(lat), None, None, 0, 0, None) == 0
+    assert lib.tc3d_logical_check(ctypes.byref(lat), None, 0, None, None, None) == 0
+
+
+def test_misaligned_and_missing_buffers(lib):
+    lat = tc.make_lattice(4)
+    # misaligned plane pointer is refused before anything runs
+    assert lib.tc3d_syndrome(ctypes.byref(lat), ctypes.c_void_p(4), ctypes.c_void_p(8), 1, 0,
+                             None) == -2
+    # workspace missing
+    assert lib.tc3d_flip_sweep(ctypes.byref(lat), ctypes.c_void_p(256), ctypes.c_void_p(512), 1,
+                               None, 0, None) == -4
+
+
+def test_strerror(lib):
+    assert lib.tc3d_strerror(0) == b"ok"
+    assert b"workspace" in lib.tc3d_strerror(-4)

@@ -1,0 +1,197 @@
+"""GPU parity of the whole experiment (tc3d_run_cycles) against the oracle.
+
+* flip + p-flip without BP (L = 6, p = q = 0.02, 6 noisy cycles + 1 perfect,
+  schedule F F P F F, 10^4 shots, seed 1): every shot's residual error, mask
+  and odd-string counts bit for bit, and the residual after every cycle.
+* with BP (FP32 against FP64): shots whose BP decisions never met a
+  near-tie agree bit for bit; the rest are counted and the logical error
+  rates agree within 3 sigma.
+* the full-size configuration (L = 48, p = q = 0.05, BP 20 + P F F P F F,
+  2048 shots per batch): sampled shots against the oracle after one cycle,
+  plus properties that hold at any size (valid residual syndromes,
+  reproducibility, independence of the batch split).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import paper_2212_06985_amd as tc
+from gpu_util import announce, bits_of_dev, oracle_run_parallel, plane_from_dev
+from oracle.oracle import Oracle, make_params
+
+pytestmark = pytest.mark.gpu
+
+FFPFF = 0b00100
+PFFPFF = 0b001001
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need an MI355X"
+    tc.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def gpu_run(L, prm, err=None, timed=False):
+    import torch
+    lat = tc.make_lattice(L)
+    S = prm.n_shots
+    W = tc.n_words(S)
+    if err is None:
+        err = torch.zeros((lat.n_edges, W), dtype=torch.int64, device="cuda")
+    mask = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    odd = torch.zeros((S, 3), dtype=torch.int32, device="cuda")
+    ws = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
+    if timed:
+        t = tc.run_cycles_timed(lat, prm, err, mask, odd, ws)
+    else:
+        tc.run_cycles(lat, prm, err, mask, odd, ws)
+        t = None
+    torch.cuda.synchronize()
+    return (mask.cpu().numpy(), odd.cpu().numpy(), bits_of_dev(err, S), t)
+
+
+def oracle_params(p, q, noisy, bp, sweeps, mask, seed=1, perfect_final=1):
+    return make_params(p, q, noisy_cycles=noisy, bp_iters=bp, n_sweeps=sweeps,
+                       pflip_mask=mask, seed=seed, perfect_final=perfect_final)
+
+
+def test_flip_pflip_config_bit_exact():
+    L, S = 6, 10_000
+    announce(f"run_cycles flip+p-flip L={L} S={S}")
+    prm = tc.make_run_params(0.02, 0.02, 6, 0, 5, FFPFF, n_shots=S, seed=1)
+    m_g, odd_g, e_g, _ = gpu_run(L, prm)
+    o = Oracle(L)
+    m_o, odd_o, e_o = oracle_run_parallel(o, oracle_params(0.02, 0.02, 6, 0, 5, FFPFF), S)
+    assert np.array_equal(e_g, e_o)
+    assert np.array_equal(odd_g, odd_o)
+    assert np.array_equal(m_g, m_o)
+    announce(f"  logical failures (any axis) {int((m_g != 0).sum())} / {S}")
+    # a different batch split gives identical results
+    prm.batch_shots = 1024
+    m_b, odd_b, e_b, _ = gpu_run(L, prm)
+    assert np.array_equal(e_b, e_g) and np.array_equal(m_b, m_g)
+
+
+def test_flip_pflip_every_cycle_bit_exact():
+    """Residual after every cycle: the run truncated after t cycles equals the
+    oracle's trace at cycle t (trajectories depend only on seed, shot, cycle)."""
+    L, S = 6, 640
+    o = Oracle(L)
+    full = oracle_params(0.02, 0.02, 6, 0, 5, FFPFF)
+    _, _, _, tr = o.run_cycles(full, S, trace=True)
+    for t in range(1, 7):
+        announce(f"  prefix of {t} noisy cycles")
+        prm = tc.make_run_params(0.02, 0.02, t, 0, 5, FFPFF, n_shots=S, seed=1, perfect_final=0)
+        _, _, e_g, _ = gpu_run(L, prm)
+        assert np.array_equal(e_g, tr[t - 1]), t
+    prm = tc.make_run_params(0.02, 0.02, 6, 0, 5, FFPFF, n_shots=S, seed=1)
+    _, _, e_g, _ = gpu_run(L, prm)
+    assert np.array_equal(e_g, tr[6])
+
+
+def test_run_continues_from_given_state_and_shot_offset():
+    L, S = 5, 200
+    o = Oracle(L)
+    init = inputs.random_bits(9, S, o.n_edges, 0.01)
+    prm_o = oracle_params(0.03, 0.03, 3, 0, 5, FFPFF, seed=44)
+    m_o, odd_o, e_o = o.run_cycles(prm_o, S, shot0=640, err=init.copy())
+    prm = tc.make_run_params(0.03, 0.03, 3, 0, 5, FFPFF, n_shots=S, seed=44, shot0=640)
+    from gpu_util import dev_plane_of_bits
+    d = dev_plane_of_bits(init)
+    m_g, odd_g, e_g, _ = gpu_run(L, prm, err=d)
+    assert np.array_equal(e_g, e_o) and np.array_equal(m_g, m_o)
+
+
+def _compare_bp_run(L, S, p, noisy, seed=1):
+    prm = tc.make_run_params(p, p, noisy, 20, 6, PFFPFF, n_shots=S, seed=seed)
+    m_g, odd_g, e_g, _ = gpu_run(L, prm)
+    o = Oracle(L)
+    m_o, odd_o, e_o = oracle_run_parallel(o, oracle_params(p, p, noisy, 20, 6, PFFPFF, seed), S)
+    same = (e_g == e_o).all(axis=1) & (m_g == m_o)
+    n_div = int((~same).sum())
+    f_g, f_o = (m_g & 1 != 0).mean(), (m_o & 1 != 0).mean()
+    sig = math.sqrt(f_g * (1 - f_g) / S + f_o * (1 - f_o) / S)
+    announce(f"  L={L} p={p}: diverged shots {n_div}/{S}; LER(x) gpu {f_g:.4f} "
+             f"oracle {f_o:.4f}")
+    return n_div, f_g, f_o, sig
+
+
+@pytest.mark.parametrize("L,S,p,noisy", [(6, 512, 0.05, 6), (5, 256, 0.04, 5),
+                                         (12, 128, 0.05, 3)])
+def test_bp_pflip_run_matches_oracle(L, S, p, noisy):
+    announce(f"run_cycles BP+p-flip L={L} S={S} p={p}")
+    n_div, f_g, f_o, sig = _compare_bp_run(L, S, p, noisy)
+    assert n_div <= max(2, S // 50)  # FP32 vs FP64 near-ties are rare
+    assert abs(f_g - f_o) <= 3 * sig + 1e-12
+
+
+def test_timed_run_counts_launches():
+    L, S = 5, 128
+    prm = tc.make_run_params(0.05, 0.05, 2, 7, 6, PFFPFF, n_shots=S, seed=3)
+    m_a, _, e_a, t = gpu_run(L, prm, timed=True)
+    m_b, _, e_b, _ = gpu_run(L, prm)
+    assert np.array_equal(e_a, e_b) and np.array_equal(m_a, m_b)
+    d = t.as_dict()
+    cycles = 3
+    assert d["bp_iter"]["launches"] == cycles * (7 - 2)
+    assert d["bp_first"]["launches"] == cycles
+    assert d["bp_post"]["launches"] == cycles
+    assert d["sweep"]["launches"] == cycles * 6
+    assert d["readout"]["launches"] == 1
+    assert t.total_ms >= sum(v["ms"] for v in d.values()) * 0.5
+
+
+# ----------------------------------------------------------- full size
+def test_full_size_sampled_shots_and_invariants():
+    """L = 48, p = q = 0.05, BP 20 + P F F P F F, 2048 shots in one batch (the
+    benchmark's launch configuration): sampled shots after one cycle against
+    the oracle, then invariants of a longer run at full size."""
+    import torch
+    import geom
+    L, S = 48, 2048
+    announce(f"full size L={L} S={S}: one cycle")
+    prm = tc.make_run_params(0.05, 0.05, 1, 20, 6, PFFPFF, n_shots=S, seed=1, perfect_final=0,
+                             batch_shots=2048)
+    m_g, odd_g, e_g, _ = gpu_run(L, prm)
+    o = Oracle(L)
+    samples = [0, 63, 64, 1001, 2047]
+    import concurrent.futures as cf
+    po = oracle_params(0.05, 0.05, 1, 20, 6, PFFPFF, perfect_final=0)
+    with cf.ThreadPoolExecutor(len(samples)) as ex:
+        res = list(ex.map(lambda s: o.run_cycles(po, 1, shot0=s), samples))
+    n_same = 0
+    for s, (m, odd, e) in zip(samples, res):
+        diff = int((e[0] != e_g[s]).sum())
+        announce(f"  shot {s}: residual weight gpu {int(e_g[s].sum())} oracle {int(e[0].sum())}"
+                 f" differing edges {diff}")
+        n_same += diff == 0
+    assert n_same >= len(samples) - 1
+
+    announce("full size: 3 noisy + 1 perfect cycle, invariants")
+    prm = tc.make_run_params(0.05, 0.05, 3, 20, 6, PFFPFF, n_shots=S, seed=1,
+                             batch_shots=2048)
+    m1, odd1, e1, _ = gpu_run(L, prm)
+    m2, odd2, e2, _ = gpu_run(L, prm)
+    assert np.array_equal(e1, e2) and np.array_equal(m1, m2)  # reproducible
+    prm.batch_shots = 1024
+    m3, odd3, e3, _ = gpu_run(L, prm)
+    assert np.array_equal(e1, e3) and np.array_equal(m1, m3)  # batch split
+    # every residual syndrome is a valid closed-loop one: cube parities even
+    lat = tc.make_lattice(L)
+    d_e = torch.from_numpy(inputs.pack(e1).view(np.int64)).cuda()
+    syn = torch.zeros_like(d_e)
+    tc.syndrome(lat, d_e, syn, tc.n_words(S))
+    N = L ** 3
+    sy = syn.view(3, L, L, L, -1)  # [normal][z][y][x][word]
+    par = torch.zeros_like(sy[0])
+    for n in range(3):
+        par ^= sy[n] ^ torch.roll(sy[n], shifts=-1, dims=2 - n)
+    assert int(par.abs().sum()) == 0
+    w_mean = e1.sum(axis=1).mean()
+    announce(f"  mean residual weight {w_mean:.1f} of {3 * N}; failures {(m1 != 0).sum()}")
+    assert w_mean < 0.01 * 3 * N
