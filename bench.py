@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--shots", type=int, default=None, help="shots per step")
     ap.add_argument("--batch-shots", type=int, default=0)
+    ap.add_argument("--noisy-cycles", type=int, default=None,
+                    help="override the workload's noisy cycles (short counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibrate", type=int, default=0,
@@ -176,6 +178,8 @@ def main():
     cfg = dict(WORKLOADS[args.workload])
     if args.shots:
         cfg["shots"] = args.shots
+    if args.noisy_cycles is not None:
+        cfg["noisy"] = args.noisy_cycles
     steps = cfg["steps"] if args.steps is None else args.steps
     warmup = cfg["warmup"] if args.warmup is None else args.warmup
     L, S = cfg["L"], cfg["shots"]

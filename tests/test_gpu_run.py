@@ -194,4 +194,6 @@ def test_full_size_sampled_shots_and_invariants():
     assert int(par.abs().sum()) == 0
     w_mean = e1.sum(axis=1).mean()
     announce(f"  mean residual weight {w_mean:.1f} of {3 * N}; failures {(m1 != 0).sum()}")
-    assert w_mean < 0.01 * 3 * N
+    # the last cycle adds fresh noise at rate p; decoding keeps the residual
+    # well below that
+    assert w_mean < 0.5 * 0.05 * 3 * N
