@@ -149,6 +149,7 @@ def main():
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--shots", type=int, default=None, help="shots per step")
     ap.add_argument("--batch-shots", type=int, default=0)
+    ap.add_argument("--bp-tile", type=int, default=0, help="BP traversal tile (0: auto)")
     ap.add_argument("--noisy-cycles", type=int, default=None,
                     help="override the workload's noisy cycles (short counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -193,7 +194,8 @@ def main():
     def params(step):
         p = cfg["ps"][step % len(cfg["ps"])]
         return tc.make_run_params(p, p, cfg["noisy"], cfg["bp"], cfg["sweeps"], cfg["mask"],
-                                  n_shots=S, seed=1, shot0=64 * W * step, batch_shots=batch)
+                                  n_shots=S, seed=1, shot0=64 * W * step, batch_shots=batch,
+                                  bp_tile=args.bp_tile)
 
     need = max(tc.run_workspace_bytes(lat, params(k)) for k in range(len(cfg["ps"])))
     ws = tc.alloc_workspace(need)

@@ -127,8 +127,8 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
                    uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes, void* stream);
 
 /* One flooding BP iteration, for inspection and parity checks. Message
- * arrays are FP32 [12][L^3][S_pad]: row (4n + k) * L^3 + v holds the message
- * from face f(v,n) to its member edge k. nu_in == NULL means the first
+ * arrays are FP32 [L^3][12][S_pad]: row 12 v + 4n + k holds the message from
+ * face f(v,n) to its member edge k. nu_in == NULL means the first
  * iteration (every variable-to-check message equals its prior). post_out
  * (NULL ok) receives the posterior computed from nu_out, [3L^3][S_pad]. */
 int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
@@ -162,6 +162,9 @@ typedef struct {
     int64_t batch_shots;       /* shots decoded together (multiple of 64);
                                   0 picks a size that keeps the workspace near
                                   24 GiB                                         */
+    int32_t bp_tile;           /* BP traversal tile edge in sites (a tuning knob
+                                  that never changes results); 0 = automatic    */
+    int32_t reserved;          /* zero                                           */
 } tc3d_run_params;
 
 size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);

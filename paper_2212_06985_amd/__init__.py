@@ -47,6 +47,7 @@ class RunParams(ctypes.Structure):
         ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
         ("seed", ctypes.c_uint64), ("shot0", ctypes.c_uint64),
         ("n_shots", ctypes.c_int64), ("batch_shots", ctypes.c_int64),
+        ("bp_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -218,12 +219,12 @@ def run_cycles_timed(lat, prm: RunParams, err_state, mask_out, odd_out, ws,
 
 def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,
                     shot0=0, p_dec=None, q_dec=None, perfect_final=1, final_qubit_noise=1,
-                    batch_shots=0) -> RunParams:
+                    batch_shots=0, bp_tile=0) -> RunParams:
     return RunParams(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                      q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                      perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                      bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
-                     shot0=shot0, n_shots=n_shots, batch_shots=batch_shots)
+                     shot0=shot0, n_shots=n_shots, batch_shots=batch_shots, bp_tile=bp_tile)
 
 
 __all__.append("make_run_params")

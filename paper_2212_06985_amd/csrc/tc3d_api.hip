@@ -163,7 +163,8 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
     if (!lattice_ok(lat) || !prm) return TC3D_EINVAL;
     if (!(prm->p >= 0.0 && prm->p < 0.5) || !(prm->q >= 0.0 && prm->q < 0.5)) return TC3D_EINVAL;
     if (prm->noisy_cycles < 0 || prm->n_sweeps < 0 || prm->n_sweeps > kMaxSweeps ||
-        prm->bp_iters < 0 || prm->n_shots < 0 || prm->batch_shots < 0)
+        prm->bp_iters < 0 || prm->n_shots < 0 || prm->batch_shots < 0 || prm->bp_tile < 0 ||
+        prm->bp_tile > kMaxL)
         return TC3D_EINVAL;
     if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
     if (prm->shot0 % 64 != 0 || prm->batch_shots % 64 != 0) return TC3D_EINVAL;
@@ -235,7 +236,7 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
             if ((rc = launch_syndrome(c, g, cE, S, bw, 0, tq, gword0, (uint32_t)t, prm->seed)))
                 return rc;
             if (prm->bp_iters > 0) {
-                BpArgs a{cS, nullptr, l0, K, 0.f, bw, 64 * bw};
+                BpArgs a{cS, nullptr, l0, K, 0.f, bw, 64 * bw, prm->bp_tile};
                 if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
                 if ((rc = launch_syndrome(c, g, cC, S, bw, 1, 0u, 0, 0, 0))) return rc;
             } else {
@@ -361,7 +362,7 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
     if (!aligned(ws, 256)) return TC3D_EALIGN;
     const int64_t nw = words_of(n_shots);
     const Ctx c{(hipStream_t)stream, nullptr};
-    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw};
+    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw, 0};
     float* b0 = (float*)ws;
     float* b1 = (float*)((char*)ws + half);
     return bp_run(c, geo_of(lat), a, iters, b0, b1, Plane{corr_out, nw}, post_out);
@@ -380,7 +381,7 @@ int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
     const int64_t nw = words_of(n_shots);
     const Ctx c{(hipStream_t)stream, nullptr};
     const Geo g = geo_of(lat);
-    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw};
+    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw, 0};
     int rc = launch_bp_iter(c, g, a, nu_in ? NU_LOAD : NU_ZERO, nu_in, nu_out,
                             nu_in ? TC3D_K_BP_ITER : TC3D_K_BP_FIRST);
     if (rc || !post_out) return rc;

@@ -85,6 +85,7 @@ struct BpArgs {
     float nu1;           // first-iteration message magnitude (NU_SIGMA only)
     int64_t nw;          // words in the batch
     int64_t s_pad;       // 64 * nw
+    int tile;            // site-tile edge of the traversal order (0: automatic)
 };
 
 // One iteration: nu_out = BP(nu_in) where the incoming state is given by mode.

@@ -68,17 +68,17 @@ def unpack(words: np.ndarray, n_shots: int) -> np.ndarray:
 
 
 def nu_to_gpu(nu: np.ndarray, L: int, s_pad: int) -> np.ndarray:
-    """Oracle messages [S][face][4] -> GPU layout [(normal*4+k)][site][s_pad]."""
+    """Oracle messages [S][face][4] -> GPU layout [site][normal*4+k][s_pad]."""
     S = nu.shape[0]
     N = L ** 3
-    out = np.zeros((12, N, s_pad), np.float32)
+    out = np.zeros((N, 12, s_pad), np.float32)
     r = nu.reshape(S, 3, N, 4)  # face = normal*N + site
-    out[:, :, :S] = r.transpose(1, 3, 2, 0).reshape(12, N, S)
+    out[:, :, :S] = r.transpose(2, 1, 3, 0).reshape(N, 12, S)
     return out
 
 
 def nu_from_gpu(g: np.ndarray, L: int, n_shots: int) -> np.ndarray:
-    """GPU layout [12][site][s_pad] -> oracle [S][face][4] (FP64)."""
+    """GPU layout [site][12][s_pad] -> oracle [S][face][4] (FP64)."""
     N = L ** 3
-    r = np.asarray(g, np.float64).reshape(3, 4, N, -1)[:, :, :, :n_shots]
-    return r.transpose(3, 0, 2, 1).reshape(n_shots, 3 * N, 4).copy()
+    r = np.asarray(g, np.float64).reshape(N, 3, 4, -1)[:, :, :, :n_shots]
+    return r.transpose(3, 1, 0, 2).reshape(n_shots, 3 * N, 4).copy()

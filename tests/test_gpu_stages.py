@@ -198,7 +198,7 @@ def test_bp_one_step_parity(L, n_shots, per_edge_prior):
     if per_edge_prior:
         llr_f32 = inputs.random_llr(L, full, o.n_edges, 0.5, 5.0).astype(np.float32)
         d_llr = to_dev(np.ascontiguousarray(llr_f32.T))  # [3N][S_pad]
-    nu = [torch.zeros((12, N, full), dtype=torch.float32, device="cuda") for _ in range(2)]
+    nu = [torch.zeros((N, 12, full), dtype=torch.float32, device="cuda") for _ in range(2)]
     post = torch.zeros((3 * N, full), dtype=torch.float32, device="cuda")
     prev = None
     worst = 0.0
@@ -285,7 +285,7 @@ def test_bp_decode_matches_chained_steps():
     corr = torch.zeros((3 * N, W), dtype=torch.int64, device="cuda")
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     tc.bp_decode(lat, d_syn, n_shots, None, l0, K, 5, corr, post_a, ws)
-    nu = [torch.zeros((12, N, full), dtype=torch.float32, device="cuda") for _ in range(2)]
+    nu = [torch.zeros((N, 12, full), dtype=torch.float32, device="cuda") for _ in range(2)]
     post_b = torch.zeros_like(post_a)
     prev = None
     for t in range(5):
