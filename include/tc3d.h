@@ -121,16 +121,20 @@ size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
  *   llr0      per-edge priors [3L^3][S_pad] in nats, or NULL to use
  *             llr0_scalar = ln((1-p)/p) on every edge
  *   post_out  posterior LLRs [3L^3][S_pad], or NULL
- * 0 <= meas_factor < 1; llr0_scalar finite. */
+ * 0 <= meas_factor < 1; |llr0_scalar| <= 40 (per-edge priors are clamped to
+ * +-40 nats). */
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                    const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
                    uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes, void* stream);
 
-/* One flooding BP iteration, for inspection and parity checks. Message
- * arrays are FP32 [L^3][12][S_pad]: row 12 v + 4n + k holds the message from
- * face f(v,n) to its member edge k. nu_in == NULL means the first
- * iteration (every variable-to-check message equals its prior). post_out
- * (NULL ok) receives the posterior computed from nu_out, [3L^3][S_pad]. */
+/* One flooding BP iteration, for inspection and parity checks. The state is
+ * the factor-to-variable messages in multiplicative form, e^nu (the form the
+ * decoder iterates in: sums of messages become products and the check rule
+ * needs no exp or log). Arrays are FP32 [L^3][12][S_pad]: row 12 v + 4n + k
+ * holds e^nu of the message from face f(v,n) to its member edge k.
+ * nu_in == NULL means the first iteration (every variable-to-check message
+ * equals its prior). post_out (NULL ok) receives the posterior LLR (nats)
+ * computed from nu_out, [3L^3][S_pad]. */
 int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                  const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
                  float* nu_out, float* post_out, void* stream);

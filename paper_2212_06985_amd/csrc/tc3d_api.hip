@@ -128,16 +128,14 @@ size_t nu_bytes(const tc3d_lattice* lat, int64_t n_shots) {
 // decision. With a scalar prior the first iteration's messages are
 // (-1)^s * nu1 for every check, so they are not stored: the second iteration
 // reads them straight from the syndrome.
-int bp_run(const Ctx& c, Geo g, BpArgs a, int32_t iters, float* buf0, float* buf1, Plane corr,
-           float* post) {
+int bp_run(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, float* buf0, float* buf1,
+           Plane corr, float* post) {
     int rc;
     int mode;
     const float* cur = nullptr;
     float* bufs[2] = {buf0, buf1};
     int nb = 0;
     if (!a.llr0) {
-        const double t = tanh(0.5 * (double)a.l0);
-        a.nu1 = (float)(2.0 * atanh((double)a.K * t * t * t));
         mode = NU_SIGMA;
     } else {
         rc = launch_bp_iter(c, g, a, NU_ZERO, nullptr, bufs[nb], TC3D_K_BP_FIRST);
@@ -158,6 +156,27 @@ int bp_run(const Ctx& c, Geo g, BpArgs a, int32_t iters, float* buf0, float* buf
 }
 
 bool prob_ok(double p) { return p >= 0.0 && p <= 1.0; }
+
+}  // namespace
+
+BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw, int tile) {
+    BpArgs a;
+    a.syn = syn;
+    a.llr0 = llr0;
+    a.l0 = l0;
+    a.K = K;
+    const double t = tanh(0.5 * (double)l0);
+    const double nu1 = 2.0 * atanh((double)K * t * t * t);
+    a.a0 = (float)exp((double)l0);
+    a.b1 = (float)exp(nu1);
+    a.b1_inv = (float)exp(-nu1);
+    a.nw = nw;
+    a.s_pad = 64 * nw;
+    a.tile = tile;
+    return a;
+}
+
+namespace {
 
 int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
     if (!lattice_ok(lat) || !prm) return TC3D_EINVAL;
@@ -236,7 +255,7 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
             if ((rc = launch_syndrome(c, g, cE, S, bw, 0, tq, gword0, (uint32_t)t, prm->seed)))
                 return rc;
             if (prm->bp_iters > 0) {
-                BpArgs a{cS, nullptr, l0, K, 0.f, bw, 64 * bw, prm->bp_tile};
+                const BpArgs a = make_bp_args(cS, nullptr, l0, K, bw, prm->bp_tile);
                 if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
                 if ((rc = launch_syndrome(c, g, cC, S, bw, 1, 0u, 0, 0, 0))) return rc;
             } else {
@@ -343,7 +362,7 @@ size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots) {
 }
 
 static bool bp_scalars_ok(float l0, float K) {
-    return isfinite(l0) && K >= 0.0f && K < 1.0f;
+    return isfinite(l0) && fabsf(l0) <= 40.0f && K >= 0.0f && K < 1.0f;
 }
 
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
@@ -362,7 +381,7 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
     if (!aligned(ws, 256)) return TC3D_EALIGN;
     const int64_t nw = words_of(n_shots);
     const Ctx c{(hipStream_t)stream, nullptr};
-    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw, 0};
+    const BpArgs a = make_bp_args(CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, nw, 0);
     float* b0 = (float*)ws;
     float* b1 = (float*)((char*)ws + half);
     return bp_run(c, geo_of(lat), a, iters, b0, b1, Plane{corr_out, nw}, post_out);
@@ -381,7 +400,7 @@ int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
     const int64_t nw = words_of(n_shots);
     const Ctx c{(hipStream_t)stream, nullptr};
     const Geo g = geo_of(lat);
-    BpArgs a{CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, 0.f, nw, 64 * nw, 0};
+    const BpArgs a = make_bp_args(CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, nw, 0);
     int rc = launch_bp_iter(c, g, a, nu_in ? NU_LOAD : NU_ZERO, nu_in, nu_out,
                             nu_in ? TC3D_K_BP_ITER : TC3D_K_BP_FIRST);
     if (rc || !post_out) return rc;

@@ -3,23 +3,32 @@
 // rule, posterior), flooding schedule, with the measurement-error variables
 // folded into a constant factor K = 1 - 2q of every check product.
 //
-// State between iterations is only the factor-to-variable messages nu, FP32,
-// [L^3][12][S_pad] with row 12 v + 4n + k = message of face f(v,n) to its
-// member k; the shot index is the fastest dimension, so a wavefront (64 lanes
-// = 64 consecutive shots of one site) reads and writes 256 contiguous bytes
-// per message row, and the 12 rows of a site are S_pad floats apart. Each
-// access is a wave-uniform 64-bit site base (scalar registers) plus a 32-bit
-// per-lane offset for the row, kept in 12 vector registers.
+// Messages are kept in multiplicative form: the state between iterations is
+// b = e^nu for every factor-to-variable message nu. Then
+//   * the posterior e^l of an edge is e^{l0} times the product of its four
+//     incoming b (E4), and the variable-to-factor message e^mu towards one
+//     check is e^{l0} times the product of the other three (E3);
+//   * with a = e^mu, tanh(mu/2) = (a - 1)/(a + 1), so the check rule E2 for
+//     member k is b_k = (D_k + sK N_k) / (D_k - sK N_k), where N_k and D_k are
+//     the products of (a - 1) and (a + 1) over the other three members and
+//     sK = (-1)^s K (because e^{2 atanh y} = (1 + y)/(1 - y));
+//   * the hard decision l < 0 is e^l < 1.
+// An iteration therefore needs one reciprocal per message and no exp or log.
+// e^mu is clamped to [e^-20, e^20], where tanh(mu/2) is already +-1 in FP32.
+//
+// Layout: FP32 [L^3][12][S_pad], row 12 v + 4n + k = message of face f(v,n)
+// to its member k; the shot index is the fastest dimension, so a wavefront
+// (64 lanes = 64 consecutive shots of one site) reads and writes 256
+// contiguous bytes per message row, and the 12 rows of a site are S_pad
+// floats apart. Each access is a wave-uniform 64-bit site base (scalar
+// registers) plus a 32-bit per-lane row offset held in vector registers.
 //
 // One iteration is one kernel: a wavefront owns site v and its three faces.
-// It rebuilds the posterior l of the 9 edges its faces touch from the old
-// messages (E4: l = l0 + sum of the 4 incoming messages), forms the
-// variable-to-factor messages mu = l - nu_old (E3 written as a difference),
-// and writes the new messages of its faces (E2). The posterior needs 24
-// messages of neighbouring sites; those come from L2 because each XCD walks
-// one shot word at a time through tile columns (T x T sites in x-y, z running
-// slowest inside the column), which keeps every neighbour within T*T sites of
-// the wavefront that first loaded it.
+// The inputs of its 12 check-member messages need 6 of its own messages and
+// 24 messages of neighbouring sites; those come from L2 because each XCD
+// walks one shot word at a time through tile columns (T x T sites in x-y, z
+// running slowest inside the column), which keeps every neighbour within
+// T*T sites of the wavefront that first loaded it.
 #include "tc3d_device.hpp"
 #include "tc3d_internal.hpp"
 
@@ -67,7 +76,8 @@ struct Src {
     const uint64_t* __restrict__ syn;
     int64_t ld_syn;
     const float* __restrict__ llr0;  // nullptr: scalar prior
-    float l0, nu1;
+    float a0;          // e^{l0} of the scalar prior
+    float b1, b1_inv;  // e^{+-nu1}
     int N;
     int64_t s_pad;
 };
@@ -110,15 +120,15 @@ struct Reader {
     int64_t ld_syn, w, site_bytes;
     uint32_t voff[12];  // byte offset of row `slot` for this lane
     int N, lane;
-    float nu1;
+    float b1, b1_inv;  // e^{+-nu1}: first-iteration messages (NU_SIGMA)
 
-    // old message of face f(site, slot / 4) to member slot % 4
+    // e^nu of the old message of face f(site, slot / 4) to member slot % 4
     __device__ __forceinline__ float operator()(int slot, int site) const {
         if constexpr (MODE == NU_ZERO) {
-            return 0.0f;
+            return 1.0f;
         } else if constexpr (MODE == NU_SIGMA) {
             const uint64_t word = syn[((int64_t)(slot >> 2) * N + site) * ld_syn + w];
-            return ((word >> lane) & 1u) ? -nu1 : nu1;
+            return ((word >> lane) & 1u) ? b1_inv : b1;
         } else {
             const char* sb = base + (int64_t)site * site_bytes;
             return *reinterpret_cast<const float*>(sb + voff[slot]);
@@ -138,14 +148,18 @@ __device__ __forceinline__ Reader<MODE> reader_of(const Src& S, const Item& it) 
     for (int k = 0; k < 12; ++k) R.voff[k] = (uint32_t)((k * S.s_pad + it.lane) * 4);
     R.N = S.N;
     R.lane = it.lane;
-    R.nu1 = S.nu1;
+    R.b1 = S.b1;
+    R.b1_inv = S.b1_inv;
     return R;
 }
 
+// e^{l0} of edge e(site, c); per-edge priors are clamped to +-40 nats.
+template <bool EDGE_PRIOR>
 __device__ __forceinline__ float prior(const Src& S, const Item& it, int c, int site) {
-    if (!S.llr0) return S.l0;
+    if constexpr (!EDGE_PRIOR) return S.a0;
     const float* row = S.llr0 + ((int64_t)c * S.N + site) * S.s_pad + it.w * 64;
-    return row[it.lane];
+    const float l = fminf(fmaxf(row[it.lane], -40.0f), 40.0f);
+    return __builtin_amdgcn_exp2f(l * 1.4426950408889634f);
 }
 
 // Neighbour sites of v = (x,y,z) by offset.
@@ -174,86 +188,72 @@ __device__ __forceinline__ Nbr neighbours(const Item& it, int L) {
     return n;
 }
 
-// The check rule E2 for one face from its four member posteriors lm and old
-// messages own: with a_k = e^{mu_k}, tanh(mu_k/2) = (a_k - 1)/(a_k + 1), so
-// the product over the other three members is N_k / D_k with N_k, D_k the
-// leave-one-out products of (a-1) and (a+1), and
-//   2 atanh(sK N_k / D_k) = ln((D_k + sK N_k) / (D_k - sK N_k)).
-// mu is clamped to +-20, where tanh(mu/2) already equals +-1 in FP32.
-__device__ __forceinline__ void check_rule(const float lm[4], const float own[4], float sK,
-                                           float out[4]) {
+// The check rule E2 of one face in multiplicative form: a[k] = e^{mu_k} of
+// its four members (clamped), out[k] = e^{nu_k} of the new messages.
+__device__ __forceinline__ void check_rule(const float a_in[4], float sK, float out[4]) {
     float am[4], ap[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float mu = fminf(fmaxf(lm[k] - own[k], -20.0f), 20.0f);
-        const float a = __builtin_amdgcn_exp2f(mu * 1.4426950408889634f);
+        const float a = fminf(fmaxf(a_in[k], 2.0611536e-9f), 4.85165195e8f);  // e^-+20
         am[k] = a - 1.0f;
         ap[k] = a + 1.0f;
     }
-    const float n01 = am[0] * am[1], n23 = am[2] * am[3];
+    const float sn01 = sK * (am[0] * am[1]), sn23 = sK * (am[2] * am[3]);
     const float d01 = ap[0] * ap[1], d23 = ap[2] * ap[3];
-    const float sn01 = sK * n01, sn23 = sK * n23;
     float Nk[4], Dk[4];
     Nk[0] = am[1] * sn23; Dk[0] = ap[1] * d23;
     Nk[1] = am[0] * sn23; Dk[1] = ap[0] * d23;
     Nk[2] = am[3] * sn01; Dk[2] = ap[3] * d01;
     Nk[3] = am[2] * sn01; Dk[3] = ap[2] * d01;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float r = (Dk[k] + Nk[k]) * __builtin_amdgcn_rcpf(Dk[k] - Nk[k]);
-        out[k] = 0.69314718055994531f * __builtin_amdgcn_logf(r);
-    }
+    for (int k = 0; k < 4; ++k) out[k] = (Dk[k] + Nk[k]) * __builtin_amdgcn_rcpf(Dk[k] - Nk[k]);
 }
 
-template <int MODE>
+template <int MODE, bool EP>
 __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
-                                                    float* __restrict__ nu_out) {
+                                                    float* __restrict__ b_out) {
     const Item it = item_of(tl);
     if (!it.ok) return;
-    const int L = tl.L;
     const Reader<MODE> R = reader_of<MODE>(S, it);
-    const Nbr nb = neighbours(it, L);
+    const Nbr nb = neighbours(it, tl.L);
     const int v = it.v;
-    float own[12];
-#pragma unroll
-    for (int s = 0; s < 12; ++s) own[s] = R(s, v);
-    // posteriors (E4) of the 9 edges touched by the faces of v
-    const float lx = prior(S, it, 0, v) + own[8] + own[4] + R(9, nb.ym) + R(5, nb.zm);
-    const float ly = prior(S, it, 1, v) + own[10] + own[0] + R(11, nb.xm) + R(1, nb.zm);
-    const float lz = prior(S, it, 2, v) + own[6] + own[2] + R(7, nb.xm) + R(3, nb.ym);
-    const float lx_yp =
-        prior(S, it, 0, nb.yp) + R(8, nb.yp) + R(4, nb.yp) + own[9] + R(5, nb.yp_zm);
-    const float lx_zp =
-        prior(S, it, 0, nb.zp) + R(8, nb.zp) + R(4, nb.zp) + R(9, nb.zp_ym) + own[5];
-    const float ly_xp =
-        prior(S, it, 1, nb.xp) + R(10, nb.xp) + R(0, nb.xp) + own[11] + R(1, nb.xp_zm);
-    const float ly_zp =
-        prior(S, it, 1, nb.zp) + R(10, nb.zp) + R(0, nb.zp) + R(11, nb.zp_xm) + own[1];
-    const float lz_xp =
-        prior(S, it, 2, nb.xp) + R(6, nb.xp) + R(2, nb.xp) + own[7] + R(3, nb.xp_ym);
-    const float lz_yp =
-        prior(S, it, 2, nb.yp) + R(6, nb.yp) + R(2, nb.yp) + R(7, nb.yp_xm) + own[3];
-    char* outb = reinterpret_cast<char*>(nu_out + it.w * 64) + (int64_t)v * R.site_bytes;
+    // own messages to the members k = 0, 2 of each face (the others are the
+    // excluded message of the member-k check and are not needed)
+    const float o0 = R(0, v), o2 = R(2, v), o4 = R(4, v), o6 = R(6, v), o8 = R(8, v),
+                o10 = R(10, v);
+    // e^{l0} times the two incoming messages from faces of other sites, for
+    // the three edges at v (each is a member of two of v's faces)
+    const float px = prior<EP>(S, it, 0, v) * R(9, nb.ym) * R(5, nb.zm);
+    const float py = prior<EP>(S, it, 1, v) * R(11, nb.xm) * R(1, nb.zm);
+    const float pz = prior<EP>(S, it, 2, v) * R(7, nb.xm) * R(3, nb.ym);
+    // e^{mu} of the six edges that are a member of one face of v
+    const float a_x_yp = prior<EP>(S, it, 0, nb.yp) * R(8, nb.yp) * R(4, nb.yp) * R(5, nb.yp_zm);
+    const float a_x_zp = prior<EP>(S, it, 0, nb.zp) * R(8, nb.zp) * R(4, nb.zp) * R(9, nb.zp_ym);
+    const float a_y_xp = prior<EP>(S, it, 1, nb.xp) * R(10, nb.xp) * R(0, nb.xp) * R(1, nb.xp_zm);
+    const float a_y_zp = prior<EP>(S, it, 1, nb.zp) * R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
+    const float a_z_xp = prior<EP>(S, it, 2, nb.xp) * R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
+    const float a_z_yp = prior<EP>(S, it, 2, nb.yp) * R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
+    char* outb = reinterpret_cast<char*>(b_out + it.w * 64) + (int64_t)v * R.site_bytes;
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-        float lm[4];
-        if (n == 2) {  // normal z, spans x, y
-            lm[0] = lx; lm[1] = lx_yp; lm[2] = ly; lm[3] = ly_xp;
-        } else if (n == 1) {  // normal y, spans x, z
-            lm[0] = lx; lm[1] = lx_zp; lm[2] = lz; lm[3] = lz_xp;
-        } else {  // normal x, spans y, z
-            lm[0] = ly; lm[1] = ly_zp; lm[2] = lz; lm[3] = lz_yp;
+        float a[4];
+        if (n == 2) {  // normal z: e(v,x), e(v+y,x), e(v,y), e(v+x,y)
+            a[0] = px * o4; a[1] = a_x_yp; a[2] = py * o0; a[3] = a_y_xp;
+        } else if (n == 1) {  // normal y: e(v,x), e(v+z,x), e(v,z), e(v+x,z)
+            a[0] = px * o8; a[1] = a_x_zp; a[2] = pz * o2; a[3] = a_z_xp;
+        } else {  // normal x: e(v,y), e(v+z,y), e(v,z), e(v+y,z)
+            a[0] = py * o10; a[1] = a_y_zp; a[2] = pz * o6; a[3] = a_z_yp;
         }
         const uint64_t sw = S.syn[((int64_t)n * S.N + v) * S.ld_syn + it.w];
         const float sK = ((sw >> it.lane) & 1u) ? -K : K;
         float out[4];
-        check_rule(lm, own + 4 * n, sK, out);
+        check_rule(a, sK, out);
 #pragma unroll
         for (int k = 0; k < 4; ++k) *reinterpret_cast<float*>(outb + R.voff[4 * n + k]) = out[k];
     }
 }
 
-template <int MODE>
+template <int MODE, bool EP>
 __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
                                                     uint64_t* __restrict__ corr, int64_t ld_c,
                                                     float* __restrict__ post) {
@@ -262,18 +262,19 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
     const Reader<MODE> R = reader_of<MODE>(S, it);
     const Nbr nb = neighbours(it, tl.L);
     const int v = it.v;
-    float l[3];
-    l[0] = prior(S, it, 0, v) + R(8, v) + R(4, v) + R(9, nb.ym) + R(5, nb.zm);
-    l[1] = prior(S, it, 1, v) + R(10, v) + R(0, v) + R(11, nb.xm) + R(1, nb.zm);
-    l[2] = prior(S, it, 2, v) + R(6, v) + R(2, v) + R(7, nb.xm) + R(3, nb.ym);
+    // e^l = e^{l0} times the four incoming messages (E4)
+    float el[3];
+    el[0] = prior<EP>(S, it, 0, v) * R(8, v) * R(4, v) * R(9, nb.ym) * R(5, nb.zm);
+    el[1] = prior<EP>(S, it, 1, v) * R(10, v) * R(0, v) * R(11, nb.xm) * R(1, nb.zm);
+    el[2] = prior<EP>(S, it, 2, v) * R(6, v) * R(2, v) * R(7, nb.xm) * R(3, nb.ym);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int64_t e = (int64_t)c * S.N + v;
         if (post) {
             float* row = post + e * S.s_pad + it.w * 64;
-            row[it.lane] = l[c];
+            row[it.lane] = 0.69314718055994531f * __builtin_amdgcn_logf(el[c]);
         }
-        const uint64_t flips = __ballot(l[c] < 0.0f);
+        const uint64_t flips = __ballot(el[c] < 1.0f);
         if (corr && it.lane == 0) corr[e * ld_c + it.w] = flips;
     }
 }
@@ -284,8 +285,9 @@ Src make_src(Geo g, const BpArgs& a, const float* nu) {
     S.syn = a.syn.p;
     S.ld_syn = a.syn.ld;
     S.llr0 = a.llr0;
-    S.l0 = a.l0;
-    S.nu1 = a.nu1;
+    S.a0 = a.a0;
+    S.b1 = a.b1;
+    S.b1_inv = a.b1_inv;
     S.N = g.N;
     S.s_pad = a.s_pad;
     return S;
@@ -332,12 +334,21 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (rc) return rc;
     const Src S = make_src(g, a, nu_in);
     const dim3 grid((unsigned)blocks), block(kBlock);
-    if (mode == NU_ZERO)
-        k_bp_iter<NU_ZERO><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
-    else if (mode == NU_SIGMA)
-        k_bp_iter<NU_SIGMA><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
-    else
-        k_bp_iter<NU_LOAD><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+    if (a.llr0) {
+        if (mode == NU_ZERO)
+            k_bp_iter<NU_ZERO, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        else if (mode == NU_LOAD)
+            k_bp_iter<NU_LOAD, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        else
+            return TC3D_EINVAL;  // the syndrome-implied first state needs a scalar prior
+    } else {
+        if (mode == NU_ZERO)
+            k_bp_iter<NU_ZERO, false><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        else if (mode == NU_SIGMA)
+            k_bp_iter<NU_SIGMA, false><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        else
+            k_bp_iter<NU_LOAD, false><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+    }
     return after_launch(c);
 }
 
@@ -351,12 +362,21 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (rc) return rc;
     const Src S = make_src(g, a, nu);
     const dim3 grid((unsigned)blocks), block(kBlock);
-    if (mode == NU_ZERO)
-        k_bp_post<NU_ZERO><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld, post);
-    else if (mode == NU_SIGMA)
-        k_bp_post<NU_SIGMA><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld, post);
-    else
-        k_bp_post<NU_LOAD><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld, post);
+    if (a.llr0) {
+        if (mode == NU_LOAD)
+            k_bp_post<NU_LOAD, true><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld, post);
+        else
+            return TC3D_EINVAL;  // a posterior follows at least one stored iteration
+    } else {
+        if (mode == NU_SIGMA)
+            k_bp_post<NU_SIGMA, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld,
+                                                                    post);
+        else if (mode == NU_LOAD)
+            k_bp_post<NU_LOAD, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld,
+                                                                   post);
+        else
+            return TC3D_EINVAL;
+    }
     return after_launch(c);
 }
 

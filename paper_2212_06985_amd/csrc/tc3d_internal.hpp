@@ -79,16 +79,21 @@ enum NuMode { NU_ZERO = 0, NU_SIGMA = 1, NU_LOAD = 2 };
 
 struct BpArgs {
     CPlane syn;          // face plane
-    const float* llr0;   // [3N][S_pad] or nullptr
-    float l0;            // scalar prior when llr0 == nullptr
+    const float* llr0;   // [3N][S_pad] per-edge priors (nats) or nullptr
+    float l0;            // scalar prior (nats) when llr0 == nullptr
     float K;             // measurement factor 1 - 2q
-    float nu1;           // first-iteration message magnitude (NU_SIGMA only)
+    float a0;            // e^{l0}
+    float b1, b1_inv;    // e^{+-nu1}, nu1 = 2 atanh(K tanh(l0/2)^3) (NU_SIGMA only)
     int64_t nw;          // words in the batch
     int64_t s_pad;       // 64 * nw
     int tile;            // site-tile edge of the traversal order (0: automatic)
 };
 
-// One iteration: nu_out = BP(nu_in) where the incoming state is given by mode.
+// Fills the derived fields of BpArgs (in double precision, then rounded).
+BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw, int tile);
+
+// One iteration: b_out = BP(b_in) (messages in the form e^nu) where the
+// incoming state is given by mode.
 int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu_in,
                    float* nu_out, int kclass);
 // Posterior from the state (mode, nu); corr (edge plane) = [posterior < 0];

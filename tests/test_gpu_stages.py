@@ -183,7 +183,8 @@ def _bp_inputs(L, n_shots, seed):
 @pytest.mark.parametrize("per_edge_prior", [False, True])
 def test_bp_one_step_parity(L, n_shots, per_edge_prior):
     """Each GPU iteration, recomputed by the oracle in FP64 from the GPU's own
-    previous state, agrees within 1e-4 relative (absolute below 0.1)."""
+    previous state, agrees within 1e-4 relative (absolute below 0.1). The GPU
+    keeps messages as e^nu; they are compared as nu = ln(e^nu)."""
     announce(f"bp one-step L={L} S={n_shots} llr0={per_edge_prior}")
     import torch
     p = q = 0.05
@@ -206,9 +207,11 @@ def test_bp_one_step_parity(L, n_shots, per_edge_prior):
         out = nu[t % 2]
         tc.bp_step(lat, d_syn, n_shots, d_llr, l0, K, prev, out, post)
         sync()
-        g_nu = inputs.nu_from_gpu(out.cpu().numpy(), L, full)
+        # the GPU state is e^nu (multiplicative form); the oracle works on nu
+        g_nu = np.log(inputs.nu_from_gpu(out.cpu().numpy(), L, full))
         g_post = post.cpu().numpy().T.astype(np.float64)
-        g_prev = None if prev is None else inputs.nu_from_gpu(prev.cpu().numpy(), L, full)
+        g_prev = None if prev is None else np.log(inputs.nu_from_gpu(prev.cpu().numpy(), L,
+                                                                     full))
         for s in range(full):
             o_nu, o_post = o.bp_step(
                 syn[s], p, q, nu_in=None if g_prev is None else g_prev[s],
