@@ -19,7 +19,8 @@
  * with rows = 3L^3 (edges or faces) and W = ceil(n_shots/64) words per row;
  * bit i of word w belongs to shot 64*w + i. Bits of padding shots (64*W >
  * n_shots) are computed like any other shot and ignored by the readout.
- * Per-shot float arrays are [rows][S_pad] with S_pad = 64*W.
+ * Per-shot float arrays are blocked by word, [W][rows][64]: element
+ * (w*rows + r)*64 + i belongs to row r and shot 64*w + i.
  *
  * Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
  * 64-bit seed (key word 0 = low half, word 1 = high half).
@@ -118,9 +119,9 @@ size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
  * Runs exactly `iters` >= 1 iterations in FP32, then corr_out (an edge plane,
  * overwritten) gets bit 1 where the posterior LLR is < 0.
  *   syn       face plane [3L^3][W], W = ceil(n_shots/64)
- *   llr0      per-edge priors [3L^3][S_pad] in nats, or NULL to use
+ *   llr0      per-edge priors [W][3L^3][64] in nats, or NULL to use
  *             llr0_scalar = ln((1-p)/p) on every edge
- *   post_out  posterior LLRs [3L^3][S_pad], or NULL
+ *   post_out  posterior LLRs [W][3L^3][64], or NULL
  * 0 <= meas_factor < 1; |llr0_scalar| <= 40 (per-edge priors are clamped to
  * +-40 nats). */
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
@@ -130,11 +131,12 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
 /* One flooding BP iteration, for inspection and parity checks. The state is
  * the factor-to-variable messages in multiplicative form, e^nu (the form the
  * decoder iterates in: sums of messages become products and the check rule
- * needs no exp or log). Arrays are FP32 [L^3][12][S_pad]: row 12 v + 4n + k
- * holds e^nu of the message from face f(v,n) to its member edge k.
- * nu_in == NULL means the first iteration (every variable-to-check message
- * equals its prior). post_out (NULL ok) receives the posterior LLR (nats)
- * computed from nu_out, [3L^3][S_pad]. */
+ * needs no exp or log). Arrays are FP32 [W][L^3][12][64]: row
+ * (w L^3 + v) 12 + 4n + k holds e^nu of the message from face f(v,n) to its
+ * member edge k for the 64 shots of word w. nu_in == NULL means the first
+ * iteration (every variable-to-check message equals its prior). post_out
+ * (NULL ok) receives the posterior LLR (nats) computed from nu_out,
+ * [W][3L^3][64]. */
 int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                  const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
                  float* nu_out, float* post_out, void* stream);

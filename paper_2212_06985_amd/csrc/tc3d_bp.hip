@@ -16,11 +16,12 @@
 // An iteration therefore needs one reciprocal per message and no exp or log.
 // e^mu is clamped to [e^-20, e^20], where tanh(mu/2) is already +-1 in FP32.
 //
-// Layout: FP32 [L^3][12][S_pad], row 12 v + 4n + k = message of face f(v,n)
-// to its member k; the shot index is the fastest dimension, so a wavefront
-// (64 lanes = 64 consecutive shots of one site) reads and writes 256
-// contiguous bytes per message row, and the 12 rows of a site are S_pad
-// floats apart. Each access is a wave-uniform 64-bit site base (scalar
+// Layout: FP32 [W][L^3][12][64]: the messages of one 64-shot word are
+// contiguous, row (w L^3 + v) 12 + 4n + k = message of face f(v,n) to its
+// member k for the 64 shots of word w. A wavefront (64 lanes = the 64 shots
+// of one word at one site) reads and writes 256 contiguous bytes per row and
+// a site's rows are adjacent, so the accesses of a word spread over every L2
+// and HBM channel. Each access is a wave-uniform 64-bit site base (scalar
 // registers) plus a 32-bit per-lane row offset held in vector registers.
 //
 // One iteration is one kernel: a wavefront owns site v and its three faces.
@@ -136,16 +137,20 @@ struct Reader {
     }
 };
 
+// First float of word w in an [W][rows][64] array.
+__device__ __forceinline__ int64_t word_base(int64_t w, int64_t rows) { return w * rows * 64; }
+
 template <int MODE>
 __device__ __forceinline__ Reader<MODE> reader_of(const Src& S, const Item& it) {
     Reader<MODE> R;
-    R.base = S.nu ? reinterpret_cast<const char*>(S.nu + it.w * 64) : nullptr;
+    R.base = S.nu ? reinterpret_cast<const char*>(S.nu + word_base(it.w, 12 * (int64_t)S.N))
+                  : nullptr;
     R.syn = S.syn;
     R.ld_syn = S.ld_syn;
     R.w = it.w;
-    R.site_bytes = 12 * S.s_pad * 4;
+    R.site_bytes = 12 * 64 * 4;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) R.voff[k] = (uint32_t)((k * S.s_pad + it.lane) * 4);
+    for (int k = 0; k < 12; ++k) R.voff[k] = (uint32_t)((k * 64 + it.lane) * 4);
     R.N = S.N;
     R.lane = it.lane;
     R.b1 = S.b1;
@@ -157,7 +162,8 @@ __device__ __forceinline__ Reader<MODE> reader_of(const Src& S, const Item& it) 
 template <bool EDGE_PRIOR>
 __device__ __forceinline__ float prior(const Src& S, const Item& it, int c, int site) {
     if constexpr (!EDGE_PRIOR) return S.a0;
-    const float* row = S.llr0 + ((int64_t)c * S.N + site) * S.s_pad + it.w * 64;
+    const float* row =
+        S.llr0 + word_base(it.w, 3 * (int64_t)S.N) + ((int64_t)c * S.N + site) * 64;
     const float l = fminf(fmaxf(row[it.lane], -40.0f), 40.0f);
     return __builtin_amdgcn_exp2f(l * 1.4426950408889634f);
 }
@@ -233,7 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
     const float a_y_zp = prior<EP>(S, it, 1, nb.zp) * R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
     const float a_z_xp = prior<EP>(S, it, 2, nb.xp) * R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
     const float a_z_yp = prior<EP>(S, it, 2, nb.yp) * R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
-    char* outb = reinterpret_cast<char*>(b_out + it.w * 64) + (int64_t)v * R.site_bytes;
+    char* outb = reinterpret_cast<char*>(b_out + word_base(it.w, 12 * (int64_t)S.N)) +
+                 (int64_t)v * R.site_bytes;
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
         float a[4];
@@ -271,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
     for (int c = 0; c < 3; ++c) {
         const int64_t e = (int64_t)c * S.N + v;
         if (post) {
-            float* row = post + e * S.s_pad + it.w * 64;
+            float* row = post + word_base(it.w, 3 * (int64_t)S.N) + e * 64;
             row[it.lane] = 0.69314718055994531f * __builtin_amdgcn_logf(el[c]);
         }
         const uint64_t flips = __ballot(el[c] < 1.0f);

@@ -68,17 +68,32 @@ def unpack(words: np.ndarray, n_shots: int) -> np.ndarray:
 
 
 def nu_to_gpu(nu: np.ndarray, L: int, s_pad: int) -> np.ndarray:
-    """Oracle messages [S][face][4] -> GPU layout [site][normal*4+k][s_pad]."""
+    """Oracle messages [S][face][4] -> GPU layout [word][site][normal*4+k][64]."""
     S = nu.shape[0]
     N = L ** 3
-    out = np.zeros((N, 12, s_pad), np.float32)
-    r = nu.reshape(S, 3, N, 4)  # face = normal*N + site
-    out[:, :, :S] = r.transpose(2, 1, 3, 0).reshape(N, 12, S)
-    return out
+    full = np.zeros((s_pad, N, 12), np.float32)
+    full[:S] = nu.reshape(S, 3, N, 4).transpose(0, 2, 1, 3).reshape(S, N, 12)
+    W = s_pad // 64
+    return np.ascontiguousarray(full.reshape(W, 64, N, 12).transpose(0, 2, 3, 1))
 
 
 def nu_from_gpu(g: np.ndarray, L: int, n_shots: int) -> np.ndarray:
-    """GPU layout [site][12][s_pad] -> oracle [S][face][4] (FP64)."""
+    """GPU layout [word][site][12][64] -> oracle [S][face][4] (FP64)."""
     N = L ** 3
-    r = np.asarray(g, np.float64).reshape(N, 3, 4, -1)[:, :, :, :n_shots]
-    return r.transpose(3, 1, 0, 2).reshape(n_shots, 3 * N, 4).copy()
+    a = np.asarray(g, np.float64).reshape(-1, N, 12, 64)
+    W = a.shape[0]
+    per_shot = a.transpose(0, 3, 1, 2).reshape(W * 64, N, 12)[:n_shots]  # [S][site][12]
+    return np.ascontiguousarray(
+        per_shot.reshape(n_shots, N, 3, 4).transpose(0, 2, 1, 3).reshape(n_shots, 3 * N, 4))
+
+
+def rows_to_gpu(x: np.ndarray) -> np.ndarray:
+    """Per-shot rows [S_pad][rows] -> word-blocked [W][rows][64] (float32)."""
+    S, R = x.shape
+    return np.ascontiguousarray(x.reshape(S // 64, 64, R).transpose(0, 2, 1).astype(np.float32))
+
+
+def rows_from_gpu(g: np.ndarray, n_rows: int) -> np.ndarray:
+    """Word-blocked [W][rows][64] -> per-shot rows [S_pad][rows]."""
+    a = np.asarray(g).reshape(-1, n_rows, 64)
+    return np.ascontiguousarray(a.transpose(0, 2, 1).reshape(-1, n_rows))

@@ -198,9 +198,9 @@ def test_bp_one_step_parity(L, n_shots, per_edge_prior):
     d_llr = None
     if per_edge_prior:
         llr_f32 = inputs.random_llr(L, full, o.n_edges, 0.5, 5.0).astype(np.float32)
-        d_llr = to_dev(np.ascontiguousarray(llr_f32.T))  # [3N][S_pad]
-    nu = [torch.zeros((N, 12, full), dtype=torch.float32, device="cuda") for _ in range(2)]
-    post = torch.zeros((3 * N, full), dtype=torch.float32, device="cuda")
+        d_llr = to_dev(inputs.rows_to_gpu(llr_f32))  # [W][3N][64]
+    nu = [torch.zeros((W, N, 12, 64), dtype=torch.float32, device="cuda") for _ in range(2)]
+    post = torch.zeros((W, 3 * N, 64), dtype=torch.float32, device="cuda")
     prev = None
     worst = 0.0
     for t in range(20):
@@ -209,7 +209,7 @@ def test_bp_one_step_parity(L, n_shots, per_edge_prior):
         sync()
         # the GPU state is e^nu (multiplicative form); the oracle works on nu
         g_nu = np.log(inputs.nu_from_gpu(out.cpu().numpy(), L, full))
-        g_post = post.cpu().numpy().T.astype(np.float64)
+        g_post = inputs.rows_from_gpu(post.cpu().numpy(), 3 * N).astype(np.float64)
         g_prev = None if prev is None else np.log(inputs.nu_from_gpu(prev.cpu().numpy(), L,
                                                                      full))
         for s in range(full):
@@ -253,13 +253,13 @@ def test_bp_decode_free_running(L, n_shots):
     N = L ** 3
     d_syn = dev_plane_of_bits(syn)
     corr = torch.zeros((3 * N, W), dtype=torch.int64, device="cuda")
-    post = torch.zeros((3 * N, full), dtype=torch.float32, device="cuda")
+    post = torch.zeros((W, 3 * N, 64), dtype=torch.float32, device="cuda")
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     tc.bp_decode(lat, d_syn, n_shots, None, math.log((1 - p) / p), 1 - 2 * q, 20, corr, post, ws)
     sync()
     c_o, p_o = o.bp_decode(syn[:n_shots], p, q, 20)
     c_g = bits_of_dev(corr, n_shots)
-    p_g = post.cpu().numpy().T[:n_shots].astype(np.float64)
+    p_g = inputs.rows_from_gpu(post.cpu().numpy(), 3 * N)[:n_shots].astype(np.float64)
     mism = c_g != c_o
     dev = np.abs(p_g - p_o)
     announce(f"  hard-decision mismatches {int(mism.sum())}, near-tie oracle posteriors "
@@ -284,11 +284,11 @@ def test_bp_decode_matches_chained_steps():
     N = L ** 3
     d_syn = dev_plane_of_bits(syn)
     l0, K = math.log((1 - p) / p), 1 - 2 * q
-    post_a = torch.zeros((3 * N, full), dtype=torch.float32, device="cuda")
+    post_a = torch.zeros((W, 3 * N, 64), dtype=torch.float32, device="cuda")
     corr = torch.zeros((3 * N, W), dtype=torch.int64, device="cuda")
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     tc.bp_decode(lat, d_syn, n_shots, None, l0, K, 5, corr, post_a, ws)
-    nu = [torch.zeros((N, 12, full), dtype=torch.float32, device="cuda") for _ in range(2)]
+    nu = [torch.zeros((W, N, 12, 64), dtype=torch.float32, device="cuda") for _ in range(2)]
     post_b = torch.zeros_like(post_a)
     prev = None
     for t in range(5):
@@ -307,7 +307,7 @@ def test_zero_syndrome_scalar_recursion_on_gpu():
     lat = tc.make_lattice(L)
     d_syn = torch.zeros((3 * L ** 3, 1), dtype=torch.int64, device="cuda")
     corr = torch.zeros_like(d_syn)
-    post = torch.zeros((3 * L ** 3, 64), dtype=torch.float32, device="cuda")
+    post = torch.zeros((1, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     l0 = math.log((1 - p) / p)
     tc.bp_decode(lat, d_syn, n_shots, None, l0, 1 - 2 * q, 20, corr, post, ws)
