@@ -28,8 +28,9 @@
 // The inputs of its 12 check-member messages need 6 of its own messages and
 // 24 messages of neighbouring sites; those come from L2 because each XCD
 // walks one shot word at a time through tile columns (T x T sites in x-y, z
-// running slowest inside the column), which keeps every neighbour within
-// T*T sites of the wavefront that first loaded it.
+// running slowest inside the column; T = L by default, i.e. plain memory
+// order), with the message stores streaming past L2 so that the rows loaded
+// for neighbours stay resident.
 #include "tc3d_device.hpp"
 #include "tc3d_internal.hpp"
 
@@ -255,8 +256,11 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
         const float sK = ((sw >> it.lane) & 1u) ? -K : K;
         float out[4];
         check_rule(a, sK, out);
+        // streaming stores: the new messages are read again only in the next
+        // iteration, so they should not evict the neighbour rows from L2
 #pragma unroll
-        for (int k = 0; k < 4; ++k) *reinterpret_cast<float*>(outb + R.voff[4 * n + k]) = out[k];
+        for (int k = 0; k < 4; ++k)
+            __builtin_nontemporal_store(out[k], reinterpret_cast<float*>(outb + R.voff[4 * n + k]));
     }
 }
 
@@ -300,14 +304,13 @@ Src make_src(Geo g, const BpArgs& a, const float* nu) {
     return S;
 }
 
-// Tile edge: the request if given, else L up to 16, else the largest divisor
-// of L in [8, 16], else 16 with the overhanging sites skipped.
+// Tile edge: the request if given, else L (whole x-y planes in memory order,
+// the fastest order measured at L = 48 once the message stores stream past
+// L2; smaller tiles shorten the z reuse distance but break up the DRAM
+// streams).
 int tile_of(int L, int req) {
     if (req > 0) return req < L ? req : L;
-    if (L <= 16) return L;
-    for (int t = 16; t >= 8; --t)
-        if (L % t == 0) return t;
-    return 16;
+    return L;
 }
 
 // Returns false when the launch's logical indices would not fit 31 bits.
