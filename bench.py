@@ -213,6 +213,8 @@ def main():
 
     per_class = {k: {"ms": 0.0, "launches": 0} for k in tc.KERNEL_CLASSES}
     fails_x = fails_any = 0
+    hist = [0] * 8  # mask histogram: bit d = logical X error on qubit d
+    ties = 0        # majority-vote ties (an axis with exactly L^2/2 odd strings)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -224,6 +226,9 @@ def main():
         m = mask.cpu()
         fails_x += int((m & 1).ne(0).sum())
         fails_any += int(m.ne(0).sum())
+        hb = torch.bincount(m.long(), minlength=8)
+        hist = [h + int(v) for h, v in zip(hist, hb.tolist())]
+        ties += int((2 * odd == L * L).any(dim=1).sum())
         log(f"[bench] step {k}: {t.total_ms:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -256,7 +261,9 @@ def main():
 
     N = S * steps
     ler = {"axis_x": fails_x / N, "axis_x_sigma": (fails_x / N * (1 - fails_x / N) / N) ** 0.5,
-           "any_axis": fails_any / N, "shots": N}
+           "any_axis": fails_any / N, "shots": N,
+           "mask_histogram": {format(k, "03b")[::-1]: hist[k] for k in range(8)},
+           "majority_ties": ties}
     out = {
         "metric": "decoded qubit-cycles/s at fixed logical error rate; CNN-prior vs plain "
                   "BP+p-flip",

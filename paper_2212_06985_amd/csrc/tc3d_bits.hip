@@ -93,48 +93,51 @@ __global__ __launch_bounds__(kBlock) void k_clear(uint64_t* __restrict__ dst, in
     dst[r * ld + w] = 0;
 }
 
-// One wavefront per word: every lane is one shot of that word. For each axis
-// d the wave walks the L^2 logical Z strings along d, XORs the L words of a
-// string (a wave-uniform load) and each lane counts the strings whose bit is
-// odd; the lane then writes its shot's mask byte and counts.
-__global__ __launch_bounds__(64) void k_readout(const uint64_t* __restrict__ err, int64_t ld,
-                                                int L, int N, int64_t n_shots,
-                                                uint8_t* __restrict__ mask,
-                                                int32_t* __restrict__ odd) {
-    const int64_t nw = (n_shots + 63) / 64;
+// One workgroup per word, 12 wavefronts: wavefront 4a + q walks every fourth
+// logical Z string of axis a (strings q, q+4, ...), XORs the L words of a
+// string (a wave-uniform load) and each lane counts the odd strings of its
+// shot. The 12 partial counts meet in LDS; wavefront 0 writes the mask byte
+// and the counts of its 64 shots.
+constexpr int kReadoutParts = 4;
+
+__global__ __launch_bounds__(64 * 3 * kReadoutParts) void k_readout(
+    const uint64_t* __restrict__ err, int64_t ld, int L, int N, int64_t n_shots,
+    uint8_t* __restrict__ mask, int32_t* __restrict__ odd) {
+    __shared__ int part_count[3 * kReadoutParts][64];
     const int64_t w = blockIdx.x;
-    if (w >= nw) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int d = wave / kReadoutParts, q = wave % kReadoutParts;
     const int64_t LL = (int64_t)L * L;
-    uint32_t bits = 0;
-    int count[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        // stride between consecutive edges of a string, and of the two other axes
-        const int64_t step = d == 0 ? 1 : (d == 1 ? L : LL);
-        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-        const int64_t s1 = d1 == 0 ? 1 : (d1 == 1 ? L : LL);
-        const int64_t s2 = d2 == 0 ? 1 : (d2 == 1 ? L : LL);
-        const uint64_t* base = err + (int64_t)d * N * ld + w;
-        int cnt = 0;
-        for (int i = 0; i < L; ++i)
-            for (int j = 0; j < L; ++j) {
-                const uint64_t* row = base + (i * s1 + j * s2) * ld;
-                uint64_t par = 0;
-                for (int t = 0; t < L; ++t) par ^= row[t * step * ld];
-                cnt += (int)((par >> lane) & 1u);
-            }
-        count[d] = cnt;
-        if (2 * (int64_t)cnt >= LL) bits |= 1u << d;
+    // stride between consecutive edges of a string, and of the two other axes
+    const int64_t step = d == 0 ? 1 : (d == 1 ? L : LL);
+    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    const int64_t s1 = d1 == 0 ? 1 : (d1 == 1 ? L : LL);
+    const int64_t s2 = d2 == 0 ? 1 : (d2 == 1 ? L : LL);
+    const uint64_t* base = err + (int64_t)d * N * ld + w;
+    int cnt = 0;
+    for (int64_t str = q; str < LL; str += kReadoutParts) {
+        const int64_t i = str / L, j = str - i * L;
+        const uint64_t* row = base + (i * s1 + j * s2) * ld;
+        uint64_t par = 0;
+        for (int t = 0; t < L; ++t) par ^= row[t * step * ld];
+        cnt += (int)((par >> lane) & 1u);
     }
+    part_count[wave][lane] = cnt;
+    __syncthreads();
+    if (wave != 0) return;
     const int64_t shot = w * 64 + lane;
     if (shot >= n_shots) return;
-    mask[shot] = (uint8_t)bits;
-    if (odd) {
-        odd[shot * 3 + 0] = count[0];
-        odd[shot * 3 + 1] = count[1];
-        odd[shot * 3 + 2] = count[2];
+    uint32_t bits = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int total = 0;
+#pragma unroll
+        for (int k = 0; k < kReadoutParts; ++k) total += part_count[a * kReadoutParts + k][lane];
+        if (2 * (int64_t)total >= LL) bits |= 1u << a;
+        if (odd) odd[shot * 3 + a] = total;
     }
+    mask[shot] = (uint8_t)bits;
 }
 
 inline int64_t blocks_for(int64_t items) { return (items + kBlock - 1) / kBlock; }
@@ -202,8 +205,8 @@ int launch_readout(const Ctx& c, Geo g, CPlane err, int64_t n_shots, uint8_t* ma
     const int64_t nw = (n_shots + 63) / 64;
     int rc = before_launch(c, TC3D_K_READOUT);
     if (rc) return rc;
-    k_readout<<<dim3((unsigned)nw), dim3(64), 0, c.stream>>>(err.p, err.ld, g.L, g.N, n_shots,
-                                                             mask, odd);
+    k_readout<<<dim3((unsigned)nw), dim3(64 * 3 * kReadoutParts), 0, c.stream>>>(
+        err.p, err.ld, g.L, g.N, n_shots, mask, odd);
     return after_launch(c);
 }
 

@@ -118,8 +118,8 @@ __device__ __forceinline__ Item item_of(const Tiling& tl) {
 template <int MODE>
 struct Reader {
     const char* __restrict__ base;  // (char*)(nu + 64 w) (NU_LOAD)
-    const uint64_t* __restrict__ syn;
-    int64_t ld_syn, w, site_bytes;
+    const uint64_t* __restrict__ syn_w;  // syndrome plane + word w (NU_SIGMA)
+    int64_t ld_syn, face_plane, w, site_bytes;
     uint32_t voff[12];  // byte offset of row `slot` for this lane
     int N, lane;
     float b1, b1_inv;  // e^{+-nu1}: first-iteration messages (NU_SIGMA)
@@ -129,7 +129,7 @@ struct Reader {
         if constexpr (MODE == NU_ZERO) {
             return 1.0f;
         } else if constexpr (MODE == NU_SIGMA) {
-            const uint64_t word = syn[((int64_t)(slot >> 2) * N + site) * ld_syn + w];
+            const uint64_t word = syn_w[(slot >> 2) * face_plane + (int64_t)site * ld_syn];
             return ((word >> lane) & 1u) ? b1_inv : b1;
         } else {
             const char* sb = base + (int64_t)site * site_bytes;
@@ -146,8 +146,9 @@ __device__ __forceinline__ Reader<MODE> reader_of(const Src& S, const Item& it) 
     Reader<MODE> R;
     R.base = S.nu ? reinterpret_cast<const char*>(S.nu + word_base(it.w, 12 * (int64_t)S.N))
                   : nullptr;
-    R.syn = S.syn;
+    R.syn_w = S.syn + it.w;
     R.ld_syn = S.ld_syn;
+    R.face_plane = (int64_t)S.N * S.ld_syn;
     R.w = it.w;
     R.site_bytes = 12 * 64 * 4;
 #pragma unroll
