@@ -197,3 +197,24 @@ def test_full_size_sampled_shots_and_invariants():
     # the last cycle adds fresh noise at rate p; decoding keeps the residual
     # well below that
     assert w_mean < 0.5 * 0.05 * 3 * N
+
+
+def test_failing_regime_ler_parity():
+    """Above threshold on a small lattice many shots fail, so the logical error
+    rates compare non-trivially: flip + p-flip bit for bit, p-BP within 3
+    sigma with diverged shots counted."""
+    L, S = 4, 2048
+    announce(f"failing regime flip+p-flip L={L} S={S}")
+    prm = tc.make_run_params(0.06, 0.06, 10, 0, 5, FFPFF, n_shots=S, seed=5)
+    m_g, odd_g, e_g, _ = gpu_run(L, prm)
+    o = Oracle(L)
+    m_o, odd_o, e_o = oracle_run_parallel(o, oracle_params(0.06, 0.06, 10, 0, 5, FFPFF, seed=5), S)
+    assert np.array_equal(m_g, m_o) and np.array_equal(e_g, e_o)
+    f = (m_g != 0).mean()
+    announce(f"  flip+p-flip any-axis LER {f:.4f}")
+    assert f > 0.05
+    announce(f"failing regime p-BP L={L} S=1024")
+    n_div, f_g, f_o, sig = _compare_bp_run(L, 1024, 0.08, 8, seed=6)
+    assert f_o > 0.02
+    assert abs(f_g - f_o) <= 3 * sig
+    assert n_div <= 1024 // 20
