@@ -71,6 +71,10 @@ def lib():
             "tco_bp_decode": (None, [vp, vp, i64, vp, f64, f64, i32, vp, vp]),
             "tco_logical_check": (None, [vp, vp, i64, vp, vp]),
             "tco_run_cycles": (None, [vp, ctypes.POINTER(Params), u64, i64, vp, vp, vp, vp]),
+            "tco_cnn_param_count": (i64, []),
+            "tco_cnn_input": (None, [vp, i64, vp, vp, vp]),
+            "tco_cnn_forward": (None, [vp, i64, vp, vp, vp, vp]),
+            "tco_cnn_loss_grad": (ctypes.c_double, [vp, i64, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -221,6 +225,60 @@ class Oracle:
         lib().tco_run_cycles(self._h, ctypes.byref(params), shot0, n_shots, _p(err), _p(mask),
                              _p(odd), _p(tr))
         return (mask, odd, err, tr) if trace else (mask, odd, err)
+
+
+# CNN prior --------------------------------------------------------------------
+CNN_CHANNELS = (8, 32, 32, 32, 3)
+
+
+def cnn_param_count() -> int:
+    return int(lib().tco_cnn_param_count())
+
+
+def cnn_layers(params: np.ndarray):
+    """Views (W [27][cin][cout], b [cout]) of each layer in a parameter vector."""
+    out, o = [], 0
+    for cin, cout in zip(CNN_CHANNELS[:-1], CNN_CHANNELS[1:]):
+        W = params[o:o + 27 * cin * cout].reshape(27, cin, cout)
+        o += 27 * cin * cout
+        b = params[o:o + cout]
+        o += cout
+        out.append((W, b))
+    return out
+
+
+def _cnn_methods():
+    def cnn_input(self, syn, prev=None):
+        _chk(syn, np.uint8)
+        S = syn.size // self.n_faces
+        x0 = np.zeros((S, self.n_sites, 8), np.float64)
+        lib().tco_cnn_input(self._h, S, _p(syn), _p(prev), _p(x0))
+        return x0
+
+    def cnn_forward(self, x0, params, with_acts=False):
+        _chk(x0, np.float64)
+        _chk(params, np.float64, (cnn_param_count(),))
+        S = x0.size // (self.n_sites * 8)
+        z = np.zeros((S, self.n_sites, 3), np.float64)
+        acts = np.zeros((3, S, self.n_sites, 32), np.float64) if with_acts else None
+        lib().tco_cnn_forward(self._h, S, _p(x0), _p(params), _p(z), _p(acts))
+        return (z, acts) if with_acts else z
+
+    def cnn_loss_grad(self, x0, params, target):
+        _chk(x0, np.float64)
+        _chk(params, np.float64, (cnn_param_count(),))
+        _chk(target, np.uint8)
+        S = x0.size // (self.n_sites * 8)
+        grad = np.zeros(cnn_param_count(), np.float64)
+        loss = lib().tco_cnn_loss_grad(self._h, S, _p(x0), _p(params), _p(target), _p(grad))
+        return float(loss), grad
+
+    Oracle.cnn_input = cnn_input
+    Oracle.cnn_forward = cnn_forward
+    Oracle.cnn_loss_grad = cnn_loss_grad
+
+
+_cnn_methods()
 
 
 def make_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, seed=1, p_dec=None,

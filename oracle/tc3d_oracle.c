@@ -461,3 +461,156 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
     free(corr);
     free(cbp);
 }
+
+/* ---------------------------------------------------------------- CNN prior */
+
+static const int kCnnCh[TCO_CNN_LAYERS + 1] = {8, 32, 32, 32, 3};
+
+int64_t tco_cnn_param_count(void) {
+    int64_t n = 0;
+    for (int l = 0; l < TCO_CNN_LAYERS; ++l) n += 27 * kCnnCh[l] * kCnnCh[l + 1] + kCnnCh[l + 1];
+    return n;
+}
+
+/* neighbour of site v at offset index d (d = (dz+1)*9 + (dy+1)*3 + (dx+1)) */
+static int64_t cnn_nbr(int32_t L, int64_t v, int d) {
+    int64_t x = v % L, y = (v / L) % L, z = v / ((int64_t)L * L);
+    int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    return site_of(L, x + dx, y + dy, z + dz);
+}
+
+void tco_cnn_input(const tco_lattice* lat, int64_t n_shots, const uint8_t* syn,
+                   const uint8_t* prev, double* x0) {
+    const int64_t N = lat->n_sites, m = lat->n_faces;
+    for (int64_t s = 0; s < n_shots; ++s)
+        for (int64_t v = 0; v < N; ++v) {
+            double* o = x0 + (s * N + v) * 8;
+            for (int n = 0; n < 3; ++n) {
+                o[n] = syn[s * m + n * N + v];
+                o[3 + n] = prev ? prev[s * m + n * N + v] : 0.0;
+            }
+            o[6] = o[7] = 0.0;
+        }
+}
+
+/* one periodic 3x3x3 convolution of one shot: y[v][co] = b + sum W x[v+d] */
+static void cnn_conv(int32_t L, int64_t N, const double* x, int cin, const double* W,
+                     const double* b, int cout, double* y) {
+    for (int64_t v = 0; v < N; ++v)
+        for (int co = 0; co < cout; ++co) {
+            double acc = b[co];
+            for (int d = 0; d < 27; ++d) {
+                const double* xn = x + cnn_nbr(L, v, d) * cin;
+                for (int ci = 0; ci < cin; ++ci) acc += W[(d * cin + ci) * cout + co] * xn[ci];
+            }
+            y[v * cout + co] = acc;
+        }
+}
+
+/* Layer buffers of one shot: h[0] = input, h[l] = post-activation of layer l
+ * (layers 1-3), h[4] = logits. */
+static void cnn_forward_shot(int32_t L, int64_t N, const double* x0, const double* params,
+                             double* h[TCO_CNN_LAYERS + 1]) {
+    const double* p = params;
+    for (int64_t i = 0; i < N * 8; ++i) h[0][i] = x0[i];
+    for (int l = 0; l < TCO_CNN_LAYERS; ++l) {
+        const int cin = kCnnCh[l], cout = kCnnCh[l + 1];
+        const double* W = p;
+        const double* b = p + 27 * cin * cout;
+        cnn_conv(L, N, h[l], cin, W, b, cout, h[l + 1]);
+        if (l + 1 < TCO_CNN_LAYERS)
+            for (int64_t i = 0; i < N * cout; ++i)
+                if (h[l + 1][i] < 0.0) h[l + 1][i] = 0.0;
+        p = b + cout;
+    }
+}
+
+void tco_cnn_forward(const tco_lattice* lat, int64_t n_shots, const double* x0,
+                     const double* params, double* z, double* acts) {
+    const int32_t L = lat->L;
+    const int64_t N = lat->n_sites;
+    double* h[TCO_CNN_LAYERS + 1];
+    for (int l = 0; l <= TCO_CNN_LAYERS; ++l) h[l] = (double*)malloc(sizeof(double) * N * 32);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        cnn_forward_shot(L, N, x0 + s * N * 8, params, h);
+        memcpy(z + s * N * 3, h[TCO_CNN_LAYERS], sizeof(double) * N * 3);
+        if (acts)
+            for (int l = 1; l < TCO_CNN_LAYERS; ++l)
+                memcpy(acts + ((int64_t)(l - 1) * n_shots + s) * N * 32, h[l],
+                       sizeof(double) * N * 32);
+    }
+    for (int l = 0; l <= TCO_CNN_LAYERS; ++l) free(h[l]);
+}
+
+/* Binary cross-entropy with logits averaged over every edge of every shot,
+ * and its gradient by the chain rule through the four layers. */
+double tco_cnn_loss_grad(const tco_lattice* lat, int64_t n_shots, const double* x0,
+                         const double* params, const uint8_t* target, double* grad) {
+    const int32_t L = lat->L;
+    const int64_t N = lat->n_sites, n_edges = lat->n_edges;
+    const double count = (double)n_shots * (double)n_edges;
+    double* h[TCO_CNN_LAYERS + 1];
+    for (int l = 0; l <= TCO_CNN_LAYERS; ++l) h[l] = (double*)malloc(sizeof(double) * N * 32);
+    double* dy = (double*)malloc(sizeof(double) * N * 32);  /* d loss / d pre-activation */
+    double* dx = (double*)malloc(sizeof(double) * N * 32);  /* d loss / d layer input    */
+    const int64_t P = tco_cnn_param_count();
+    for (int64_t i = 0; i < P; ++i) grad[i] = 0.0;
+    /* parameter offsets of each layer */
+    int64_t off[TCO_CNN_LAYERS];
+    {
+        int64_t o = 0;
+        for (int l = 0; l < TCO_CNN_LAYERS; ++l) {
+            off[l] = o;
+            o += 27 * kCnnCh[l] * kCnnCh[l + 1] + kCnnCh[l + 1];
+        }
+    }
+    double loss = 0.0;
+    for (int64_t s = 0; s < n_shots; ++s) {
+        cnn_forward_shot(L, N, x0 + s * N * 8, params, h);
+        const uint8_t* t = target + s * n_edges;
+        for (int64_t v = 0; v < N; ++v)
+            for (int c = 0; c < 3; ++c) {
+                const double zz = h[TCO_CNN_LAYERS][v * 3 + c];
+                const double tt = t[(int64_t)c * N + v];
+                const double softplus = (zz > 0 ? zz : 0.0) + log1p(exp(-fabs(zz)));
+                loss += softplus - tt * zz;
+                dy[v * 3 + c] = (1.0 / (1.0 + exp(-zz)) - tt) / count;
+            }
+        for (int l = TCO_CNN_LAYERS - 1; l >= 0; --l) {
+            const int cin = kCnnCh[l], cout = kCnnCh[l + 1];
+            const double* W = params + off[l];
+            double* gW = grad + off[l];
+            double* gb = gW + 27 * cin * cout;
+            /* weights and bias */
+            for (int64_t v = 0; v < N; ++v)
+                for (int co = 0; co < cout; ++co) {
+                    const double g = dy[v * cout + co];
+                    if (g == 0.0) continue;
+                    gb[co] += g;
+                    for (int d = 0; d < 27; ++d) {
+                        const double* xn = h[l] + cnn_nbr(L, v, d) * cin;
+                        for (int ci = 0; ci < cin; ++ci) gW[(d * cin + ci) * cout + co] += g * xn[ci];
+                    }
+                }
+            if (l == 0) break;
+            /* input of this layer: x[u] feeds y[v] for u = v + d */
+            for (int64_t i = 0; i < N * cin; ++i) dx[i] = 0.0;
+            for (int64_t v = 0; v < N; ++v)
+                for (int d = 0; d < 27; ++d) {
+                    const int64_t u = cnn_nbr(L, v, d);
+                    for (int ci = 0; ci < cin; ++ci) {
+                        double acc = 0.0;
+                        for (int co = 0; co < cout; ++co)
+                            acc += W[(d * cin + ci) * cout + co] * dy[v * cout + co];
+                        dx[u * cin + ci] += acc;
+                    }
+                }
+            /* through the ReLU of the previous layer */
+            for (int64_t i = 0; i < N * cin; ++i) dy[i] = h[l][i] > 0.0 ? dx[i] : 0.0;
+        }
+    }
+    for (int l = 0; l <= TCO_CNN_LAYERS; ++l) free(h[l]);
+    free(dy);
+    free(dx);
+    return loss / count;
+}

@@ -106,6 +106,35 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
                     int64_t n_shots, uint8_t* err, uint8_t* mask, int32_t* odd,
                     uint8_t* trace);
 
+/* ------------------------------------------------------------------ CNN prior
+ * A learned per-edge prior for BP (not part of the paper's method): a
+ * translation-invariant periodic 3D CNN, four 3x3x3 convolutions with
+ * channels 8 -> 32 -> 32 -> 32 -> 3 and ReLU between them.
+ *   input  x0[s][v][8]: channels 0-2 the measured syndrome bits of faces
+ *          f(v,0..2) this cycle, 3-5 the working-syndrome bits those faces
+ *          kept at the end of the previous cycle, 6-7 zero;
+ *   layer  y[v][co] = b[co] + sum over offsets d in {-1,0,1}^3 and ci of
+ *          W[d][ci][co] x[v + d][ci] (coordinates mod L), offset index
+ *          d = (dz+1)*9 + (dy+1)*3 + (dx+1);
+ *   output z[s][v][c] = logit of an error on edge e(v,c); the BP prior is
+ *          llr0 = -z;
+ *   loss   mean over all edges of softplus(z) - t z (binary cross-entropy
+ *          with the true error bit t).
+ * Parameters (FP64 here): for l = 1..4, W_l [27][cin][cout] then b_l [cout]. */
+#define TCO_CNN_LAYERS 4
+int64_t tco_cnn_param_count(void);
+/* x0 from syndrome bit arrays [S][3N] of this cycle and of the previous one. */
+void tco_cnn_input(const tco_lattice* lat, int64_t n_shots, const uint8_t* syn,
+                   const uint8_t* prev, double* x0);
+/* z [S][N][3]; acts (NULL ok) receives the post-ReLU activations of layers
+ * 1-3, each [S][N][32], concatenated. */
+void tco_cnn_forward(const tco_lattice* lat, int64_t n_shots, const double* x0,
+                     const double* params, double* z, double* acts);
+/* Loss and its gradient with respect to every parameter; target [S][3N]
+ * (edge bits, edge index c*N + v). */
+double tco_cnn_loss_grad(const tco_lattice* lat, int64_t n_shots, const double* x0,
+                         const double* params, const uint8_t* target, double* grad);
+
 #ifdef __cplusplus
 }
 #endif
