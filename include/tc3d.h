@@ -200,7 +200,8 @@ enum {
     TC3D_K_SWEEP = 5,     /* flip / p-flip decision pass                    */
     TC3D_K_APPLY = 6,     /* plane XOR / clear                               */
     TC3D_K_READOUT = 7,   /* majority vote                                   */
-    TC3D_K_COUNT = 8
+    TC3D_K_CNN = 8,       /* CNN prior (input packing, convolutions)         */
+    TC3D_K_COUNT = 9
 };
 
 typedef struct {
@@ -214,6 +215,51 @@ typedef struct {
 int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
                           uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
                           size_t ws_bytes, void* stream, tc3d_timing* timing);
+
+/* ------------------------------------------------------------- CNN prior
+ * A learned per-edge prior for BP (an addition to the paper's method, whose
+ * BP starts from the channel prior ln((1-p)/p)): a translation-invariant
+ * periodic 3D CNN of four 3x3x3 convolutions, channels 8 -> 32 -> 32 -> 32 ->
+ * 3, ReLU between them, BF16 weights and activations, FP32 accumulation.
+ *   input of site v: the measured syndrome bits of faces f(v,0..2) this
+ *     cycle and the working-syndrome bits those faces kept at the end of the
+ *     previous cycle (zero in the first cycle);
+ *   layer: y[v][co] = b[co] + sum_{d, ci} W[d][ci][co] x[v + off(d)][ci] with
+ *     off(d) = (d%3 - 1, d/3%3 - 1, d/9 - 1), coordinates mod L;
+ *   output: z[v][c] = logit of an error on edge e(v,c); llr0 = -z.
+ * Parameters are an FP32 vector of tc3d_cnn_param_count() floats: for each
+ * layer W [27][cin][cout] then b [cout]. The kernels read a packed BF16 copy
+ * (tc3d_cnn_packed_bytes(), made by tc3d_cnn_pack). */
+int64_t tc3d_cnn_param_count(void);
+size_t tc3d_cnn_packed_bytes(void);
+int tc3d_cnn_pack(const float* params, void* packed, void* stream);
+/* Scratch of one pass over n_shots shots (training != 0: forward + backward). */
+size_t tc3d_cnn_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots, int32_t training);
+/* llr_out [W][3L^3][64] = -z for the shots of the face planes syn and prev
+ * ([3L^3][W], prev NULL = zeros). */
+int tc3d_cnn_forward(const tc3d_lattice* lat, const uint64_t* syn, const uint64_t* prev,
+                     int64_t n_shots, const void* packed, float* llr_out, void* ws,
+                     size_t ws_bytes, void* stream);
+/* Mean binary cross-entropy of the logits against the error bits of the
+ * edge plane `target`, its gradient grad [param_count] (FP32) and the mean
+ * loss (*loss, one device float). Every shot of the 64 W covered counts. */
+int tc3d_cnn_loss_grad(const tc3d_lattice* lat, const uint64_t* syn, const uint64_t* prev,
+                       const uint64_t* target, int64_t n_shots, const void* packed,
+                       float* llr_out, float* grad, float* loss, void* ws, size_t ws_bytes,
+                       void* stream);
+/* One Adam step (step >= 1) on params with moment buffers m, v, then repack. */
+int tc3d_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void* packed, void* stream);
+/* tc3d_run_cycles with the BP prior of every cycle taken from the CNN
+ * (llr0 = -z of that cycle's syndromes) instead of ln((1-p_dec)/p_dec). */
+size_t tc3d_run_cnn_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);
+int tc3d_run_cycles_cnn(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
+                        uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
+                        size_t ws_bytes, void* stream);
+int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
+                              const void* packed, uint64_t* err_state, uint8_t* mask_out,
+                              int32_t* odd_out, void* ws, size_t ws_bytes, void* stream,
+                              tc3d_timing* timing);
 
 /* Human-readable text of a return code. */
 const char* tc3d_strerror(int code);

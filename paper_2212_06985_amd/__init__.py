@@ -25,7 +25,7 @@ __all__ = [
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtc3d.so")
 
 KERNEL_CLASSES = ["bp_iter", "bp_first", "bp_post", "noise", "syndrome", "sweep", "apply",
-                  "readout"]
+                  "readout", "cnn"]
 
 
 class Tc3dError(RuntimeError):
@@ -52,7 +52,7 @@ class RunParams(ctypes.Structure):
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
+    _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9),
                 ("total_ms", ctypes.c_double)]
 
     def as_dict(self):
@@ -92,6 +92,17 @@ def lib():
         "tc3d_run_cycles_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp,
                                                  ctypes.POINTER(Timing)]),
         "tc3d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "tc3d_cnn_param_count": (i64, []),
+        "tc3d_cnn_packed_bytes": (sz, []),
+        "tc3d_cnn_pack": (ctypes.c_int, [vp, vp, vp]),
+        "tc3d_cnn_workspace_bytes": (sz, [lat, i64, i32]),
+        "tc3d_cnn_forward": (ctypes.c_int, [lat, vp, vp, i64, vp, vp, vp, sz, vp]),
+        "tc3d_cnn_loss_grad": (ctypes.c_int, [lat, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]),
+        "tc3d_cnn_adam": (ctypes.c_int, [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]),
+        "tc3d_run_cnn_workspace_bytes": (sz, [lat, prm]),
+        "tc3d_run_cycles_cnn": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, vp, sz, vp]),
+        "tc3d_run_cycles_cnn_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, vp, sz, vp,
+                                                     ctypes.POINTER(Timing)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -215,6 +226,76 @@ def run_cycles_timed(lat, prm: RunParams, err_state, mask_out, odd_out, ws,
                                        ws.numel() * ws.element_size(), _stream(stream),
                                        ctypes.byref(t)), "run_cycles_timed")
     return t
+
+
+# ------------------------------------------------------------------ CNN prior
+def cnn_param_count() -> int:
+    return int(lib().tc3d_cnn_param_count())
+
+
+def cnn_packed_bytes() -> int:
+    return int(lib().tc3d_cnn_packed_bytes())
+
+
+def cnn_pack(params, packed, stream=None):
+    _check(lib().tc3d_cnn_pack(_ptr(params), _ptr(packed), _stream(stream)), "cnn_pack")
+
+
+def cnn_workspace_bytes(lat, n_shots, training=False) -> int:
+    n = int(lib().tc3d_cnn_workspace_bytes(ctypes.byref(lat), int(n_shots), 1 if training else 0))
+    if n == 0:
+        raise Tc3dError("cnn_workspace_bytes: invalid lattice or shot count")
+    return n
+
+
+def cnn_forward(lat, syn, prev, n_shots, packed, llr_out, ws, stream=None):
+    _check(lib().tc3d_cnn_forward(ctypes.byref(lat), _ptr(syn), _ptr(prev), int(n_shots),
+                                  _ptr(packed), _ptr(llr_out), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)), "cnn_forward")
+
+
+def cnn_loss_grad(lat, syn, prev, target, n_shots, packed, llr_out, grad, loss, ws, stream=None):
+    _check(lib().tc3d_cnn_loss_grad(ctypes.byref(lat), _ptr(syn), _ptr(prev), _ptr(target),
+                                    int(n_shots), _ptr(packed), _ptr(llr_out), _ptr(grad),
+                                    _ptr(loss), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _stream(stream)), "cnn_loss_grad")
+
+
+def cnn_adam(params, grad, m, v, step, lr, packed, beta1=0.9, beta2=0.999, eps=1e-8,
+             stream=None):
+    _check(lib().tc3d_cnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                               float(lr), float(beta1), float(beta2), float(eps), _ptr(packed),
+                               _stream(stream)), "cnn_adam")
+
+
+def run_cnn_workspace_bytes(lat, prm: RunParams) -> int:
+    n = int(lib().tc3d_run_cnn_workspace_bytes(ctypes.byref(lat), ctypes.byref(prm)))
+    if n == 0:
+        raise Tc3dError("run_cnn_workspace_bytes: invalid lattice or parameters")
+    return n
+
+
+def run_cycles_cnn(lat, prm: RunParams, packed, err_state, mask_out, odd_out, ws, stream=None):
+    _check(lib().tc3d_run_cycles_cnn(ctypes.byref(lat), ctypes.byref(prm), _ptr(packed),
+                                     _ptr(err_state), _ptr(mask_out), _ptr(odd_out), _ptr(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)),
+           "run_cycles_cnn")
+
+
+def run_cycles_cnn_timed(lat, prm: RunParams, packed, err_state, mask_out, odd_out, ws,
+                         stream=None) -> Timing:
+    t = Timing()
+    _check(lib().tc3d_run_cycles_cnn_timed(ctypes.byref(lat), ctypes.byref(prm), _ptr(packed),
+                                           _ptr(err_state), _ptr(mask_out), _ptr(odd_out),
+                                           _ptr(ws), ws.numel() * ws.element_size(),
+                                           _stream(stream), ctypes.byref(t)),
+           "run_cycles_cnn_timed")
+    return t
+
+
+__all__ += ["cnn_param_count", "cnn_packed_bytes", "cnn_pack", "cnn_workspace_bytes",
+            "cnn_forward", "cnn_loss_grad", "cnn_adam", "run_cnn_workspace_bytes",
+            "run_cycles_cnn", "run_cycles_cnn_timed"]
 
 
 def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,

@@ -194,35 +194,56 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
     return TC3D_OK;
 }
 
-// Words decoded together.
-int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm) {
-    const int64_t W = words_of(prm->n_shots);
-    if (W == 0) return 0;
-    if (prm->batch_shots > 0) return std::min<int64_t>(W, prm->batch_shots / 64);
-    const size_t per_word = 3 * plane_bytes(lat, 1) +
-                            (prm->bp_iters > 0 ? 2 * nu_bytes(lat, 64) : 0);
-    const size_t budget = (size_t)24 << 30;
-    return std::max<int64_t>(1, std::min<int64_t>(W, (int64_t)(budget / per_word)));
+size_t llr_bytes(const tc3d_lattice* lat, int64_t nw) {
+    return round_up((size_t)nw * 64 * (size_t)lat->n_edges * 4, 256);
 }
 
-size_t run_ws_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t* nb_out) {
-    const int64_t nb = batch_words(lat, prm);
+// Words decoded together. With the CNN prior a batch also holds the CNN's
+// activations and its rows (64 words N) must stay below 2^31.
+int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cnn) {
+    const int64_t W = words_of(prm->n_shots);
+    if (W == 0) return 0;
+    int64_t nb;
+    if (prm->batch_shots > 0) {
+        nb = std::min<int64_t>(W, prm->batch_shots / 64);
+    } else {
+        size_t per_word = (cnn ? 4 : 3) * plane_bytes(lat, 1) +
+                          (prm->bp_iters > 0 ? 2 * nu_bytes(lat, 64) : 0);
+        if (cnn) per_word += llr_bytes(lat, 1) + cnn_workspace_bytes(64 * lat->n_sites, 0);
+        const size_t budget = (size_t)24 << 30;
+        nb = std::max<int64_t>(1, std::min<int64_t>(W, (int64_t)(budget / per_word)));
+    }
+    if (cnn) nb = std::min<int64_t>(nb, std::max<int64_t>(1, 0x7fffffffLL / (64 * lat->n_sites)));
+    return nb;
+}
+
+size_t run_ws_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t* nb_out,
+                    bool cnn) {
+    const int64_t nb = batch_words(lat, prm, cnn);
     if (nb_out) *nb_out = nb;
     if (nb == 0) return 256;
     size_t b = 3 * plane_bytes(lat, nb);  // syn, corr, flips
     if (prm->bp_iters > 0) b += 2 * nu_bytes(lat, 64 * nb);
+    if (cnn)  // previous working syndrome, priors, CNN activations
+        b += plane_bytes(lat, nb) + llr_bytes(lat, nb) +
+             round_up(cnn_workspace_bytes(64 * nb * lat->n_sites, 0), 256);
     return b;
 }
 
-int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
-             uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes, const Ctx& c) {
+// packed == nullptr: the paper's BP prior; else the CNN prior every cycle.
+int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
+             uint64_t* err, uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes,
+             const Ctx& c) {
     int rc = check_run(lat, prm);
     if (rc) return rc;
+    const bool cnn = packed != nullptr;
+    if (cnn && prm->bp_iters <= 0) return TC3D_EINVAL;
     if (prm->n_shots == 0) return TC3D_OK;
     if (!err || !mask) return TC3D_EINVAL;
-    if (!aligned(err, 8) || (odd && !aligned(odd, 4))) return TC3D_EALIGN;
+    if (!aligned(err, 8) || (odd && !aligned(odd, 4)) || (cnn && !aligned(packed, 256)))
+        return TC3D_EALIGN;
     int64_t nb = 0;
-    const size_t need = run_ws_bytes(lat, prm, &nb);
+    const size_t need = run_ws_bytes(lat, prm, &nb, cnn);
     if (!ws || ws_bytes < need) return TC3D_EWORKSPACE;
     if (!aligned(ws, 256)) return TC3D_EALIGN;
     const Geo g = geo_of(lat);
@@ -234,9 +255,21 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
     uint64_t* flips = (uint64_t*)(base + 2 * plane_bytes(lat, nb));
     float* nu0 = nullptr;
     float* nu1 = nullptr;
+    char* next = base + 3 * plane_bytes(lat, nb);
     if (prm->bp_iters > 0) {
-        nu0 = (float*)(base + 3 * plane_bytes(lat, nb));
-        nu1 = (float*)((char*)nu0 + nu_bytes(lat, 64 * nb));
+        nu0 = (float*)next;
+        nu1 = (float*)(next + nu_bytes(lat, 64 * nb));
+        next += 2 * nu_bytes(lat, 64 * nb);
+    }
+    uint64_t* prev = nullptr;
+    float* llr = nullptr;
+    void* cnn_ws = nullptr;
+    if (cnn) {
+        prev = (uint64_t*)next;
+        next += plane_bytes(lat, nb);
+        llr = (float*)next;
+        next += llr_bytes(lat, nb);
+        cnn_ws = next;
     }
     const int32_t cycles = prm->noisy_cycles + prm->perfect_final;
     const uint32_t th_p = threshold_of(prm->p), th_q = threshold_of(prm->q);
@@ -255,7 +288,11 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
             if ((rc = launch_syndrome(c, g, cE, S, bw, 0, tq, gword0, (uint32_t)t, prm->seed)))
                 return rc;
             if (prm->bp_iters > 0) {
-                const BpArgs a = make_bp_args(cS, nullptr, l0, K, bw, prm->bp_tile);
+                if (cnn &&
+                    (rc = cnn_forward(c, g, syn, t == 0 ? nullptr : prev, bw, 64 * bw * g.N,
+                                      packed, llr, cnn_ws)))
+                    return rc;
+                const BpArgs a = make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw, prm->bp_tile);
                 if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
                 if ((rc = launch_syndrome(c, g, cC, S, bw, 1, 0u, 0, 0, 0))) return rc;
             } else {
@@ -268,6 +305,7 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
                     return rc;
                 if ((rc = launch_syndrome(c, g, cF, S, bw, 1, 0u, 0, 0, 0))) return rc;
             }
+            if (cnn && (rc = copy_plane(c, Plane{prev, bw}, cS, rows, bw))) return rc;
             if ((rc = launch_xor(c, E, cC, rows, bw))) return rc;
         }
         const int64_t shots_b = std::min<int64_t>(64 * bw, prm->n_shots - 64 * w0);
@@ -421,14 +459,14 @@ int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_s
 
 size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm) {
     if (check_run(lat, prm)) return 0;
-    return run_ws_bytes(lat, prm, nullptr);
+    return run_ws_bytes(lat, prm, nullptr, false);
 }
 
 int tc3d_run_cycles(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err_state,
                     uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
                     void* stream) {
     const Ctx c{(hipStream_t)stream, nullptr};
-    return run_impl(lat, prm, err_state, mask_out, odd_out, ws, ws_bytes, c);
+    return run_impl(lat, prm, nullptr, err_state, mask_out, odd_out, ws, ws_bytes, c);
 }
 
 int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
@@ -437,7 +475,105 @@ int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
     if (!timing) return TC3D_EINVAL;
     Timer tm((hipStream_t)stream);
     const Ctx c{(hipStream_t)stream, &tm};
-    int rc = run_impl(lat, prm, err_state, mask_out, odd_out, ws, ws_bytes, c);
+    int rc = run_impl(lat, prm, nullptr, err_state, mask_out, odd_out, ws, ws_bytes, c);
+    int rc2 = tm.finish(timing);
+    return rc ? rc : rc2;
+}
+
+// ------------------------------------------------------------------ CNN prior
+int64_t tc3d_cnn_param_count(void) { return cnn_param_count(); }
+
+size_t tc3d_cnn_packed_bytes(void) { return cnn_packed_bytes(); }
+
+int tc3d_cnn_pack(const float* params, void* packed, void* stream) {
+    if (!params || !packed) return TC3D_EINVAL;
+    if (!aligned(params, 4) || !aligned(packed, 256)) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return cnn_pack(c, params, packed);
+}
+
+static int64_t cnn_rows(const tc3d_lattice* lat, int64_t n_shots) {
+    const int64_t R = 64 * words_of(n_shots) * lat->n_sites;
+    return R < 0x7fffffffLL ? R : -1;
+}
+
+size_t tc3d_cnn_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots, int32_t training) {
+    if (!lattice_ok(lat) || n_shots <= 0) return 0;
+    const int64_t R = cnn_rows(lat, n_shots);
+    if (R < 0) return 0;
+    return cnn_workspace_bytes(R, training ? 1 : 0);
+}
+
+static int cnn_common_checks(const tc3d_lattice* lat, const uint64_t* syn, const uint64_t* prev,
+                             int64_t n_shots, const void* packed, const float* llr, void* ws,
+                             size_t ws_bytes, int training) {
+    if (!lattice_ok(lat) || n_shots <= 0 || !syn || !packed || !llr) return TC3D_EINVAL;
+    if (!aligned(syn, 8) || (prev && !aligned(prev, 8)) || !aligned(packed, 256) ||
+        !aligned(llr, 4))
+        return TC3D_EALIGN;
+    const int64_t R = cnn_rows(lat, n_shots);
+    if (R < 0) return TC3D_EINVAL;
+    if (!ws || ws_bytes < cnn_workspace_bytes(R, training)) return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
+    return TC3D_OK;
+}
+
+int tc3d_cnn_forward(const tc3d_lattice* lat, const uint64_t* syn, const uint64_t* prev,
+                     int64_t n_shots, const void* packed, float* llr_out, void* ws,
+                     size_t ws_bytes, void* stream) {
+    int rc = cnn_common_checks(lat, syn, prev, n_shots, packed, llr_out, ws, ws_bytes, 0);
+    if (rc) return rc;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return cnn_forward(c, geo_of(lat), syn, prev, words_of(n_shots), cnn_rows(lat, n_shots),
+                       packed, llr_out, ws);
+}
+
+int tc3d_cnn_loss_grad(const tc3d_lattice* lat, const uint64_t* syn, const uint64_t* prev,
+                       const uint64_t* target, int64_t n_shots, const void* packed,
+                       float* llr_out, float* grad, float* loss, void* ws, size_t ws_bytes,
+                       void* stream) {
+    int rc = cnn_common_checks(lat, syn, prev, n_shots, packed, llr_out, ws, ws_bytes, 1);
+    if (rc) return rc;
+    if (!target || !grad || !loss) return TC3D_EINVAL;
+    if (!aligned(target, 8) || !aligned(grad, 4) || !aligned(loss, 4)) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return cnn_loss_grad(c, geo_of(lat), syn, prev, target, words_of(n_shots),
+                         cnn_rows(lat, n_shots), packed, llr_out, grad, loss, ws);
+}
+
+int tc3d_cnn_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void* packed, void* stream) {
+    if (!params || !grad || !m || !v || !packed || step < 1 || !(lr > 0.f) ||
+        !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return TC3D_EINVAL;
+    if (!aligned(params, 4) || !aligned(grad, 4) || !aligned(m, 4) || !aligned(v, 4) ||
+        !aligned(packed, 256))
+        return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return cnn_adam(c, params, grad, m, v, step, lr, beta1, beta2, eps, packed);
+}
+
+size_t tc3d_run_cnn_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm) {
+    if (check_run(lat, prm) || prm->bp_iters <= 0) return 0;
+    return run_ws_bytes(lat, prm, nullptr, true);
+}
+
+int tc3d_run_cycles_cnn(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
+                        uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!packed) return TC3D_EINVAL;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return run_impl(lat, prm, packed, err_state, mask_out, odd_out, ws, ws_bytes, c);
+}
+
+int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
+                              const void* packed, uint64_t* err_state, uint8_t* mask_out,
+                              int32_t* odd_out, void* ws, size_t ws_bytes, void* stream,
+                              tc3d_timing* timing) {
+    if (!packed || !timing) return TC3D_EINVAL;
+    Timer tm((hipStream_t)stream);
+    const Ctx c{(hipStream_t)stream, &tm};
+    int rc = run_impl(lat, prm, packed, err_state, mask_out, odd_out, ws, ws_bytes, c);
     int rc2 = tm.finish(timing);
     return rc ? rc : rc2;
 }

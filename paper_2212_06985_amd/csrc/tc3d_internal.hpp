@@ -101,6 +101,21 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
                    float* post);
 
+// ----------------------------------------------------------------- CNN prior
+int64_t cnn_param_count();
+size_t cnn_packed_bytes();
+size_t cnn_workspace_bytes(int64_t rows, int training);
+int cnn_pack(const Ctx& c, const float* params, void* packed);
+// llr [W][3N][64] = -CNN(syn, prev) for R = 64 W N rows; prev may be null.
+int cnn_forward(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev, int64_t ld,
+                int64_t rows, const void* packed, float* llr, void* ws);
+int cnn_loss_grad(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev,
+                  const uint64_t* target, int64_t ld, int64_t rows, const void* packed,
+                  float* llr, float* grad, float* loss, void* ws);
+int cnn_adam(const Ctx& c, float* params, const float* grad, float* m, float* v, int step,
+             float lr, float b1, float b2, float eps, void* packed);
+int copy_plane(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw);
+
 // Wrappers around hipGetLastError / timers for the launchers.
 int after_launch(const Ctx& c);
 int before_launch(const Ctx& c, int kclass);

@@ -1,0 +1,232 @@
+"""GPU parity of the CNN prior against the oracle (same BF16-rounded weights;
+the GPU also stores activations and gradients in BF16, the oracle keeps
+everything in FP64), its training step, and its use as the BP prior."""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import paper_2212_06985_amd as tc
+from gpu_util import announce, bits_of_dev, dev_plane_of_bits, to_dev
+from oracle.oracle import CNN_CHANNELS, Oracle, cnn_layers, cnn_param_count
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need an MI355X"
+    tc.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def bf16_round(x):
+    """Round FP32 values to the nearest BF16 (ties to even), returned as FP32."""
+    a = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    a = (a + 0x7FFF + ((a >> 16) & 1)) & 0xFFFF0000
+    return a.astype(np.uint32).view(np.float32)
+
+
+def random_params(seed, gain=1.0):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(cnn_param_count(), np.float32)
+    for W, b in cnn_layers(p):
+        fan_in = W.shape[0] * W.shape[1]
+        W[...] = rng.normal(0, gain * math.sqrt(2.0 / fan_in), W.shape)
+        b[...] = rng.normal(0, 0.05, b.shape)
+    return p
+
+
+def oracle_params(p32):
+    """FP64 parameters the GPU actually uses: BF16 weights, FP32 biases."""
+    out = p32.astype(np.float64).copy()
+    for W, _ in cnn_layers(out):
+        W[...] = bf16_round(W.astype(np.float32)).astype(np.float64)
+    return out
+
+
+def packed_of(p32):
+    import torch
+    d = to_dev(p32)
+    packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
+    tc.cnn_pack(d, packed)
+    return d, packed
+
+
+def z_from_llr(llr, L, S):
+    N = L ** 3
+    rows = inputs.rows_from_gpu(llr.cpu().numpy(), 3 * N)[:S]  # [S][3N], e = c*N + v
+    return -rows.reshape(S, 3, N).transpose(0, 2, 1).astype(np.float64)
+
+
+@pytest.mark.parametrize("L,S", [(3, 64), (4, 100), (6, 64)])
+def test_forward_parity(L, S):
+    import torch
+    announce(f"cnn forward L={L} S={S}")
+    o = Oracle(L)
+    lat = tc.make_lattice(L)
+    W = inputs.n_words(S)
+    full = 64 * W
+    syn = inputs.random_bits(20 + L, full, o.n_faces, 0.3)
+    prev = inputs.random_bits(30 + L, full, o.n_faces, 0.2)
+    p32 = random_params(L)
+    _, packed = packed_of(p32)
+    llr = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
+    ws = tc.alloc_workspace(tc.cnn_workspace_bytes(lat, S))
+    tc.cnn_forward(lat, dev_plane_of_bits(syn), dev_plane_of_bits(prev), S, packed, llr, ws)
+    sync()
+    z_g = z_from_llr(llr, L, full)
+    z_o = o.cnn_forward(o.cnn_input(syn, prev), oracle_params(p32))
+    err = np.abs(z_g - z_o)
+    rel = np.linalg.norm(err) / np.linalg.norm(z_o)
+    announce(f"  relative L2 error {rel:.2e}, max abs {err.max():.3e} (|z| max {np.abs(z_o).max():.2f})")
+    assert rel < 1e-2
+    assert err.max() < 0.05 * np.abs(z_o).max()
+    # first cycle: no previous syndrome
+    tc.cnn_forward(lat, dev_plane_of_bits(syn), None, S, packed, llr, ws)
+    sync()
+    z_o0 = o.cnn_forward(o.cnn_input(syn, None), oracle_params(p32))
+    assert np.linalg.norm(z_from_llr(llr, L, full) - z_o0) / np.linalg.norm(z_o0) < 1e-2
+
+
+@pytest.mark.parametrize("L,S", [(3, 64), (4, 128)])
+def test_gradient_parity(L, S):
+    import torch
+    announce(f"cnn gradient L={L} S={S}")
+    o = Oracle(L)
+    lat = tc.make_lattice(L)
+    W = inputs.n_words(S)
+    full = 64 * W
+    syn = inputs.random_bits(40 + L, full, o.n_faces, 0.3)
+    prev = inputs.random_bits(50 + L, full, o.n_faces, 0.2)
+    target = inputs.random_bits(60 + L, full, o.n_edges, 0.15)
+    p32 = random_params(70 + L)
+    _, packed = packed_of(p32)
+    llr = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
+    grad = torch.zeros(cnn_param_count(), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = tc.alloc_workspace(tc.cnn_workspace_bytes(lat, S, training=True))
+    tc.cnn_loss_grad(lat, dev_plane_of_bits(syn), dev_plane_of_bits(prev),
+                     dev_plane_of_bits(target), S, packed, llr, grad, loss, ws)
+    sync()
+    loss_o, grad_o = o.cnn_loss_grad(o.cnn_input(syn, prev), oracle_params(p32), target)
+    g = grad.cpu().numpy().astype(np.float64)
+    announce(f"  loss gpu {float(loss.item()):.6f} oracle {loss_o:.6f}")
+    assert abs(float(loss.item()) - loss_o) < 5e-3 * loss_o
+    for l, ((Wg, bg), (Wo, bo)) in enumerate(zip(cnn_layers(g), cnn_layers(grad_o))):
+        for name, a, b in (("W", Wg, Wo), ("b", bg, bo)):
+            a, b = a.ravel(), b.ravel()
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300)
+            rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-300)
+            announce(f"  layer {l + 1} d{name}: cosine {cos:.6f} relative L2 {rel:.2e}")
+            assert cos > 0.999 and rel < 5e-2, (l, name, cos, rel)
+
+
+def test_training_lowers_the_loss():
+    import torch
+    L, S = 4, 256
+    o = Oracle(L)
+    lat = tc.make_lattice(L)
+    W = inputs.n_words(S)
+    # target: the error bits; inputs: their syndrome, so the task is learnable
+    err = inputs.random_bits(80, S, o.n_edges, 0.05)
+    syn = o.syndrome(err)
+    d_syn, d_err = dev_plane_of_bits(syn), dev_plane_of_bits(err)
+    p32 = random_params(81, gain=0.5)
+    params, packed = packed_of(p32)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    llr = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
+    grad = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = tc.alloc_workspace(tc.cnn_workspace_bytes(lat, S, training=True))
+    hist = []
+    for step in range(1, 61):
+        tc.cnn_loss_grad(lat, d_syn, None, d_err, S, packed, llr, grad, loss, ws)
+        hist.append(float(loss.item()))
+        tc.cnn_adam(params, grad, m, v, step, 3e-3, packed)
+    sync()
+    announce(f"  loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    assert hist[-1] < 0.5 * hist[0]
+    assert np.all(np.isfinite(params.cpu().numpy()))
+
+
+def _run(L, prm, packed=None):
+    import torch
+    lat = tc.make_lattice(L)
+    S = prm.n_shots
+    err = torch.zeros((lat.n_edges, tc.n_words(S)), dtype=torch.int64, device="cuda")
+    mask = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    odd = torch.zeros((S, 3), dtype=torch.int32, device="cuda")
+    if packed is None:
+        ws = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
+        tc.run_cycles(lat, prm, err, mask, odd, ws)
+    else:
+        ws = tc.alloc_workspace(tc.run_cnn_workspace_bytes(lat, prm))
+        tc.run_cycles_cnn(lat, prm, packed, err, mask, odd, ws)
+    sync()
+    return mask.cpu().numpy(), bits_of_dev(err, S)
+
+
+def test_constant_cnn_prior_reproduces_the_paper_decoder():
+    """All weights zero and output bias -l0: every prior is l0 = ln((1-p)/p)
+    and the CNN-prior run is the paper's p-BP up to FP32 rounding."""
+    L, S, p = 6, 256, 0.05
+    l0 = math.log((1 - p) / p)
+    p32 = np.zeros(cnn_param_count(), np.float32)
+    cnn_layers(p32)[3][1][:] = -l0
+    _, packed = packed_of(p32)
+    prm = tc.make_run_params(p, p, 4, 20, 6, 0b001001, n_shots=S, seed=9)
+    m_a, e_a = _run(L, prm)
+    m_b, e_b = _run(L, prm, packed)
+    same = ((e_a == e_b).all(axis=1) & (m_a == m_b)).sum()
+    announce(f"  identical shots {same}/{S}")
+    assert same >= S - 3
+
+
+def test_cnn_run_equals_composed_stages():
+    """tc3d_run_cycles_cnn equals the same cycle composed from the stage
+    entry points: noise, syndrome, CNN (with the previous working syndrome),
+    BP from the CNN priors, sweeps, carry."""
+    import torch
+    L, S, p, cycles, seed = 5, 128, 0.05, 3, 21
+    lat = tc.make_lattice(L)
+    W = tc.n_words(S)
+    p32 = random_params(22, gain=0.5)
+    _, packed = packed_of(p32)
+    prm = tc.make_run_params(p, p, cycles, 10, 6, 0b001001, n_shots=S, seed=seed,
+                             perfect_final=0)
+    m_run, e_run = _run(L, prm, packed)
+    n = lat.n_edges
+    err = torch.zeros((n, W), dtype=torch.int64, device="cuda")
+    prev = None
+    llr = torch.zeros((W, n, 64), dtype=torch.float32, device="cuda")
+    cws = tc.alloc_workspace(tc.cnn_workspace_bytes(lat, S))
+    bws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, S))
+    sws = tc.alloc_workspace(tc.sweep_workspace_bytes(lat, W))
+    for t in range(cycles):
+        tc.sample_noise(lat, err, 0, p, seed, t, 0, S)
+        syn = torch.zeros_like(err)
+        tc.syndrome(lat, err, syn, W)
+        tc.sample_noise(lat, syn, 1, p, seed, t, 0, S)
+        tc.cnn_forward(lat, syn, prev, S, packed, llr, cws)
+        corr = torch.zeros_like(err)
+        tc.bp_decode(lat, syn, S, llr, 0.0, 1 - 2 * p, 10, corr, None, bws)
+        tc.syndrome(lat, corr, syn, W, xor_into=True)
+        for k in range(6):
+            if (0b001001 >> k) & 1:
+                tc.pflip_sweep(lat, syn, corr, W, seed, t, k, 0, sws)
+            else:
+                tc.flip_sweep(lat, syn, corr, W, sws)
+        prev = syn.clone()
+        err ^= corr
+    sync()
+    assert np.array_equal(bits_of_dev(err, S), e_run)
