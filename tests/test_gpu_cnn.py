@@ -230,3 +230,23 @@ def test_cnn_run_equals_composed_stages():
         err ^= corr
     sync()
     assert np.array_equal(bits_of_dev(err, S), e_run)
+
+
+def test_trained_prior_lowers_the_logical_error_rate():
+    """The committed network (trained by paper_2212_06985_amd.train_cnn at
+    L = 12, p = q = 0.05 on 10^7 simulated snapshots), blended with the channel
+    prior at beta = 0.2, decodes better than the paper's p-BP on the same
+    shots: L = 12, p = q = 0.065, 40 noisy cycles + 1 perfect, 32768 shots."""
+    import os
+    from paper_2212_06985_amd import eval_cnn
+    from paper_2212_06985_amd.train_cnn import blend_prior
+    path = os.path.join(os.path.dirname(tc.__file__), "weights", "cnn_L12_p05.npy")
+    w = np.load(path, allow_pickle=False)
+    assert w.shape == (cnn_param_count(),)
+    base = eval_cnn.run(12, 32768, 0.065, 40, None, seed=777)
+    cnn = eval_cnn.run(12, 32768, 0.065, 40, blend_prior(w, 0.2, 0.065), seed=777)
+    announce(f"  plain LER {base['ler_any']:.4f} residual syndrome {base['mean_residual_syndrome']:.2f}; "
+             f"CNN LER {cnn['ler_any']:.4f} residual syndrome {cnn['mean_residual_syndrome']:.2f}")
+    sig = math.sqrt(base["ler_any_sigma"] ** 2 + cnn["ler_any_sigma"] ** 2)
+    assert base["ler_any"] - cnn["ler_any"] > 3 * sig
+    assert cnn["mean_residual_syndrome"] < base["mean_residual_syndrome"]
