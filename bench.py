@@ -12,7 +12,11 @@ Prints one JSON line with the throughput in decoded qubit-cycles/s (one
 qubit-cycle = one edge x one cycle x one shot), the roofline of the dominant
 kernel, measured live with HIP events, and the oracle timed on the host.
 
-    python bench.py [--workload c5|c2|c1] [--steps K] [--warmup W]
+    python bench.py [--workload c5|c4|c2|c1] [--decoder plain|cnn] [--steps K] [--warmup W]
+
+With --decoder cnn the BP prior comes from the committed CNN (blended with
+the channel prior); with --compare the other decoder also decodes the same
+shots and its throughput and logical error rate are reported beside it.
 """
 from __future__ import annotations
 
@@ -38,6 +42,10 @@ WORKLOADS = {
     # BP 20 + P F F P F F, 10^5 shots per p (one step per p value)
     "c2": dict(L=12, ps=[0.04, 0.05, 0.055, 0.06], noisy=12, bp=20, sweeps=6, mask=0b001001,
                sched="PFFPFF", shots=100_032, steps=4, warmup=1),
+    # CNN prior vs plain: L = 24 (41,472 qubits), p = q = 0.05, 24 + 1 cycles,
+    # BP 20 + P F F P F F, 10^5 shots (5 steps of 20,032), both decoders on the same shots
+    "c4": dict(L=24, ps=[0.05], noisy=24, bp=20, sweeps=6, mask=0b001001,
+               sched="PFFPFF", shots=20_032, steps=5, warmup=1, decoder="cnn", compare=True),
     # L = 6 (648 qubits), p = q = 0.02, 6 + 1 cycles, flip + p-flip F F P F F,
     # no BP, 10^4 shots
     "c1": dict(L=6, ps=[0.02], noisy=6, bp=0, sweeps=5, mask=0b00100, sched="FFPFF",
@@ -57,6 +65,15 @@ ALGO_BYTES = {
     "apply": (24.0, "edge-word"),
     "readout": (8.0, "edge-word"),
 }
+
+# The CNN prior's forward pass: 4 periodic 3x3x3 convolutions 8 -> 32 -> 32 -> 32
+# -> 3 channels, 27 (8*32 + 32*32 + 32*32 + 32*3) multiply-adds per site of a shot.
+# One forward is 5 launches (input assembly + 4 layers); the class average
+# launch carries a fifth of a forward.
+CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
+CNN_LAUNCHES_PER_FORWARD = 5
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_p05.npy")
 
 
 def log(msg):
@@ -141,17 +158,145 @@ def copy_calibration(nbytes: int, reps: int):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
+def cnn_packed(p: float, beta: float, weights: str):
+    """Device copy of the committed network, blended with the channel prior at
+    strength beta, in the library's packed BF16 layout."""
+    import numpy as np
+    import torch
+
+    import paper_2212_06985_amd as tc
+    from paper_2212_06985_amd.train_cnn import blend_prior
+    w = np.load(weights, allow_pickle=False)
+    d = torch.from_numpy(blend_prior(w, beta, p)).cuda()
+    packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
+    tc.cnn_pack(d, packed)
+    torch.cuda.synchronize()
+    return packed
+
+
+def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, weights, tag):
+    """Warm up, then time `steps` complete experiments of one decoder. Returns
+    the wall time of the timed steps, per-class kernel times and statistics."""
+    import torch
+    W = tc.n_words(S)
+    L = cfg["L"]
+    cnn = decoder == "cnn"
+
+    def params(step):
+        p = cfg["ps"][step % len(cfg["ps"])]
+        return tc.make_run_params(p, p, cfg["noisy"], cfg["bp"], cfg["sweeps"], cfg["mask"],
+                                  n_shots=S, seed=1, shot0=64 * W * step, batch_shots=batch,
+                                  bp_tile=bp_tile)
+
+    nps = len(cfg["ps"])
+    packs = [cnn_packed(p, beta, weights) for p in cfg["ps"]] if cnn else [None] * nps
+    ws_of = tc.run_cnn_workspace_bytes if cnn else tc.run_workspace_bytes
+    need = max(ws_of(lat, params(k)) for k in range(nps))
+    ws = tc.alloc_workspace(need)
+    err = torch.zeros((lat.n_edges, W), dtype=torch.int64, device="cuda")
+    mask = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    odd = torch.zeros((S, 3), dtype=torch.int32, device="cuda")
+    log(f"[bench] {tag} decoder {decoder}: L={L} shots/step={S} cycles={cfg['noisy'] + 1} "
+        f"batch={batch} workspace {need / 2**30:.2f} GiB; warmup {warmup}, steps {steps}")
+
+    def one(k, timed):
+        err.zero_()
+        pk = packs[k % nps]
+        if cnn:
+            f = tc.run_cycles_cnn_timed if timed else tc.run_cycles_cnn
+            return f(lat, params(k), pk, err, mask, odd, ws)
+        f = tc.run_cycles_timed if timed else tc.run_cycles
+        return f(lat, params(k), err, mask, odd, ws)
+
+    for k in range(warmup):
+        one(k, False)
+        torch.cuda.synchronize()
+        log(f"[bench] {tag} warmup step {k} done")
+
+    per_class = {k: {"ms": 0.0, "launches": 0} for k in tc.KERNEL_CLASSES}
+    fails_x = fails_any = 0
+    hist = [0] * 8  # mask histogram: bit d = logical X error on qubit d
+    ties = 0        # majority-vote ties (an axis with exactly L^2/2 odd strings)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        t = one(k, True)
+        for name, v in t.as_dict().items():
+            per_class[name]["ms"] += v["ms"]
+            per_class[name]["launches"] += v["launches"]
+        m = mask.cpu()
+        fails_x += int((m & 1).ne(0).sum())
+        fails_any += int(m.ne(0).sum())
+        hb = torch.bincount(m.long(), minlength=8)
+        hist = [h + int(v) for h, v in zip(hist, hb.tolist())]
+        ties += int((2 * odd == L * L).any(dim=1).sum())
+        log(f"[bench] {tag} step {k}: {t.total_ms:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    N = S * steps
+    ler = {"axis_x": fails_x / N, "axis_x_sigma": (fails_x / N * (1 - fails_x / N) / N) ** 0.5,
+           "any_axis": fails_any / N,
+           "any_axis_sigma": (fails_any / N * (1 - fails_any / N) / N) ** 0.5, "shots": N,
+           "mask_histogram": {format(k, "03b")[::-1]: hist[k] for k in range(8)},
+           "majority_ties": ties}
+    # residual syndrome weight of the last step's final state (what the
+    # decoder left behind; stabiliser-equivalent residue is invisible to it)
+    syn = torch.zeros_like(err)
+    tc.syndrome(lat, err, syn, W)
+    import numpy as np
+    resid = int(np.unpackbits(syn.cpu().numpy().view(np.uint8)).sum()) / (64 * W)
+    del ws
+    return wall, per_class, ler, resid
+
+
+def roofline(per_class, n, batch, n_sites, workload):
+    """Roofline of the dominant kernel class, from the HIP-event launch times."""
+    dom = max(per_class, key=lambda k: per_class[k]["ms"])
+    d = per_class[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    if dom == "cnn":
+        # MFMA-bound: algorithmic FLOP of one forward over the batch, a fifth per launch
+        flop = CNN_FLOP_PER_SITE * n_sites * batch / CNN_LAUNCHES_PER_FORWARD
+        achieved = flop / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
+                "traffic": None, "kernel": "cnn (forward: input + 4 BF16 conv launches)",
+                "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
+                "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
+                "unit_of_work": "site-shot forward / 5 launches"}
+    per_unit, unit = ALGO_BYTES[dom]
+    # one launch covers one batch (the last batch of a step may be smaller;
+    # with batch = the whole step every launch is a full batch)
+    units = n * batch if unit == "edge-shot" else n * (batch // 64)
+    algo_bytes = per_unit * units
+    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(dom, workload), "kernel": dom,
+            "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
+            "algo_bytes_per_launch": algo_bytes, "algo_bytes_per_unit": per_unit,
+            "unit_of_work": unit}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
+    ap.add_argument("--L", type=int, default=None, help="override the workload's lattice size")
     ap.add_argument("--shots", type=int, default=None, help="shots per step")
     ap.add_argument("--batch-shots", type=int, default=0)
     ap.add_argument("--bp-tile", type=int, default=0, help="BP traversal tile (0: auto)")
     ap.add_argument("--noisy-cycles", type=int, default=None,
                     help="override the workload's noisy cycles (short counter runs)")
+    ap.add_argument("--decoder", choices=["plain", "cnn"], default=None,
+                    help="plain p-BP or BP with the CNN prior (default: the workload's)")
+    ap.add_argument("--compare", action=argparse.BooleanOptionalAction, default=None,
+                    help="also decode the same shots with the other decoder")
+    ap.add_argument("--beta", type=float, default=0.2,
+                    help="CNN prior strength: llr0 = l0 + beta (llr_cnn - l0)")
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibrate", type=int, default=0,
@@ -179,91 +324,55 @@ def main():
     cfg = dict(WORKLOADS[args.workload])
     if args.shots:
         cfg["shots"] = args.shots
+    if args.L:
+        cfg["L"] = args.L
+        if args.noisy_cycles is None:
+            cfg["noisy"] = args.L
     if args.noisy_cycles is not None:
         cfg["noisy"] = args.noisy_cycles
+    decoder = args.decoder or cfg.get("decoder", "plain")
+    compare = cfg.get("compare", False) if args.compare is None else args.compare
     steps = cfg["steps"] if args.steps is None else args.steps
     warmup = cfg["warmup"] if args.warmup is None else args.warmup
     L, S = cfg["L"], cfg["shots"]
     lat = tc.make_lattice(L)
     cycles = cfg["noisy"] + 1
     W = tc.n_words(S)
+    n = lat.n_edges
+    if decoder == "cnn" and not cfg["bp"]:
+        sys.exit("the CNN prior feeds BP: pick a workload with BP iterations")
 
     # shots decoded together: the whole step unless a smaller batch is asked for
     batch = min(64 * W, args.batch_shots) if args.batch_shots else 64 * W
 
-    def params(step):
-        p = cfg["ps"][step % len(cfg["ps"])]
-        return tc.make_run_params(p, p, cfg["noisy"], cfg["bp"], cfg["sweeps"], cfg["mask"],
-                                  n_shots=S, seed=1, shot0=64 * W * step, batch_shots=batch,
-                                  bp_tile=args.bp_tile)
-
-    need = max(tc.run_workspace_bytes(lat, params(k)) for k in range(len(cfg["ps"])))
-    ws = tc.alloc_workspace(need)
-    err = torch.zeros((lat.n_edges, W), dtype=torch.int64, device="cuda")
-    mask = torch.zeros(S, dtype=torch.uint8, device="cuda")
-    odd = torch.zeros((S, 3), dtype=torch.int32, device="cuda")
-    log(f"[bench] workload {args.workload}: L={L} shots/step={S} cycles={cycles} "
-        f"batch={batch} workspace {need / 2**30:.2f} GiB; warmup {warmup}, steps {steps}")
-
-    for k in range(warmup):
-        err.zero_()
-        tc.run_cycles(lat, params(k), err, mask, odd, ws)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup step {k} done")
-
-    per_class = {k: {"ms": 0.0, "launches": 0} for k in tc.KERNEL_CLASSES}
-    fails_x = fails_any = 0
-    hist = [0] * 8  # mask histogram: bit d = logical X error on qubit d
-    ties = 0        # majority-vote ties (an axis with exactly L^2/2 odd strings)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        err.zero_()
-        t = tc.run_cycles_timed(lat, params(k), err, mask, odd, ws)
-        for name, v in t.as_dict().items():
-            per_class[name]["ms"] += v["ms"]
-            per_class[name]["launches"] += v["launches"]
-        m = mask.cpu()
-        fails_x += int((m & 1).ne(0).sum())
-        fails_any += int(m.ne(0).sum())
-        hb = torch.bincount(m.long(), minlength=8)
-        hist = [h + int(v) for h, v in zip(hist, hb.tolist())]
-        ties += int((2 * odd == L * L).any(dim=1).sum())
-        log(f"[bench] step {k}: {t.total_ms:.1f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    n = lat.n_edges
+    wall, per_class, ler, resid = run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch,
+                                              args.bp_tile, args.beta, args.weights, "main")
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
+    roof = roofline(per_class, n, batch, lat.n_sites, args.workload)
+    # with the CNN prior, the conv launches' own (MFMA) roofline as well
+    cnn_roof = None
+    if decoder == "cnn" and per_class["cnn"]["launches"]:
+        only = {k: (v if k == "cnn" else {"ms": 0.0, "launches": 0}) for k, v in per_class.items()}
+        cnn_roof = roofline(only, n, batch, lat.n_sites, args.workload)
 
-    # roofline of the dominant kernel class
-    dom = max(per_class, key=lambda k: per_class[k]["ms"])
-    d = per_class[dom]
-    avg_ms = d["ms"] / max(d["launches"], 1)
-    per_unit, unit = ALGO_BYTES[dom]
-    # one launch covers one batch (the last batch of a step may be smaller;
-    # with batch = the whole step every launch is a full batch)
-    units = n * batch if unit == "edge-shot" else n * (batch // 64)
-    algo_bytes = per_unit * units
-    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = stored_traffic(dom, args.workload)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
-            "launches": d["launches"], "algo_bytes_per_launch": algo_bytes,
-            "algo_bytes_per_unit": per_unit, "unit_of_work": unit}
+    comparison = None
+    if compare:
+        other = "plain" if decoder == "cnn" else "cnn"
+        w2, pc2, ler2, resid2 = run_decoder(tc, lat, cfg, other, steps, warmup, S, batch,
+                                            args.bp_tile, args.beta, args.weights, "compare")
+        comparison = {"decoder": other, "value": qubit_cycles / w2, "unit": "qubit-cycles/s",
+                      "ms_per_step": w2 / steps * 1e3, "ler": ler2,
+                      "mean_residual_syndrome": resid2,
+                      "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload),
+                      "kernel_ms": {k: round(v["ms"], 3) for k, v in pc2.items()}}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         cpu = cpu_baseline(cfg, args.cpu_seconds)
 
-    N = S * steps
-    ler = {"axis_x": fails_x / N, "axis_x_sigma": (fails_x / N * (1 - fails_x / N) / N) ** 0.5,
-           "any_axis": fails_any / N, "shots": N,
-           "mask_histogram": {format(k, "03b")[::-1]: hist[k] for k in range(8)},
-           "majority_ties": ties}
+    dec_name = "plain p-BP" if decoder == "plain" else f"CNN prior (beta={args.beta}) + p-BP"
     out = {
         "metric": "decoded qubit-cycles/s at fixed logical error rate; CNN-prior vs plain "
                   "BP+p-flip",
@@ -276,20 +385,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if cfg["bp"] else "u64",
+        "dtype": ("bf16+f32" if decoder == "cnn" else "f32") if cfg["bp"] else "u64",
         "data": "synthetic (phenomenological noise drawn from Philox counters, seed 1)",
         "config": {"workload": f"L={L} p=q={'/'.join(str(p) for p in cfg['ps'])} "
                                f"{cfg['noisy']}+1 cycles "
                                f"{'BP' + str(cfg['bp']) + ' + ' if cfg['bp'] else ''}"
-                               f"{cfg['sched']}",
-                   "L": L, "shots_per_step": S, "batch_shots": batch, "shots_total": N, "cycles": cycles,
-                   "bp_iters": cfg["bp"], "schedule": cfg["sched"], "decoder": "plain p-BP",
+                               f"{cfg['sched']}"
+                               f"{' with the CNN prior' if decoder == 'cnn' else ''}",
+                   "L": L, "shots_per_step": S, "batch_shots": batch, "shots_total": S * steps,
+                   "cycles": cycles, "bp_iters": cfg["bp"], "schedule": cfg["sched"],
+                   "decoder": dec_name,
                    "parallelism": "shots (bit-sliced 64 per word; one lane per shot in BP)"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "ler": ler,
+        "mean_residual_syndrome": resid,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in per_class.items()},
     }
+    if cnn_roof is not None:
+        out["cnn_roofline"] = cnn_roof
+    if comparison is not None:
+        out["comparison"] = comparison
     print(json.dumps(out), flush=True)
 
 

@@ -2,22 +2,29 @@
 // 3x3x3 convolutions 8 -> 32 -> 32 -> 32 -> 3 with ReLU between them, BF16
 // weights and activations, FP32 accumulation on the gfx950 matrix cores.
 //
-//   input   row g = s*N + v (shot s, site v), 8 BF16 channels: the measured
-//           syndrome bits of faces f(v,0..2) this cycle, the working-syndrome
-//           bits those faces kept at the end of the previous cycle, 2 zeros
+//   rows    g = (w N + v) 64 + l for shot s = 64 w + l at site v: the 64
+//           shots of a bit-plane word are adjacent, as in BP's message layout
+//   input   8 BF16 channels per row: the measured syndrome bits of faces
+//           f(v,0..2) this cycle, the working-syndrome bits those faces kept
+//           at the end of the previous cycle, 2 zeros
 //   layer   y[v][co] = b[co] + sum_{d, ci} W[d][ci][co] x[v + off(d)][ci],
 //           off(d) = (d%3 - 1, d/3%3 - 1, d/9 - 1), coordinates mod L
 //   output  z[v][c] = logit of an error on edge e(v,c); the BP prior
 //           llr0 = -z is written straight into BP's [W][3N][64] layout
 //
-// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16: a
-// wavefront computes 16 rows x 16 output channels per instruction; its A
-// operand is the 16-byte channel chunk of one neighbour row (for 32 input
-// channels one offset per K step, for 8 input channels four offsets per K
-// step), its B operand a 16-byte column chunk of the packed weights held in
-// LDS. The backward pass uses the same kernel with the taps reversed and the
-// weights transposed (dX[u] = sum_d W[d]^T dY[u - off(d)]), and a separate
-// weight-gradient kernel (a GEMM over rows, staged transposed in LDS).
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16 with the
+// weights as the A operand (16 output channels x 32 input channels of one
+// tap, or of the three x-taps of one (dy, dz) column for 8 input channels)
+// and the activations of 16 shots at one site as the B operand: each B
+// fragment is one contiguous 16-row slab. A wavefront owns a run of NX sites
+// along x of one pencil (y, z) for 16 shots; for each of the 9 (dy, dz)
+// columns it loads the NX + 2 neighbouring slabs once and applies the three
+// x-taps to them from registers, so every activation slab is fetched
+// (NX + 2) / NX times per column instead of 3. The weights of all taps sit in
+// LDS in lane order. The backward pass uses the same kernel with the taps
+// reversed and the weights transposed (dX[u] = sum_d W[d]^T dY[u - off(d)]),
+// and a separate weight-gradient kernel (a GEMM over rows, staged transposed
+// in LDS).
 #include <math.h>
 
 #include "tc3d_device.hpp"
@@ -44,10 +51,14 @@ __host__ __device__ constexpr int64_t param_offset(int layer) {
 }
 constexpr int64_t kParams = param_offset(4);
 
-// Packed BF16 weight blocks, each [KS][NT][16][32]: a K step t, an output
-// tile nt, output column n, K index k. Forward blocks for layers 1-4, then
-// backward-data blocks for layers 4, 3, 2 (taps reversed, weights
-// transposed: input channels = that layer's outputs, outputs = its inputs).
+// Packed BF16 weight blocks, each [KS][NT][64][8]: K step t, output tile nt,
+// then one MFMA A fragment in lane order (lane = 16 q + n holds output
+// channel 16 nt + n, K indices 8 q .. 8 q + 7). With 32 input channels K step
+// t is tap t and k the input channel; with 8 input channels K step t is the
+// (dy, dz) column t (taps 3t, 3t+1, 3t+2, i.e. dx = -1, 0, 1) and k = 8 dx' +
+// c, dx' = k / 8 = 3 being zero padding. Forward blocks for layers 1-4, then
+// backward-data blocks for layers 4, 3, 2 (taps reversed, weights transposed:
+// input channels = that layer's outputs, outputs = its inputs).
 struct Block {
     int layer;   // 0..3
     int bwd;     // 0 forward, 1 backward-data
@@ -62,12 +73,12 @@ __host__ __device__ constexpr Block block_of(int i) {
     if (i < 4) {
         const int cin = kCh[i], cout = kCh[i + 1];
         const int cin_k = cin == 8 ? 8 : 32;
-        return Block{i, 0, cin_k, cin, cout, cin_k == 32 ? 27 : 7, (cout + 15) / 16};
+        return Block{i, 0, cin_k, cin, cout, cin_k == 32 ? 27 : 9, (cout + 15) / 16};
     }
     const int layer = 7 - i;  // 3, 2, 1
     const int cin = kCh[layer + 1], cout = kCh[layer];
     const int cin_k = cin <= 8 ? 8 : 32;
-    return Block{layer, 1, cin_k, cin, cout, cin_k == 32 ? 27 : 7, (cout + 15) / 16};
+    return Block{layer, 1, cin_k, cin, cout, cin_k == 32 ? 27 : 9, (cout + 15) / 16};
 }
 
 __host__ __device__ constexpr int64_t block_elems(int i) {
@@ -103,13 +114,14 @@ __global__ void k_pack(const float* __restrict__ params, bf16* __restrict__ pack
     while (b + 1 < kBlocks && i >= block_offset(b + 1)) ++b;
     const Block B = block_of(b);
     int64_t r = i - block_offset(b);
-    const int k = (int)(r % 32);
-    r /= 32;
-    const int n = (int)(r % 16);
-    r /= 16;
+    const int j = (int)(r % 8);
+    r /= 8;
+    const int lane = (int)(r % 64);
+    r /= 64;
+    const int n = lane % 16, k = 8 * (lane / 16) + j;
     const int nt = (int)(r % B.nt);
     const int t = (int)(r / B.nt);
-    const int d = B.cin_k == 32 ? t : 4 * t + k / 8;
+    const int d = B.cin_k == 32 ? t : (k / 8 < 3 ? 3 * t + k / 8 : 27);
     const int c = B.cin_k == 32 ? k : k % 8;  // input channel of this conv
     const int o = 16 * nt + n;                // output channel of this conv
     float v = 0.f;
@@ -126,15 +138,15 @@ __global__ void k_pack(const float* __restrict__ params, bf16* __restrict__ pack
 
 // ---------------------------------------------------------- input rows
 // x0[g][8] from the bit planes of this cycle's syndrome and the previous
-// cycle's final working syndrome (nullptr: zeros).
+// cycle's final working syndrome (nullptr: zeros); row g = (w N + v) 64 + l.
 __global__ void k_cnn_input(const uint64_t* __restrict__ syn, const uint64_t* __restrict__ prev,
                             int64_t ld, int N, int64_t R, bf16* __restrict__ x0) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= R) return;
-    const int64_t s = g / N;
-    const int v = (int)(g - s * N);
-    const int64_t w = s >> 6;
-    const int bit = (int)(s & 63);
+    const int bit = (int)(g & 63);
+    const int64_t wv = g >> 6;
+    const int64_t w = wv / N;
+    const int v = (int)(wv - w * N);
     bf16x8 o;
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
@@ -150,19 +162,31 @@ __global__ void k_cnn_input(const uint64_t* __restrict__ syn, const uint64_t* __
 // ------------------------------------------------------------ conv (MFMA)
 enum { EPI_RELU = 0, EPI_LLR = 1, EPI_MASK = 2 };
 
-// x [R][CIN] BF16 (CIN = 8 or 32); packed block [KS][NT][16][32].
-//  EPI_RELU: y = relu(acc + bias) as BF16 [R][NT*16]
-//  EPI_LLR : llr[(s/64)*3N + c*N + v][s%64] = -(acc + bias) for c < 3
-//  EPI_MASK: y = acc where mask_act > 0 else 0, BF16 [R][NT*16]
+// Work item of a wavefront: 16 shots (group sg, shots 16 sg .. 16 sg + 15),
+// the pencil (y, z) and the run of NX sites x0 .. x0 + NX - 1 along x
+// (clipped at L). Items are numbered with the x-run fastest, then y, z and
+// the shot group, so that consecutive items share most of their neighbour
+// slabs.
+struct ConvItems {
+    int L, N, nxr;       // lattice, sites, x-runs per pencil
+    uint32_t n_items;    // 4 W L^2 nxr
+};
+
+// x rows [R][CIN] BF16 (CIN = 8 or 32); packed block [KS][NT][64][8].
+//  EPI_RELU: y = relu(acc + bias) as BF16 [R][32]
+//  EPI_LLR : llr[(w 3 + c) N + v][l] = -(acc + bias) for c < 3 (NT = 1)
+//  EPI_MASK: y = acc where mask_act > 0 else 0, BF16 [R][32]
 // Every variant reads x[v + off(d)]; the backward-data blocks carry the
 // reversed taps in their packing.
-template <int CIN, int NT, int EPI>
+template <int CIN, int EPI, int NX>
 __global__ __launch_bounds__(kConvBlock) void k_conv(
     const bf16* __restrict__ x, const bf16* __restrict__ wp, const float* __restrict__ bias,
-    const bf16* __restrict__ mask_act, bf16* __restrict__ y, float* __restrict__ llr, int L,
-    int N, uint32_t R, uint32_t n_tiles) {
-    constexpr int KS = CIN == 32 ? 27 : 7;
-    constexpr int WELEMS = KS * NT * 16 * 32;
+    const bf16* __restrict__ mask_act, bf16* __restrict__ y, float* __restrict__ llr,
+    ConvItems it) {
+    constexpr int NT = EPI == EPI_LLR ? 1 : 2;
+    constexpr int KS = CIN == 32 ? 27 : 9;
+    constexpr int WELEMS = KS * NT * 64 * 8;
+    constexpr int NB = CIN == 32 ? NX + 2 : NX;  // B fragments per (dy, dz) column
     __shared__ __attribute__((aligned(16))) bf16 wl[WELEMS];
     for (int i = threadIdx.x * 8; i < WELEMS; i += kConvBlock * 8)
         *reinterpret_cast<bf16x8*>(wl + i) = *reinterpret_cast<const bf16x8*>(wp + i);
@@ -170,61 +194,123 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int r16 = lane & 15, q = lane >> 4;
-    const int LL = L * L;
-    for (uint32_t tile = blockIdx.x * kConvWaves + wave; tile < n_tiles;
-         tile += gridDim.x * kConvWaves) {
-        // A row of this lane
-        const uint32_t g = tile * 16 + r16;
-        const uint32_t gc = g < R ? g : R - 1;
-        const uint32_t s = gc / (uint32_t)N;
-        const int v = (int)(gc - s * (uint32_t)N);
-        const int vx = v % L, vy = (v / L) % L, vz = v / LL;
-        const bf16* xs = x + (int64_t)s * N * CIN;
-        f32x4 acc[NT];
+    const int L = it.L, N = it.N;
+    // per-lane channel block of the A/B fragments and output channels
+    float bv[NT][4];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
-        for (int t = 0; t < KS; ++t) {
-            const int d = CIN == 32 ? t : 4 * t + q;
-            bf16x8 a;
-            if (d < 27) {
-                const int ux = wrap(vx + off_x(d), L), uy = wrap(vy + off_y(d), L),
-                          uz = wrap(vz + off_z(d), L);
-                const int u = ux + L * (uy + L * uz);
-                a = *reinterpret_cast<const bf16x8*>(xs + (int64_t)u * CIN + (CIN == 32 ? 8 * q : 0));
+        for (int i = 0; i < 4; ++i)
+            bv[mt][i] = (EPI == EPI_MASK) ? 0.f : bias[16 * mt + 4 * q + i];
+    const int64_t G = gridDim.x;
+    const int64_t lb = xcd_block(blockIdx.x, G);
+    for (int64_t base = lb * kConvWaves; base < it.n_items; base += G * kConvWaves) {
+        const uint32_t item = (uint32_t)(base + wave);
+        if (item >= it.n_items) break;
+        // wave-uniform decode
+        uint32_t t = item;
+        const int xr = (int)(t % (uint32_t)it.nxr);
+        t /= (uint32_t)it.nxr;
+        const int yy = (int)(t % (uint32_t)L);
+        t /= (uint32_t)L;
+        const int zz = (int)(t % (uint32_t)L);
+        const uint32_t sg = t / (uint32_t)L;
+        const int64_t w = sg >> 2;
+        const int l0 = 16 * (int)(sg & 3);
+        const int x0 = xr * NX;
+        // row (w, v, l) = (w N + v) 64 + l; lane part of every fragment address
+        const int64_t wrow = w * N;
+        const int lane_off = (l0 + r16) * CIN + (CIN == 32 ? 8 * q : 0);
+        f32x4 acc[NX][NT];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) acc[i][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int j = 0; j < 9; ++j) {  // (dy, dz) column: j = 3 (dz + 1) + (dy + 1)
+            const int uy = wrap(yy + j % 3 - 1, L), uz = wrap(zz + j / 3 - 1, L);
+            const int64_t pencil = (wrow + (int64_t)L * (uy + (int64_t)L * uz)) * 64;
+            bf16x8 b[NB];
+            if constexpr (CIN == 32) {
+                // slabs x0 - 1 .. x0 + NX
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const int ux = wrap(x0 - 1 + i, L);
+                    const bf16* src = x + (pencil + (int64_t)ux * 64) * CIN;
+                    b[i] = *reinterpret_cast<const bf16x8*>(src + lane_off);
+                }
             } else {
+                // lane group q reads site x + q - 1 (q = 3: zero padding)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) a[j] = (bf16)0.f;
+                for (int i = 0; i < NB; ++i) {
+                    if (q < 3) {
+                        const int ux = wrap(x0 + i + q - 1, L);
+                        b[i] = *reinterpret_cast<const bf16x8*>(
+                            x + (pencil + (int64_t)ux * 64) * CIN + lane_off);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) b[i][e] = (bf16)0.f;
+                    }
+                }
             }
+            if constexpr (CIN == 32) {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const bf16x8 b =
-                    *reinterpret_cast<const bf16x8*>(wl + ((t * NT + nt) * 16 + r16) * 32 + 8 * q);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+                for (int dx = 0; dx < 3; ++dx) {
+                    bf16x8 a[NT];
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt)
+                        a[mt] = *reinterpret_cast<const bf16x8*>(
+                            wl + (((3 * j + dx) * NT + mt) * 64 + lane) * 8);
+#pragma unroll
+                    for (int i = 0; i < NX; ++i)
+#pragma unroll
+                        for (int mt = 0; mt < NT; ++mt)
+                            acc[i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[mt], b[i + dx], acc[i][mt], 0, 0, 0);
+                }
+            } else {
+                bf16x8 a[NT];
+#pragma unroll
+                for (int mt = 0; mt < NT; ++mt)
+                    a[mt] = *reinterpret_cast<const bf16x8*>(wl + ((j * NT + mt) * 64 + lane) * 8);
+#pragma unroll
+                for (int i = 0; i < NX; ++i)
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt)
+                        acc[i][mt] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[i], acc[i][mt], 0, 0, 0);
             }
         }
-        // lane holds D[row 4q + i][column r16 + 16 nt]
+        // epilogue: lane holds D[channel 16 mt + 4 q + i][shot l0 + r16] of site x0 + i
+        const int64_t vrow = (int64_t)L * (yy + (int64_t)L * zz);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int col = 16 * nt + r16;
+        for (int i = 0; i < NX; ++i) {
+            if (x0 + i >= L) break;
+            const int64_t v = vrow + x0 + i;
+            const int64_t row = (wrow + v) * 64 + l0 + r16;
+            if constexpr (EPI == EPI_LLR) {
+                if (q == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t row = tile * 16 + 4 * q + i;
-                if (row >= R) continue;
-                float val = acc[nt][i];
-                if constexpr (EPI == EPI_RELU) {
-                    val = fmaxf(val + bias[col], 0.f);
-                    y[(int64_t)row * (NT * 16) + col] = (bf16)val;
-                } else if constexpr (EPI == EPI_MASK) {
-                    const float m = (float)mask_act[(int64_t)row * (NT * 16) + col];
-                    y[(int64_t)row * (NT * 16) + col] = m > 0.f ? (bf16)val : (bf16)0.f;
-                } else {
-                    if (col < 3) {
-                        const uint32_t rs = row / (uint32_t)N;
-                        const int rv = (int)(row - rs * (uint32_t)N);
-                        const int64_t e = (int64_t)col * N + rv;
-                        llr[((int64_t)(rs >> 6) * 3 * N + e) * 64 + (rs & 63)] = -(val + bias[col]);
+                    for (int c = 0; c < 3; ++c)
+                        llr[((w * 3 + c) * N + v) * 64 + l0 + r16] = -(acc[i][0][c] + bv[0][c]);
+                }
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < NT; ++mt) {
+                    const int64_t o = row * 32 + 16 * mt + 4 * q;
+                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                    bf16x4 out;
+                    if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            out[e] = (bf16)fmaxf(acc[i][mt][e] + bv[mt][e], 0.f);
+                    } else {
+                        const bf16x4 m = *reinterpret_cast<const bf16x4*>(mask_act + o);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            out[e] = (float)m[e] > 0.f ? (bf16)acc[i][mt][e] : (bf16)0.f;
                     }
+                    *reinterpret_cast<bf16x4*>(y + o) = out;
                 }
             }
         }
@@ -244,16 +330,18 @@ __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ llr,
     const uint32_t g = blockIdx.x * 256 + threadIdx.x;
     float acc = 0.f;
     if (g < R) {
-        const uint32_t s = g / (uint32_t)N;
-        const int v = (int)(g - s * (uint32_t)N);
+        const int l = (int)(g & 63);
+        const uint32_t wv = g >> 6;
+        const uint32_t w = wv / (uint32_t)N;
+        const int v = (int)(wv - w * (uint32_t)N);
         bf16x8 o;
 #pragma unroll
         for (int j = 0; j < 8; ++j) o[j] = (bf16)0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int64_t e = (int64_t)c * N + v;
-            const float z = -llr[((int64_t)(s >> 6) * 3 * N + e) * 64 + (s & 63)];
-            const float t = (float)((target[e * ld + (s >> 6)] >> (s & 63)) & 1u);
+            const float z = -llr[((int64_t)w * 3 * N + e) * 64 + l];
+            const float t = (float)((target[e * ld + w] >> l) & 1u);
             const float sp = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
             acc += sp - t * z;
             o[c] = (bf16)((1.f / (1.f + expf(-z)) - t) * inv_count);
@@ -310,11 +398,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ x,
     for (uint32_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
         const uint32_t g = chunk * 256 + tid;
         const bool ok = g < R;
-        uint32_t s = 0;
+        uint32_t w = 0;
         int vx = 0, vy = 0, vz = 0;
         if (ok) {
-            s = g / (uint32_t)N;
-            const int v = (int)(g - s * (uint32_t)N);
+            const uint32_t wv = g >> 6;
+            w = wv / (uint32_t)N;
+            const int v = (int)(wv - w * (uint32_t)N);
             vx = v % L;
             vy = (v / L) % L;
             vz = v / LL;
@@ -332,7 +421,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ x,
             if (ok) {
                 const int ux = wrap(vx + off_x(d), L), uy = wrap(vy + off_y(d), L),
                           uz = wrap(vz + off_z(d), L);
-                const int64_t row = (int64_t)s * N + ux + L * (uy + L * uz);
+                const int64_t row =
+                    ((int64_t)w * N + ux + L * (uy + L * uz)) * 64 + (g & 63);
 #pragma unroll
                 for (int c8 = 0; c8 < CIN; c8 += 8) {
                     const bf16x8 v8 = *reinterpret_cast<const bf16x8*>(x + row * CIN + c8);
@@ -474,19 +564,26 @@ CnnWs carve(void* ws, int64_t R, int training) {
     return w;
 }
 
-int conv_grid(int64_t tiles) {
-    const int64_t g = cdiv(tiles, kConvWaves);
-    return (int)(g < 2048 ? g : 2048);
-}
+constexpr int kConvNX = 4;  // sites per wavefront run along x
 
-template <int CIN, int NT, int EPI>
+// R = 64 W N rows; one wavefront item per (16 shots, pencil, x-run).
+template <int CIN, int EPI>
 int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
                 const bf16* mask_act, bf16* y, float* llr, Geo g, int64_t R) {
-    const int64_t tiles = cdiv(R, 16);
+    const int64_t W = R / (64 * (int64_t)g.N);
+    ConvItems it;
+    it.L = g.L;
+    it.N = g.N;
+    it.nxr = (g.L + kConvNX - 1) / kConvNX;
+    const int64_t items = 4 * W * (int64_t)g.L * g.L * it.nxr;
+    if (items >= (1ll << 32)) return TC3D_EINVAL;
+    it.n_items = (uint32_t)items;
+    const int64_t blocks = cdiv(items, kConvWaves);
+    const int grid = (int)(blocks < 1024 ? blocks : 1024);
     int rc = before_launch(c, TC3D_K_CNN);
     if (rc) return rc;
-    k_conv<CIN, NT, EPI><<<dim3(conv_grid(tiles)), dim3(kConvBlock), 0, c.stream>>>(
-        x, wp, bias, mask_act, y, llr, g.L, g.N, (uint32_t)R, (uint32_t)tiles);
+    k_conv<CIN, EPI, kConvNX><<<dim3(grid), dim3(kConvBlock), 0, c.stream>>>(
+        x, wp, bias, mask_act, y, llr, it);
     return after_launch(c);
 }
 
@@ -503,16 +600,16 @@ int cnn_forward_impl(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* p
     k_cnn_input<<<dim3((unsigned)cdiv(R, 256)), dim3(256), 0, c.stream>>>(syn, prev, ld, g.N, R,
                                                                            w.x0);
     if ((rc = after_launch(c))) return rc;
-    if ((rc = launch_conv<8, 2, EPI_RELU>(c, w.x0, blk(packed, 0), bias_of(packed, 0), nullptr,
+    if ((rc = launch_conv<8, EPI_RELU>(c, w.x0, blk(packed, 0), bias_of(packed, 0), nullptr,
                                           w.a[0], nullptr, g, R)))
         return rc;
-    if ((rc = launch_conv<32, 2, EPI_RELU>(c, w.a[0], blk(packed, 1), bias_of(packed, 1), nullptr,
+    if ((rc = launch_conv<32, EPI_RELU>(c, w.a[0], blk(packed, 1), bias_of(packed, 1), nullptr,
                                            w.a[1], nullptr, g, R)))
         return rc;
-    if ((rc = launch_conv<32, 2, EPI_RELU>(c, w.a[1], blk(packed, 2), bias_of(packed, 2), nullptr,
+    if ((rc = launch_conv<32, EPI_RELU>(c, w.a[1], blk(packed, 2), bias_of(packed, 2), nullptr,
                                            w.a[2], nullptr, g, R)))
         return rc;
-    return launch_conv<32, 1, EPI_LLR>(c, w.a[2], blk(packed, 3), bias_of(packed, 3), nullptr,
+    return launch_conv<32, EPI_LLR>(c, w.a[2], blk(packed, 3), bias_of(packed, 3), nullptr,
                                        nullptr, llr, g, R);
 }
 
@@ -574,19 +671,19 @@ int cnn_loss_grad(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev
     if ((rc = after_launch(c))) return rc;
     // layer 4 (32 -> 3): weight gradient, then dy of layer 3 through its ReLU
     if ((rc = launch_wgrad<32, 3>(c, w.a[2], w.dy8, g, R, w, grad + param_offset(3)))) return rc;
-    if ((rc = launch_conv<8, 2, EPI_MASK>(c, w.dy8, blk(packed, 4), nullptr, w.a[2], w.dyb[0],
+    if ((rc = launch_conv<8, EPI_MASK>(c, w.dy8, blk(packed, 4), nullptr, w.a[2], w.dyb[0],
                                           nullptr, g, R)))
         return rc;
     // layer 3 (32 -> 32)
     if ((rc = launch_wgrad<32, 32>(c, w.a[1], w.dyb[0], g, R, w, grad + param_offset(2))))
         return rc;
-    if ((rc = launch_conv<32, 2, EPI_MASK>(c, w.dyb[0], blk(packed, 5), nullptr, w.a[1],
+    if ((rc = launch_conv<32, EPI_MASK>(c, w.dyb[0], blk(packed, 5), nullptr, w.a[1],
                                            w.dyb[1], nullptr, g, R)))
         return rc;
     // layer 2 (32 -> 32)
     if ((rc = launch_wgrad<32, 32>(c, w.a[0], w.dyb[1], g, R, w, grad + param_offset(1))))
         return rc;
-    if ((rc = launch_conv<32, 2, EPI_MASK>(c, w.dyb[1], blk(packed, 6), nullptr, w.a[0],
+    if ((rc = launch_conv<32, EPI_MASK>(c, w.dyb[1], blk(packed, 6), nullptr, w.a[0],
                                            w.dyb[0], nullptr, g, R)))
         return rc;
     // layer 1 (8 -> 32): weight gradient only

@@ -1,0 +1,47 @@
+"""The paper's flip-family thresholds, reproduced by the GPU path.
+
+With the flip rule applied once per cycle (Fig. 2) the paper finds the
+failure curves of different L crossing at p = q = 2.611%; with five rule
+applications per cycle, every third one p-flip (Table 1, n_A = 5,
+lambda_p = 3: F F P F F), at 4.445%, both after 1000 cycles. Below the
+crossing a larger lattice fails less often, above it more often. The test
+brackets each printed threshold by two error rates, one on either side, and
+requires L = 32 to fail significantly less often than L = 14 at the lower one
+and significantly more often at the upper one."""
+import math
+
+import pytest
+
+from gpu_util import announce
+from paper_2212_06985_amd import experiments as ex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need an MI355X"
+    yield
+    torch.cuda.synchronize()
+
+
+def _rate(L, p, n_a, lam, shots):
+    r = ex.memory_run(L, p, 1000, "flip", shots, seed=1, n_a=n_a, lambda_p=lam)
+    return ex.pfail(r)
+
+
+@pytest.mark.parametrize("n_a,lam,p_lo,p_hi,paper", [
+    (1, 0, 0.0258, 0.0264, 0.02611),   # Fig. 2
+    (5, 3, 0.0440, 0.0450, 0.04445),   # Table 1
+])
+def test_threshold_is_bracketed(n_a, lam, p_lo, p_hi, paper):
+    assert p_lo < paper < p_hi
+    shots = 4096
+    for p, below in ((p_lo, True), (p_hi, False)):
+        f14, s14 = _rate(14, p, n_a, lam, shots)
+        f32, s32 = _rate(32, p, n_a, lam, shots)
+        announce(f"  n_A={n_a} lambda_p={lam} p={p}: p_fail L=14 {f14:.4f}+-{s14:.4f}, "
+                 f"L=32 {f32:.4f}+-{s32:.4f}")
+        gap = (f14 - f32) if below else (f32 - f14)
+        assert gap > 3 * math.sqrt(s14 ** 2 + s32 ** 2), (p, f14, f32)
