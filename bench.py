@@ -68,10 +68,10 @@ ALGO_BYTES = {
 
 # The CNN prior's forward pass: 4 periodic 3x3x3 convolutions 8 -> 32 -> 32 -> 32
 # -> 3 channels, 27 (8*32 + 32*32 + 32*32 + 32*3) multiply-adds per site of a shot.
-# One forward is 5 launches (input assembly + 4 layers); the class average
-# launch carries a fifth of a forward.
+# A forward runs as passes over a few shot groups, 5 launches each (input
+# assembly + 4 layers); the class average launch carries the forward's FLOP
+# divided by its launches.
 CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
-CNN_LAUNCHES_PER_FORWARD = 5
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_p05.npy")
 
@@ -249,21 +249,23 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
     return wall, per_class, ler, resid
 
 
-def roofline(per_class, n, batch, n_sites, workload):
-    """Roofline of the dominant kernel class, from the HIP-event launch times."""
+def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0):
+    """Roofline of the dominant kernel class, from the HIP-event launch times.
+    For the CNN class, `forwards` forward passes over `shots_padded` shots
+    (whole 64-shot words) were timed."""
     dom = max(per_class, key=lambda k: per_class[k]["ms"])
     d = per_class[dom]
     avg_ms = d["ms"] / max(d["launches"], 1)
     if dom == "cnn":
-        # MFMA-bound: algorithmic FLOP of one forward over the batch, a fifth per launch
-        flop = CNN_FLOP_PER_SITE * n_sites * batch / CNN_LAUNCHES_PER_FORWARD
+        # MFMA-bound: algorithmic FLOP of all forwards, per launch on average
+        flop = CNN_FLOP_PER_SITE * n_sites * shots_padded * forwards / max(d["launches"], 1)
         achieved = flop / (avg_ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
                 "traffic": None, "kernel": "cnn (forward: input + 4 BF16 conv launches)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
                 "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
-                "unit_of_work": "site-shot forward / 5 launches"}
+                "unit_of_work": "site-shot forward (passes of 5 launches)"}
     per_unit, unit = ALGO_BYTES[dom]
     # one launch covers one batch (the last batch of a step may be smaller;
     # with batch = the whole step every launch is a full batch)
@@ -349,12 +351,14 @@ def main():
                                               args.bp_tile, args.beta, args.weights, "main")
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
-    roof = roofline(per_class, n, batch, lat.n_sites, args.workload)
+    roof = roofline(per_class, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
+                    shots_padded=64 * W)
     # with the CNN prior, the conv launches' own (MFMA) roofline as well
     cnn_roof = None
     if decoder == "cnn" and per_class["cnn"]["launches"]:
         only = {k: (v if k == "cnn" else {"ms": 0.0, "launches": 0}) for k, v in per_class.items()}
-        cnn_roof = roofline(only, n, batch, lat.n_sites, args.workload)
+        cnn_roof = roofline(only, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
+                            shots_padded=64 * W)
 
     comparison = None
     if compare:
@@ -364,7 +368,8 @@ def main():
         comparison = {"decoder": other, "value": qubit_cycles / w2, "unit": "qubit-cycles/s",
                       "ms_per_step": w2 / steps * 1e3, "ler": ler2,
                       "mean_residual_syndrome": resid2,
-                      "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload),
+                      "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload,
+                                           forwards=cycles * steps, shots_padded=64 * W),
                       "kernel_ms": {k: round(v["ms"], 3) for k, v in pc2.items()}}
 
     cpu = None

@@ -137,16 +137,20 @@ __global__ void k_pack(const float* __restrict__ params, bf16* __restrict__ pack
 }
 
 // ---------------------------------------------------------- input rows
-// x0[g][8] from the bit planes of this cycle's syndrome and the previous
-// cycle's final working syndrome (nullptr: zeros); row g = (w N + v) 64 + l.
+// x0[g][8] for the rows of shot groups sg0 .. sg0 + n_sg - 1 (row g = (w N +
+// v) 64 + l, shot 64 w + l) from the bit planes of this cycle's syndrome and
+// the previous cycle's final working syndrome (nullptr: zeros).
 __global__ void k_cnn_input(const uint64_t* __restrict__ syn, const uint64_t* __restrict__ prev,
-                            int64_t ld, int N, int64_t R, bf16* __restrict__ x0) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= R) return;
-    const int bit = (int)(g & 63);
-    const int64_t wv = g >> 6;
-    const int64_t w = wv / N;
-    const int v = (int)(wv - w * N);
+                            int64_t ld, int N, int64_t sg0, int64_t n_sg, bf16* __restrict__ x0) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_sg * 16 * N) return;
+    const int64_t sgl = t / (16 * (int64_t)N);
+    const int64_t rem = t - sgl * 16 * N;
+    const int v = (int)(rem >> 4);
+    const int64_t sg = sg0 + sgl;
+    const int64_t w = sg >> 2;
+    const int bit = (int)((sg & 3) * 16 + (rem & 15));
+    const int64_t g = (w * N + v) * 64 + bit;
     bf16x8 o;
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
@@ -159,6 +163,17 @@ __global__ void k_cnn_input(const uint64_t* __restrict__ syn, const uint64_t* __
     *reinterpret_cast<bf16x8*>(x0 + g * 8) = o;
 }
 
+int launch_input(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev, int64_t ld,
+                 int64_t sg0, int64_t n_sg, bf16* x0) {
+    const int64_t n = n_sg * 16 * (int64_t)g.N;
+    if (n == 0) return TC3D_OK;
+    int rc = before_launch(c, TC3D_K_CNN);
+    if (rc) return rc;
+    k_cnn_input<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream>>>(syn, prev, ld, g.N,
+                                                                               sg0, n_sg, x0);
+    return after_launch(c);
+}
+
 // ------------------------------------------------------------ conv (MFMA)
 enum { EPI_RELU = 0, EPI_LLR = 1, EPI_MASK = 2 };
 
@@ -169,8 +184,10 @@ enum { EPI_RELU = 0, EPI_LLR = 1, EPI_MASK = 2 };
 // slabs.
 struct ConvItems {
     int L, N, nxr;       // lattice, sites, x-runs per pencil
-    uint32_t n_items;    // 4 W L^2 nxr
+    uint32_t n_items;    // n_sg L^2 nxr, for shot groups sg0 .. sg0 + n_sg - 1
+    uint32_t sg0;
 };
+
 
 // x rows [R][CIN] BF16 (CIN = 8 or 32); packed block [KS][NT][64][8].
 //  EPI_RELU: y = relu(acc + bias) as BF16 [R][32]
@@ -214,7 +231,7 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
         const int yy = (int)(t % (uint32_t)L);
         t /= (uint32_t)L;
         const int zz = (int)(t % (uint32_t)L);
-        const uint32_t sg = t / (uint32_t)L;
+        const uint32_t sg = it.sg0 + t / (uint32_t)L;
         const int64_t w = sg >> 2;
         const int l0 = 16 * (int)(sg & 3);
         const int x0 = xr * NX;
@@ -566,18 +583,20 @@ CnnWs carve(void* ws, int64_t R, int training) {
 
 constexpr int kConvNX = 4;  // sites per wavefront run along x
 
-// R = 64 W N rows; one wavefront item per (16 shots, pencil, x-run).
+// Rows of shot groups sg0 .. sg0 + n_sg - 1 (16 shots each); one wavefront
+// item per (shot group, pencil, x-run).
 template <int CIN, int EPI>
 int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
-                const bf16* mask_act, bf16* y, float* llr, Geo g, int64_t R) {
-    const int64_t W = R / (64 * (int64_t)g.N);
+                const bf16* mask_act, bf16* y, float* llr, Geo g, int64_t sg0, int64_t n_sg) {
     ConvItems it;
     it.L = g.L;
     it.N = g.N;
     it.nxr = (g.L + kConvNX - 1) / kConvNX;
-    const int64_t items = 4 * W * (int64_t)g.L * g.L * it.nxr;
-    if (items >= (1ll << 32)) return TC3D_EINVAL;
+    const int64_t items = n_sg * (int64_t)g.L * g.L * it.nxr;
+    if (items >= (1ll << 32) || sg0 + n_sg >= (1ll << 32)) return TC3D_EINVAL;
+    if (items == 0) return TC3D_OK;
     it.n_items = (uint32_t)items;
+    it.sg0 = (uint32_t)sg0;
     const int64_t blocks = cdiv(items, kConvWaves);
     const int grid = (int)(blocks < 1024 ? blocks : 1024);
     int rc = before_launch(c, TC3D_K_CNN);
@@ -587,30 +606,47 @@ int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     return after_launch(c);
 }
 
+// Shot groups per pass of the forward network: one pass keeps its input and
+// output activations (2 x 16 x N x 64 bytes per group) within the 256 MB
+// Infinity Cache, so the neighbour re-reads of the convolutions are served
+// from it rather than from HBM.
+constexpr int64_t kPassBytes = 96ll << 20;
+int64_t groups_per_pass(Geo g) {
+    const int64_t per = (int64_t)g.N * 16 * 64;
+    const int64_t c = kPassBytes / per;
+    return c < 1 ? 1 : c;
+}
+
 const bf16* blk(const void* packed, int i) { return (const bf16*)packed + block_offset(i); }
 const float* bias_of(const void* packed, int layer) {
     return (const float*)((const char*)packed + kBiasOffsetBytes) + 32 * layer;
 }
 
-// Forward pass: x0 from the syndromes, then the four layers; writes llr.
+// Forward pass over passes of a few shot groups each: input rows from the
+// syndromes, then the four layers; writes llr. Rows of every shot group are
+// written, so the weight gradient of the first layer can read x0 afterwards.
 int cnn_forward_impl(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev, int64_t ld,
                      int64_t R, const void* packed, float* llr, const CnnWs& w) {
-    int rc = before_launch(c, TC3D_K_CNN);
-    if (rc) return rc;
-    k_cnn_input<<<dim3((unsigned)cdiv(R, 256)), dim3(256), 0, c.stream>>>(syn, prev, ld, g.N, R,
-                                                                           w.x0);
-    if ((rc = after_launch(c))) return rc;
-    if ((rc = launch_conv<8, EPI_RELU>(c, w.x0, blk(packed, 0), bias_of(packed, 0), nullptr,
-                                          w.a[0], nullptr, g, R)))
-        return rc;
-    if ((rc = launch_conv<32, EPI_RELU>(c, w.a[0], blk(packed, 1), bias_of(packed, 1), nullptr,
-                                           w.a[1], nullptr, g, R)))
-        return rc;
-    if ((rc = launch_conv<32, EPI_RELU>(c, w.a[1], blk(packed, 2), bias_of(packed, 2), nullptr,
-                                           w.a[2], nullptr, g, R)))
-        return rc;
-    return launch_conv<32, EPI_LLR>(c, w.a[2], blk(packed, 3), bias_of(packed, 3), nullptr,
-                                       nullptr, llr, g, R);
+    int rc;
+    const int64_t n_sg = R / (16 * (int64_t)g.N);
+    const int64_t per = groups_per_pass(g);
+    for (int64_t sg0 = 0; sg0 < n_sg; sg0 += per) {
+        const int64_t k = n_sg - sg0 < per ? n_sg - sg0 : per;
+        if ((rc = launch_input(c, g, syn, prev, ld, sg0, k, w.x0))) return rc;
+        if ((rc = launch_conv<8, EPI_RELU>(c, w.x0, blk(packed, 0), bias_of(packed, 0), nullptr,
+                                           w.a[0], nullptr, g, sg0, k)))
+            return rc;
+        if ((rc = launch_conv<32, EPI_RELU>(c, w.a[0], blk(packed, 1), bias_of(packed, 1),
+                                            nullptr, w.a[1], nullptr, g, sg0, k)))
+            return rc;
+        if ((rc = launch_conv<32, EPI_RELU>(c, w.a[1], blk(packed, 2), bias_of(packed, 2),
+                                            nullptr, w.a[2], nullptr, g, sg0, k)))
+            return rc;
+        if ((rc = launch_conv<32, EPI_LLR>(c, w.a[2], blk(packed, 3), bias_of(packed, 3), nullptr,
+                                           nullptr, llr, g, sg0, k)))
+            return rc;
+    }
+    return TC3D_OK;
 }
 
 template <int CIN, int COUT>
@@ -671,20 +707,21 @@ int cnn_loss_grad(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev
     if ((rc = after_launch(c))) return rc;
     // layer 4 (32 -> 3): weight gradient, then dy of layer 3 through its ReLU
     if ((rc = launch_wgrad<32, 3>(c, w.a[2], w.dy8, g, R, w, grad + param_offset(3)))) return rc;
+    const int64_t n_sg = R / (16 * (int64_t)g.N);
     if ((rc = launch_conv<8, EPI_MASK>(c, w.dy8, blk(packed, 4), nullptr, w.a[2], w.dyb[0],
-                                          nullptr, g, R)))
+                                       nullptr, g, 0, n_sg)))
         return rc;
     // layer 3 (32 -> 32)
     if ((rc = launch_wgrad<32, 32>(c, w.a[1], w.dyb[0], g, R, w, grad + param_offset(2))))
         return rc;
     if ((rc = launch_conv<32, EPI_MASK>(c, w.dyb[0], blk(packed, 5), nullptr, w.a[1],
-                                           w.dyb[1], nullptr, g, R)))
+                                        w.dyb[1], nullptr, g, 0, n_sg)))
         return rc;
     // layer 2 (32 -> 32)
     if ((rc = launch_wgrad<32, 32>(c, w.a[0], w.dyb[1], g, R, w, grad + param_offset(1))))
         return rc;
     if ((rc = launch_conv<32, EPI_MASK>(c, w.dyb[1], blk(packed, 6), nullptr, w.a[0],
-                                           w.dyb[0], nullptr, g, R)))
+                                        w.dyb[0], nullptr, g, 0, n_sg)))
         return rc;
     // layer 1 (8 -> 32): weight gradient only
     return launch_wgrad<8, 32>(c, w.x0, w.dyb[0], g, R, w, grad + param_offset(0));
