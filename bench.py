@@ -12,7 +12,7 @@ Prints one JSON line with the throughput in decoded qubit-cycles/s (one
 qubit-cycle = one edge x one cycle x one shot), the roofline of the dominant
 kernel, measured live with HIP events, and the oracle timed on the host.
 
-    python bench.py [--workload c5|c4|c2|c1] [--decoder plain|cnn] [--steps K] [--warmup W]
+    python bench.py [--workload c5|c4|c3|c2|c1] [--decoder plain|cnn] [--steps K] [--warmup W]
 
 With --decoder cnn the BP prior comes from the committed CNN (blended with
 the channel prior); with --compare the other decoder also decodes the same
@@ -42,6 +42,11 @@ WORKLOADS = {
     # BP 20 + P F F P F F, 10^5 shots per p (one step per p value)
     "c2": dict(L=12, ps=[0.04, 0.05, 0.055, 0.06], noisy=12, bp=20, sweeps=6, mask=0b001001,
                sched="PFFPFF", shots=100_032, steps=4, warmup=1),
+    # batched mixed jobs: L in {8, 12, 16, 20, 24} x p = q in {0.045 .. 0.065},
+    # L noisy cycles + 1 perfect each, BP 20 + P F F P F F, all 25 jobs in one
+    # captured graph per step (2x10^4 shots per job per step; --shots changes it)
+    "c3": dict(Ls=[8, 12, 16, 20, 24], ps=[0.045, 0.05, 0.055, 0.06, 0.065], bp=20, sweeps=6,
+               mask=0b001001, sched="PFFPFF", shots=20_032, steps=2, warmup=1, L=24, noisy=24),
     # CNN prior vs plain: L = 24 (41,472 qubits), p = q = 0.05, 24 + 1 cycles,
     # BP 20 + P F F P F F, 10^5 shots (5 steps of 20,032), both decoders on the same shots
     "c4": dict(L=24, ps=[0.05], noisy=24, bp=20, sweeps=6, mask=0b001001,
@@ -267,9 +272,11 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0)
                 "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
                 "unit_of_work": "site-shot forward (passes of 5 launches)"}
     per_unit, unit = ALGO_BYTES[dom]
-    # one launch covers one batch (the last batch of a step may be smaller;
-    # with batch = the whole step every launch is a full batch)
-    units = n * batch if unit == "edge-shot" else n * (batch // 64)
+    # a launch covers one batch of shots; with uneven batches (the last one of
+    # a step may be smaller) the average launch carries shots / batches
+    shots = shots_padded if shots_padded else batch
+    n_batches = -(-shots // batch)
+    units = n * shots / n_batches if unit == "edge-shot" else n * (shots // 64) / n_batches
     algo_bytes = per_unit * units
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -278,6 +285,114 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0)
             "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
             "algo_bytes_per_launch": algo_bytes, "algo_bytes_per_unit": per_unit,
             "unit_of_work": unit}
+
+
+def run_c3(args, cfg, tc):
+    """The batched workload: every (L, p) job of a step in one tc3d_run_jobs
+    call (concurrent job streams captured in one graph), after autotuning the
+    traversal tile and batch size per L. The same jobs run sequentially (one
+    stream, no graph) for comparison."""
+    import torch
+    S = cfg["shots"]
+    W = tc.n_words(S)
+    steps = cfg["steps"] if args.steps is None else args.steps
+    warmup = cfg["warmup"] if args.warmup is None else args.warmup
+    tuned = {}
+    for L in cfg["Ls"]:
+        lat = tc.make_lattice(L)
+        prm = tc.make_run_params(0.055, 0.055, L, cfg["bp"], cfg["sweeps"], cfg["mask"],
+                                 n_shots=S, seed=1, batch_shots=min(64 * W, 32768))
+        ws = tc.alloc_workspace(tc.autotune_workspace_bytes(lat, prm))
+        tried = tc.autotune(lat, prm, ws, probe_cycles=1)
+        tuned[L] = (prm.bp_tile, prm.batch_shots, tried)
+        del ws
+        log(f"[bench] c3 autotune L={L}: tile {prm.bp_tile} batch {prm.batch_shots} "
+            f"({len(tried)} candidates)")
+    specs = [(L, p) for L in cfg["Ls"] for p in cfg["ps"]]
+    bufs = []
+    for L, p in specs:
+        n = 3 * L ** 3
+        bufs.append((torch.zeros((n, W), dtype=torch.int64, device="cuda"),
+                     torch.zeros(S, dtype=torch.uint8, device="cuda"),
+                     torch.zeros((S, 3), dtype=torch.int32, device="cuda")))
+
+    def jobs_of(step):
+        out = []
+        for (L, p), (e, m, o) in zip(specs, bufs):
+            prm = tc.make_run_params(p, p, L, cfg["bp"], cfg["sweeps"], cfg["mask"], n_shots=S,
+                                     seed=1, shot0=64 * W * step, batch_shots=tuned[L][1],
+                                     bp_tile=tuned[L][0])
+            out.append(tc.make_job(L, prm, e, m, o))
+        return out
+
+    ws = tc.alloc_workspace(tc.run_jobs_workspace_bytes(jobs_of(0)))
+    qc = sum(3 * L ** 3 * (L + 1) * S for L, _ in specs)
+    hist = {f"L={L} p={p}": [0] * 8 for L, p in specs}
+
+    def timed(flags, tag, count):
+        t_all = 0.0
+        for k in range(warmup + steps):
+            for e, _, _ in bufs:
+                e.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tc.run_jobs(jobs_of(k), ws, flags)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if k >= warmup:
+                t_all += dt
+                if count:
+                    for (L, p), (_, m, _) in zip(specs, bufs):
+                        hb = torch.bincount(m.long(), minlength=8).tolist()
+                        h = hist[f"L={L} p={p}"]
+                        for i in range(8):
+                            h[i] += hb[i]
+            log(f"[bench] c3 {tag} step {k}: {dt * 1e3:.1f} ms")
+        return t_all
+
+    wall = timed(tc.JOBS_CONCURRENT | tc.JOBS_GRAPH, "graph", True)
+    wall_seq = timed(0, "sequential", False)
+    # roofline of the dominant kernel from one timed run of the largest job
+    L = max(cfg["Ls"])
+    lat = tc.make_lattice(L)
+    prm = tc.make_run_params(0.055, 0.055, L, cfg["bp"], cfg["sweeps"], cfg["mask"], n_shots=S,
+                             seed=1, batch_shots=tuned[L][1], bp_tile=tuned[L][0])
+    w1 = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
+    e, m, o = bufs[-1]
+    e.zero_()
+    t = tc.run_cycles_timed(lat, prm, e, m, o, w1)
+    per_class = t.as_dict()
+    batch = tuned[L][1] if tuned[L][1] else 64 * W
+    roof = roofline(per_class, lat.n_edges, min(batch, 64 * W), lat.n_sites, "c3",
+                    shots_padded=64 * W)
+    roof["measured_on"] = f"L={L} job, p=0.055, {S} shots, timed separately"
+    N = S * steps
+    ler = {k: {"axis_x": sum(h[i] for i in range(8) if i & 1) / N,
+               "any_axis": sum(h[1:]) / N} for k, h in hist.items()}
+    return {
+        "metric": "decoded qubit-cycles/s at fixed logical error rate; CNN-prior vs plain "
+                  "BP+p-flip",
+        "value": qc * steps / wall,
+        "unit": "qubit-cycles/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (phenomenological noise drawn from Philox counters, seed 1)",
+        "config": {"workload": f"batched: L in {cfg['Ls']} x p=q in {cfg['ps']}, L+1 cycles, "
+                               f"BP{cfg['bp']} + {cfg['sched']}, one graph per step",
+                   "jobs": len(specs), "shots_per_job_per_step": S, "shots_per_job": N,
+                   "decoder": "plain p-BP",
+                   "autotuned": {str(L): {"bp_tile": v[0], "batch_shots": v[1]}
+                                 for L, v in tuned.items()},
+                   "parallelism": "jobs on 8 concurrent streams inside one HIP graph; shots "
+                                  "bit-sliced 64 per word"},
+        "roofline": roof,
+        "cpu_baseline": None,
+        "comparison": {"decoder": "same jobs, one stream, no graph",
+                       "value": qc * steps / wall_seq, "unit": "qubit-cycles/s",
+                       "ms_per_step": wall_seq / steps * 1e3},
+        "ler": ler,
+    }
 
 
 def main():
@@ -326,6 +441,14 @@ def main():
     cfg = dict(WORKLOADS[args.workload])
     if args.shots:
         cfg["shots"] = args.shots
+    if args.workload == "c3":
+        out = run_c3(args, cfg, tc)
+        if not args.no_cpu_baseline:
+            log("[bench] timing the oracle on the host")
+            out["cpu_baseline"] = cpu_baseline(dict(cfg, L=12, ps=[0.055], noisy=12),
+                                               args.cpu_seconds)
+        print(json.dumps(out), flush=True)
+        return
     if args.L:
         cfg["L"] = args.L
         if args.noisy_cycles is None:

@@ -261,6 +261,54 @@ int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* pr
                               int32_t* odd_out, void* ws, size_t ws_bytes, void* stream,
                               tc3d_timing* timing);
 
+/* -------------------------------------------------------- batched jobs
+ * Many experiments of Sections 3-4 at once: any mix of lattice sizes, error
+ * rates, cycle counts, decoders and seeds (the sweeps behind Figs. 2, 5, 6
+ * and Table 1 are such mixes). Every job is exactly tc3d_run_cycles on its
+ * own buffers, so its results do not depend on the other jobs or the flags. */
+typedef struct {
+    int32_t L;               /* lattice size of this job                     */
+    int32_t reserved;        /* zero                                          */
+    tc3d_run_params prm;     /* its experiment                                */
+    uint64_t* err_state;     /* [3L^3][ceil(n_shots/64)], in/out              */
+    uint8_t* mask_out;       /* [n_shots]                                     */
+    int32_t* odd_out;        /* [n_shots][3] or NULL                          */
+} tc3d_job;
+
+enum {
+    TC3D_JOBS_CONCURRENT = 1, /* each job on its own stream branch, so the
+                                 kernels of small jobs overlap               */
+    TC3D_JOBS_GRAPH = 2       /* capture every launch of every job into one
+                                 HIP graph and launch that graph once        */
+};
+
+/* Workspace of tc3d_run_jobs: the sum of the jobs' run workspaces (each
+ * rounded up to 256 bytes), 0 for invalid input. */
+size_t tc3d_run_jobs_workspace_bytes(const tc3d_job* jobs, int32_t n_jobs);
+/* Runs n_jobs (1 .. 4096) jobs, all validated before anything is enqueued.
+ * Ordered after prior work on `stream`; blocks until every job is done (the
+ * graph and the job streams are released before returning). */
+int tc3d_run_jobs(const tc3d_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                  int32_t flags, void* stream);
+
+/* Autotuning of the knobs that never change results: the BP traversal tile
+ * (bp_tile) and the shots decoded together (batch_shots). Each candidate
+ * decodes the first probe_cycles noisy cycles of *prm's shots (timed with
+ * HIP events, after one untimed warm-up run) and the fastest is written back
+ * into prm->bp_tile and prm->batch_shots. The candidates tried (at most
+ * max_out are reported; *n_out = their number) are returned with their time.
+ * Workspace: tc3d_autotune_workspace_bytes. Blocks until done. */
+typedef struct {
+    int32_t bp_tile;
+    int32_t reserved;
+    int64_t batch_shots;
+    double ms;
+} tc3d_tune_choice;
+size_t tc3d_autotune_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);
+int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_cycles,
+                  void* ws, size_t ws_bytes, tc3d_tune_choice* out, int32_t max_out,
+                  int32_t* n_out, void* stream);
+
 /* Human-readable text of a return code. */
 const char* tc3d_strerror(int code);
 

@@ -60,6 +60,21 @@ class Timing(ctypes.Structure):
                 for i, k in enumerate(KERNEL_CLASSES)}
 
 
+class Job(ctypes.Structure):
+    """One experiment of a batched call (tc3d_job)."""
+    _fields_ = [("L", ctypes.c_int32), ("reserved", ctypes.c_int32), ("prm", RunParams),
+                ("err_state", ctypes.c_void_p), ("mask_out", ctypes.c_void_p),
+                ("odd_out", ctypes.c_void_p)]
+
+
+class TuneChoice(ctypes.Structure):
+    _fields_ = [("bp_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("batch_shots", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+JOBS_CONCURRENT = 1
+JOBS_GRAPH = 2
+
 _lib = None
 
 
@@ -103,6 +118,11 @@ def lib():
         "tc3d_run_cycles_cnn": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, vp, sz, vp]),
         "tc3d_run_cycles_cnn_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, vp, sz, vp,
                                                      ctypes.POINTER(Timing)]),
+        "tc3d_run_jobs_workspace_bytes": (sz, [ctypes.POINTER(Job), i32]),
+        "tc3d_run_jobs": (ctypes.c_int, [ctypes.POINTER(Job), i32, vp, sz, i32, vp]),
+        "tc3d_autotune_workspace_bytes": (sz, [lat, prm]),
+        "tc3d_autotune": (ctypes.c_int, [lat, prm, i32, vp, sz, ctypes.POINTER(TuneChoice), i32,
+                                         ctypes.POINTER(i32), vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -309,3 +329,55 @@ def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots,
 
 
 __all__.append("make_run_params")
+
+
+# --------------------------------------------------------------- batched jobs
+def make_job(L: int, prm: RunParams, err_state, mask_out, odd_out=None) -> Job:
+    def addr(t):
+        p = _ptr(t)
+        return None if p is None else p.value
+    return Job(L=int(L), reserved=0, prm=prm, err_state=addr(err_state),
+               mask_out=addr(mask_out), odd_out=addr(odd_out))
+
+
+def _job_array(jobs):
+    arr = (Job * len(jobs))(*jobs)
+    return arr, len(jobs)
+
+
+def run_jobs_workspace_bytes(jobs) -> int:
+    arr, n = _job_array(jobs)
+    b = int(lib().tc3d_run_jobs_workspace_bytes(arr, n))
+    if b == 0:
+        raise Tc3dError("run_jobs_workspace_bytes: invalid jobs")
+    return b
+
+
+def run_jobs(jobs, ws, flags=JOBS_CONCURRENT | JOBS_GRAPH, stream=None):
+    """Runs every job (blocking); each equals run_cycles on its own buffers."""
+    arr, n = _job_array(jobs)
+    _check(lib().tc3d_run_jobs(arr, n, _ptr(ws), ws.numel() * ws.element_size(), int(flags),
+                               _stream(stream)), "run_jobs")
+
+
+def autotune_workspace_bytes(lat, prm: RunParams) -> int:
+    b = int(lib().tc3d_autotune_workspace_bytes(ctypes.byref(lat), ctypes.byref(prm)))
+    if b == 0:
+        raise Tc3dError("autotune_workspace_bytes: invalid lattice or parameters")
+    return b
+
+
+def autotune(lat, prm: RunParams, ws, probe_cycles=2, stream=None):
+    """Times the candidate (bp_tile, batch_shots) settings on the first
+    probe_cycles cycles of prm's shots and writes the fastest into prm.
+    Returns the list of (bp_tile, batch_shots, ms) tried."""
+    out = (TuneChoice * 64)()
+    n = ctypes.c_int32(0)
+    _check(lib().tc3d_autotune(ctypes.byref(lat), ctypes.byref(prm), int(probe_cycles), _ptr(ws),
+                               ws.numel() * ws.element_size(), out, 64, ctypes.byref(n),
+                               _stream(stream)), "autotune")
+    return [(out[i].bp_tile, out[i].batch_shots, out[i].ms) for i in range(min(n.value, 64))]
+
+
+__all__ += ["Job", "TuneChoice", "JOBS_CONCURRENT", "JOBS_GRAPH", "make_job",
+            "run_jobs_workspace_bytes", "run_jobs", "autotune_workspace_bytes", "autotune"]

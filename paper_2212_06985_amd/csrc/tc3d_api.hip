@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "tc3d_internal.hpp"
 
@@ -231,9 +232,10 @@ size_t run_ws_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t
 }
 
 // packed == nullptr: the paper's BP prior; else the CNN prior every cycle.
-int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
-             uint64_t* err, uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes,
-             const Ctx& c) {
+// Every argument check of run_impl, without launching anything.
+int run_validate(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
+                 const uint64_t* err, const uint8_t* mask, const int32_t* odd, const void* ws,
+                 size_t ws_bytes) {
     int rc = check_run(lat, prm);
     if (rc) return rc;
     const bool cnn = packed != nullptr;
@@ -242,10 +244,21 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
     if (!err || !mask) return TC3D_EINVAL;
     if (!aligned(err, 8) || (odd && !aligned(odd, 4)) || (cnn && !aligned(packed, 256)))
         return TC3D_EALIGN;
-    int64_t nb = 0;
-    const size_t need = run_ws_bytes(lat, prm, &nb, cnn);
+    const size_t need = run_ws_bytes(lat, prm, nullptr, cnn);
     if (!ws || ws_bytes < need) return TC3D_EWORKSPACE;
     if (!aligned(ws, 256)) return TC3D_EALIGN;
+    return TC3D_OK;
+}
+
+int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
+             uint64_t* err, uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes,
+             const Ctx& c) {
+    int rc = run_validate(lat, prm, packed, err, mask, odd, ws, ws_bytes);
+    if (rc) return rc;
+    if (prm->n_shots == 0) return TC3D_OK;
+    const bool cnn = packed != nullptr;
+    int64_t nb = 0;
+    (void)run_ws_bytes(lat, prm, &nb, cnn);
     const Geo g = geo_of(lat);
     const int64_t W = words_of(prm->n_shots);
     const int64_t rows = lat->n_edges;
@@ -576,6 +589,181 @@ int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* pr
     int rc = run_impl(lat, prm, packed, err_state, mask_out, odd_out, ws, ws_bytes, c);
     int rc2 = tm.finish(timing);
     return rc ? rc : rc2;
+}
+
+// ------------------------------------------------------------ batched jobs
+static constexpr int32_t kMaxJobs = 4096;
+static constexpr int kMaxJobStreams = 8;
+
+size_t tc3d_run_jobs_workspace_bytes(const tc3d_job* jobs, int32_t n_jobs) {
+    if (!jobs || n_jobs <= 0 || n_jobs > kMaxJobs) return 0;
+    size_t b = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        tc3d_lattice lat;
+        if (tc3d_make_lattice(jobs[i].L, &lat) || check_run(&lat, &jobs[i].prm)) return 0;
+        b += round_up(run_ws_bytes(&lat, &jobs[i].prm, nullptr, false), 256);
+    }
+    return b;
+}
+
+namespace {
+// Streams and events of one tc3d_run_jobs call, released on every exit path.
+struct JobStreams {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[1 + j]: join of stream j
+    ~JobStreams() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto x : s)
+            if (x) (void)hipStreamDestroy(x);
+    }
+};
+}  // namespace
+
+int tc3d_run_jobs(const tc3d_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                  int32_t flags, void* stream) {
+    if (!jobs || n_jobs <= 0 || n_jobs > kMaxJobs) return TC3D_EINVAL;
+    if (flags & ~(TC3D_JOBS_CONCURRENT | TC3D_JOBS_GRAPH)) return TC3D_EINVAL;
+    if (!ws || !aligned(ws, 256)) return ws ? TC3D_EALIGN : TC3D_EWORKSPACE;
+    // validate everything before the first launch (nothing half-enqueued,
+    // nothing half-captured)
+    std::vector<tc3d_lattice> lats((size_t)n_jobs);
+    std::vector<size_t> off((size_t)n_jobs), len((size_t)n_jobs);
+    size_t total = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const tc3d_job& j = jobs[i];
+        if (j.reserved != 0 || tc3d_make_lattice(j.L, &lats[i])) return TC3D_EINVAL;
+        int rc = check_run(&lats[i], &j.prm);
+        if (rc) return rc;
+        len[i] = round_up(run_ws_bytes(&lats[i], &j.prm, nullptr, false), 256);
+        off[i] = total;
+        total += len[i];
+        if (total > ws_bytes) return TC3D_EWORKSPACE;
+        rc = run_validate(&lats[i], &j.prm, nullptr, j.err_state, j.mask_out, j.odd_out,
+                          (char*)ws + off[i], len[i]);
+        if (rc) return rc;
+    }
+    const hipStream_t origin = (hipStream_t)stream;
+    const bool graph = (flags & TC3D_JOBS_GRAPH) != 0;
+    const int n_str = (flags & TC3D_JOBS_CONCURRENT) ? std::min(n_jobs, kMaxJobStreams) : 1;
+    // stream 0 of js.s is the capture stream in graph mode (a capture cannot
+    // start on the legacy default stream, which `stream` may be)
+    JobStreams js;
+    js.s.assign((size_t)n_str + 1, nullptr);
+    js.ev.assign((size_t)n_str + 1, nullptr);
+    for (auto& x : js.s)
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return TC3D_EHIP;
+    for (auto& e : js.ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return TC3D_EHIP;
+    const hipStream_t head = graph ? js.s[0] : origin;
+    if (graph && hipStreamBeginCapture(head, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return TC3D_EHIP;
+    int rc = TC3D_OK;
+    // fork: every job stream starts after the work already on `head`
+    if (hipEventRecord(js.ev[0], head) != hipSuccess) rc = TC3D_EHIP;
+    for (int k = 1; k <= n_str && !rc; ++k)
+        if (hipStreamWaitEvent(js.s[k], js.ev[0], 0) != hipSuccess) rc = TC3D_EHIP;
+    for (int32_t i = 0; i < n_jobs && !rc; ++i) {
+        const tc3d_job& j = jobs[i];
+        const Ctx c{js.s[1 + (size_t)(i % n_str)], nullptr};
+        rc = run_impl(&lats[i], &j.prm, nullptr, j.err_state, j.mask_out, j.odd_out,
+                      (char*)ws + off[i], len[i], c);
+    }
+    // join: `head` continues after every job
+    for (int k = 1; k <= n_str; ++k) {
+        if (hipEventRecord(js.ev[k], js.s[k]) != hipSuccess && !rc) rc = TC3D_EHIP;
+        if (hipStreamWaitEvent(head, js.ev[k], 0) != hipSuccess && !rc) rc = TC3D_EHIP;
+    }
+    if (graph) {
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(head, &g) != hipSuccess && !rc) rc = TC3D_EHIP;
+        hipGraphExec_t ex = nullptr;
+        if (!rc && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) rc = TC3D_EHIP;
+        if (!rc && hipGraphLaunch(ex, origin) != hipSuccess) rc = TC3D_EHIP;
+        if (hipStreamSynchronize(origin) != hipSuccess && !rc) rc = TC3D_EHIP;
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (hipStreamSynchronize(origin) != hipSuccess && !rc) rc = TC3D_EHIP;
+    return rc;
+}
+
+// ------------------------------------------------------------- autotuning
+size_t tc3d_autotune_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm) {
+    if (!lattice_ok(lat) || !prm || check_run(lat, prm) || prm->n_shots <= 0) return 0;
+    tc3d_run_params p = *prm;
+    p.batch_shots = 0;
+    return plane_bytes(lat, words_of(prm->n_shots)) + round_up((size_t)prm->n_shots, 256) +
+           round_up(run_ws_bytes(lat, &p, nullptr, false), 256);
+}
+
+int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_cycles,
+                  void* ws, size_t ws_bytes, tc3d_tune_choice* out, int32_t max_out,
+                  int32_t* n_out, void* stream) {
+    if (!lattice_ok(lat) || !prm || probe_cycles < 1 || probe_cycles > 64 || max_out < 0 ||
+        (max_out > 0 && !out))
+        return TC3D_EINVAL;
+    int rc = check_run(lat, prm);
+    if (rc) return rc;
+    if (prm->n_shots <= 0) return TC3D_EINVAL;
+    if (!ws || ws_bytes < tc3d_autotune_workspace_bytes(lat, prm)) return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t W = words_of(prm->n_shots);
+    char* base = (char*)ws;
+    uint64_t* err = (uint64_t*)base;
+    uint8_t* mask = (uint8_t*)(base + plane_bytes(lat, W));
+    char* rws = (char*)mask + round_up((size_t)prm->n_shots, 256);
+    const size_t rws_bytes = ws_bytes - (size_t)(rws - base);
+
+    tc3d_run_params probe = *prm;
+    probe.noisy_cycles = probe_cycles;
+    probe.perfect_final = 0;
+    probe.batch_shots = 0;
+    int64_t nb_auto = 0;
+    (void)run_ws_bytes(lat, &probe, &nb_auto, false);
+    // candidates: traversal tiles, then batches of the automatic size, 1/2, 1/4
+    std::vector<int32_t> tiles{0};
+    if (prm->bp_iters > 0)
+        for (int32_t t : {4, 8, 12, 16, 24, 32})
+            if (t < lat->L) tiles.push_back(t);
+    std::vector<int64_t> batches;
+    for (int64_t b : {nb_auto, nb_auto / 2, nb_auto / 4})
+        if (b >= 1 && (batches.empty() || b != batches.back())) batches.push_back(b);
+    const Ctx plain{st, nullptr};
+    // warm-up (first launches, code-object loading)
+    if ((rc = launch_clear(plain, Plane{err, W}, lat->n_edges, W))) return rc;
+    if ((rc = run_impl(lat, &probe, nullptr, err, mask, nullptr, rws, rws_bytes, plain)))
+        return rc;
+    double best = 1e300;
+    int32_t best_tile = prm->bp_tile;
+    int64_t best_batch = prm->batch_shots;
+    int32_t n = 0;
+    for (int64_t b : batches) {
+        for (int32_t t : tiles) {
+            probe.bp_tile = t;
+            probe.batch_shots = 64 * b;
+            if ((rc = launch_clear(plain, Plane{err, W}, lat->n_edges, W))) return rc;
+            Timer tm(st);
+            const Ctx c{st, &tm};
+            if ((rc = run_impl(lat, &probe, nullptr, err, mask, nullptr, rws, rws_bytes, c)))
+                return rc;
+            tc3d_timing tmg;
+            if ((rc = tm.finish(&tmg))) return rc;
+            if (n < max_out) out[n] = tc3d_tune_choice{t, 0, 64 * b, tmg.total_ms};
+            ++n;
+            if (tmg.total_ms < best) {
+                best = tmg.total_ms;
+                best_tile = t;
+                best_batch = 64 * b;
+            }
+        }
+    }
+    if (n_out) *n_out = n;
+    prm->bp_tile = best_tile;
+    prm->batch_shots = best_batch;
+    return TC3D_OK;
 }
 
 const char* tc3d_strerror(int code) {

@@ -109,3 +109,31 @@ def test_misaligned_and_missing_buffers(lib):
 def test_strerror(lib):
     assert lib.tc3d_strerror(0) == b"ok"
     assert b"workspace" in lib.tc3d_strerror(-4)
+
+
+def test_batched_jobs_and_autotune_reject_bad_arguments(lib):
+    """Argument errors come back before any stream, event or launch."""
+    import ctypes
+    import paper_2212_06985_amd as tc
+    prm = tc.make_run_params(0.05, 0.05, 2, 20, 6, 0b001001, n_shots=64)
+    good = tc.Job(L=6, reserved=0, prm=prm, err_state=None, mask_out=None, odd_out=None)
+    arr = (tc.Job * 2)(good, good)
+    L = tc.lib()
+    assert L.tc3d_run_jobs_workspace_bytes(arr, 2) > 0
+    assert L.tc3d_run_jobs_workspace_bytes(arr, 0) == 0
+    bad = (tc.Job * 1)(tc.Job(L=2, reserved=0, prm=prm))
+    assert L.tc3d_run_jobs_workspace_bytes(bad, 1) == 0
+    assert L.tc3d_run_jobs(arr, 0, None, 0, 0, None) == -1           # no jobs
+    assert L.tc3d_run_jobs(arr, 2, None, 0, 0, None) == -4           # no workspace
+    assert L.tc3d_run_jobs(arr, 2, None, 0, 8, None) == -1           # unknown flag
+    ws = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced
+    assert L.tc3d_run_jobs(arr, 2, ws, 16, 0, None) == -4            # too small
+    n = L.tc3d_run_jobs_workspace_bytes(arr, 2)
+    assert L.tc3d_run_jobs(arr, 2, ws, n, 0, None) == -1             # missing buffers
+    lat = tc.make_lattice(6)
+    out = (tc.TuneChoice * 4)()
+    cnt = ctypes.c_int32(0)
+    assert L.tc3d_autotune(ctypes.byref(lat), ctypes.byref(prm), 0, ws, 1 << 30, out, 4,
+                           ctypes.byref(cnt), None) == -1            # probe_cycles 0
+    assert L.tc3d_autotune(ctypes.byref(lat), ctypes.byref(prm), 1, None, 0, out, 4,
+                           ctypes.byref(cnt), None) == -4            # no workspace
