@@ -85,10 +85,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+# source files each kernel class is built from (its counters stay valid while
+# these are unchanged)
+KERNEL_SOURCES = {
+    "bp_iter": ["tc3d_bp.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
+    "cnn": ["tc3d_cnn.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
+}
+
+
+def kernel_source_hash(kernel: str = "bp_iter") -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2212_06985_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(KERNEL_SOURCES.get(kernel, os.listdir(csrc))):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -106,7 +114,7 @@ def stored_traffic(kernel: str, workload: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != kernel_source_hash():
+    if vals.get("source_sha256") != kernel_source_hash(kernel):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

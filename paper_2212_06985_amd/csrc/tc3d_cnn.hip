@@ -243,11 +243,10 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
         for (int i = 0; i < NX; ++i)
 #pragma unroll
             for (int mt = 0; mt < NT; ++mt) acc[i][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-        for (int j = 0; j < 9; ++j) {  // (dy, dz) column: j = 3 (dz + 1) + (dy + 1)
+        // the B slabs of (dy, dz) column j: j = 3 (dz + 1) + (dy + 1)
+        auto load_col = [&](int j, bf16x8 (&b)[NB]) {
             const int uy = wrap(yy + j % 3 - 1, L), uz = wrap(zz + j / 3 - 1, L);
             const int64_t pencil = (wrow + (int64_t)L * (uy + (int64_t)L * uz)) * 64;
-            bf16x8 b[NB];
             if constexpr (CIN == 32) {
                 // slabs x0 - 1 .. x0 + NX
 #pragma unroll
@@ -270,6 +269,8 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
                     }
                 }
             }
+        };
+        auto mma_col = [&](int j, const bf16x8 (&b)[NB]) {
             if constexpr (CIN == 32) {
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
@@ -296,6 +297,19 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
                     for (int mt = 0; mt < NT; ++mt)
                         acc[i][mt] =
                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[i], acc[i][mt], 0, 0, 0);
+            }
+        };
+        // software pipeline: the slabs of column j + 1 are in flight while the
+        // matrix cores work on column j
+        bf16x8 b0[NB], b1[NB];
+        load_col(0, b0);
+#pragma unroll
+        for (int j = 0; j < 9; j += 2) {
+            if (j + 1 < 9) load_col(j + 1, b1);
+            mma_col(j, b0);
+            if (j + 1 < 9) {
+                if (j + 2 < 9) load_col(j + 2, b0);
+                mma_col(j + 1, b1);
             }
         }
         // epilogue: lane holds D[channel 16 mt + 4 q + i][shot l0 + r16] of site x0 + i
