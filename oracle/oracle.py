@@ -21,8 +21,12 @@ LIB_PATH = os.path.join(_HERE, "libtc3d_oracle.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(LIB_PATH):
+    """Compile the oracle with gcc (plain -O2, no fast-math), again whenever
+    its source or header is newer than the library."""
+    hdr = os.path.splitext(_SRC)[0] + ".h"
+    stale = not os.path.exists(LIB_PATH) or max(os.path.getmtime(_SRC), os.path.getmtime(hdr)) > \
+        os.path.getmtime(LIB_PATH)
+    if force or stale:
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
@@ -38,7 +42,8 @@ class Params(ctypes.Structure):
         ("noisy_cycles", ctypes.c_int32), ("perfect_final", ctypes.c_int32),
         ("final_qubit_noise", ctypes.c_int32), ("bp_iters", ctypes.c_int32),
         ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("subset_mask", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -65,6 +70,9 @@ def lib():
             "tco_syndrome": (None, [vp, vp, vp, i64, i32]),
             "tco_flip_sweep": (None, [vp, vp, vp, i64]),
             "tco_pflip_sweep": (None, [vp, vp, vp, u64, u32, u32, u64, i64]),
+            "tco_edge_class": (i32, [vp, i64]),
+            "tco_subset_class": (i32, [i32, i32, u32]),
+            "tco_subset_pflip_sweep": (None, [vp, vp, vp, u64, u32, u32, u64, i64, i32]),
             "tco_pflip_sweep_coins": (None, [vp, vp, vp, vp]),
             "tco_sequential_flip": (i64, [vp, vp, vp, i64]),
             "tco_bp_step": (None, [vp, vp, vp, f64, f64, vp, vp, vp]),
@@ -170,6 +178,16 @@ class Oracle:
         _chk(corr, np.uint8)
         S = syn.size // self.n_faces
         lib().tco_pflip_sweep(self._h, _p(syn), _p(corr), seed, cycle, sweep, shot0, S)
+
+    def edge_class(self, edge):
+        return int(lib().tco_edge_class(self._h, int(edge)))
+
+    def subset_pflip_sweep(self, syn, corr, seed, cycle, sweep, edge_class, shot0=0):
+        _chk(syn, np.uint8)
+        _chk(corr, np.uint8)
+        S = syn.size // self.n_faces
+        lib().tco_subset_pflip_sweep(self._h, _p(syn), _p(corr), seed, cycle, sweep, shot0, S,
+                                     int(edge_class))
 
     def pflip_sweep_coins(self, syn, corr, coins):
         _chk(syn, np.uint8, (self.n_faces,))
@@ -282,8 +300,14 @@ _cnn_methods()
 
 
 def make_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, seed=1, p_dec=None,
-                q_dec=None, perfect_final=1, final_qubit_noise=1) -> Params:
+                q_dec=None, perfect_final=1, final_qubit_noise=1, subset_mask=0) -> Params:
     return Params(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                   q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                   perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
-                  bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed)
+                  bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
+                  subset_mask=subset_mask)
+
+
+def subset_class(j, m, cycle):
+    """Edge class of the j-th subset sweep (of m per cycle) in cycle `cycle`."""
+    return int(lib().tco_subset_class(int(j), int(m), int(cycle)))

@@ -278,6 +278,45 @@ void tco_pflip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, uint64
     free(coins);
 }
 
+/* Subset p-flip. Two edges of one class never share a face: a face spanned by
+ * axes a < b holds two a-edges whose b coordinates differ by one and two
+ * b-edges whose a coordinates differ by one, so with L even each pair differs
+ * in the parity that the class records. */
+int32_t tco_edge_class(const tco_lattice* lat, int64_t edge) {
+    const int64_t N = lat->n_sites;
+    const int a = (int)(edge / N);
+    const int64_t v = edge % N;
+    const int L = lat->L;
+    const int c[3] = {(int)(v % L), (int)((v / L) % L), (int)(v / ((int64_t)L * L))};
+    const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
+    return 4 * a + 2 * (c[b0] & 1) + (c[b1] & 1);
+}
+
+int32_t tco_subset_class(int32_t j, int32_t m, uint32_t cycle) {
+    return (int32_t)(((uint64_t)j + (uint64_t)cycle * (uint64_t)m) % 12u);
+}
+
+void tco_subset_pflip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, uint64_t seed,
+                            uint32_t cycle, uint32_t sweep, uint64_t shot0, int64_t n_shots,
+                            int32_t edge_class) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    uint8_t* F = (uint8_t*)malloc(n);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        uint8_t* sy = syn + s * m;
+        for (int64_t b = 0; b < n; ++b) {
+            F[b] = 0;
+            if (tco_edge_class(lat, b) != edge_class) continue;
+            const int unsat = unsat_count(lat, sy, b), sat = 4 - unsat;
+            if (sat < unsat)
+                F[b] = 1;
+            else if (sat == unsat)
+                F[b] = (uint8_t)(tco_coin(seed, (uint32_t)b, cycle, sweep, shot0 + (uint64_t)s) != 0);
+        }
+        apply_flips(lat, F, sy, corr + s * n);
+    }
+    free(F);
+}
+
 /* flip as first stated (Section 3.1): one bit at a time. */
 int64_t tco_sequential_flip(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
                             int64_t max_flips) {
@@ -445,8 +484,13 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
                 for (int64_t i = 0; i < n; ++i) corr[i] = cbp[i];
                 tco_syndrome(lat, cbp, syn, 1, 1);
             }
-            for (int32_t k = 0; k < prm->n_sweeps; ++k) {
-                if ((prm->pflip_mask >> k) & 1u)
+            int32_t n_subset = 0;
+            for (int32_t k = 0; k < prm->n_sweeps; ++k) n_subset += (prm->subset_mask >> k) & 1u;
+            for (int32_t k = 0, j = 0; k < prm->n_sweeps; ++k) {
+                if ((prm->subset_mask >> k) & 1u)
+                    tco_subset_pflip_sweep(lat, syn, corr, prm->seed, (uint32_t)t, (uint32_t)k,
+                                           shot, 1, tco_subset_class(j++, n_subset, (uint32_t)t));
+                else if ((prm->pflip_mask >> k) & 1u)
                     tco_pflip_sweep(lat, syn, corr, prm->seed, (uint32_t)t, (uint32_t)k, shot,
                                     1);
                 else

@@ -42,6 +42,9 @@ typedef struct {
     int32_t n_sweeps;         /* number of flip / p-flip sweeps after BP        */
     uint32_t pflip_mask;      /* bit k set: sweep k is p-flip, else flip        */
     uint64_t seed;            /* Philox key                                     */
+    uint32_t subset_mask;     /* bit k set: sweep k is a subset p-flip sweep on
+                                 the edge class tco_subset_class(j, m, t)        */
+    uint32_t reserved;
 } tco_params;
 
 tco_lattice* tco_lattice_new(int32_t L);
@@ -74,6 +77,16 @@ void tco_pflip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, uint64
 /* One parallel p-flip sweep of a single shot with explicit coins[n_edges]. */
 void tco_pflip_sweep_coins(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
                            const uint8_t* coins);
+/* Subset p-flip (the recovery of Dennis et al. that the footnote of Section
+ * 3.2 contrasts with p-flip): the p-flip rule on one class of qubits no two of
+ * which share a check. Classes (L even): edge e(v,a) is in class
+ * 4a + 2 (v_b mod 2) + (v_c mod 2), b < c the two axes other than a. */
+int32_t tco_edge_class(const tco_lattice* lat, int64_t edge);
+/* Class of the j-th subset sweep (of m per cycle) in cycle t. */
+int32_t tco_subset_class(int32_t j, int32_t m, uint32_t cycle);
+void tco_subset_pflip_sweep(const tco_lattice* lat, uint8_t* syn, uint8_t* corr, uint64_t seed,
+                            uint32_t cycle, uint32_t sweep, uint64_t shot0, int64_t n_shots,
+                            int32_t edge_class);
 /* Sequential flip: flip the lowest-index bit with more unsatisfied than
  * satisfied checks until none is left or max_flips is reached. One shot.
  * Returns the number of flips made. */
