@@ -92,7 +92,7 @@ int tc3d_sample_noise(const tc3d_lattice* lat, uint64_t* plane, int32_t kind, do
 int tc3d_syndrome(const tc3d_lattice* lat, const uint64_t* err, uint64_t* syn,
                   int64_t n_words, int32_t xor_into, void* stream);
 
-/* Scratch needed by one flip or p-flip sweep: one edge plane. */
+/* Scratch needed by one flip, p-flip or subset p-flip sweep: one edge plane. */
 size_t tc3d_sweep_workspace_bytes(const tc3d_lattice* lat, int64_t n_words);
 
 /* flip (Section 3.1) in its parallel form (Section 3.2): every qubit with
@@ -108,6 +108,19 @@ int tc3d_flip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int6
 int tc3d_pflip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
                      uint64_t seed, uint32_t cycle, uint32_t sweep, uint64_t shot0, void* ws,
                      size_t ws_bytes, void* stream);
+
+/* Subset p-flip: the recovery rule of Dennis et al. for the 4D toric code,
+ * which the footnote of Section 3.2 contrasts with p-flip; it acts only on a
+ * set of qubits no two of which share a check. Here the p-flip rule is
+ * applied to the edges of one class (0 <= edge_class < 12): edge e(v,a) has
+ * class 4a + 2 (v_b mod 2) + (v_c mod 2), b < c the two other axes. With L
+ * even (required, else EINVAL) two edges of a class never share a face, so
+ * the sweep equals the rule applied to the class one edge at a time. Coins
+ * as in tc3d_pflip_sweep. */
+int tc3d_subset_pflip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr,
+                            int64_t n_words, uint64_t seed, uint32_t cycle, uint32_t sweep,
+                            uint64_t shot0, int32_t edge_class, void* ws, size_t ws_bytes,
+                            void* stream);
 
 /* Scratch of tc3d_bp_decode: two message buffers of 12 L^3 S_pad floats. */
 size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
@@ -170,7 +183,10 @@ typedef struct {
                                   24 GiB                                         */
     int32_t bp_tile;           /* BP traversal tile edge in sites (a tuning knob
                                   that never changes results); 0 = automatic    */
-    int32_t reserved;          /* zero                                           */
+    uint32_t subset_mask;      /* bit k set: sweep k is a subset p-flip sweep
+                                  (see tc3d_subset_pflip_sweep); the j-th of the
+                                  m such sweeps of cycle t acts on edge class
+                                  (j + t m) mod 12. Needs L even; 0 = none      */
 } tc3d_run_params;
 
 size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);

@@ -17,7 +17,7 @@ import os
 
 __all__ = [
     "Lattice", "RunParams", "Timing", "Tc3dError", "lib", "make_lattice", "sample_noise",
-    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "bp_workspace_bytes",
+    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "subset_pflip_sweep", "bp_workspace_bytes",
     "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
     "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
 ]
@@ -47,7 +47,7 @@ class RunParams(ctypes.Structure):
         ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
         ("seed", ctypes.c_uint64), ("shot0", ctypes.c_uint64),
         ("n_shots", ctypes.c_int64), ("batch_shots", ctypes.c_int64),
-        ("bp_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bp_tile", ctypes.c_int32), ("subset_mask", ctypes.c_uint32),
     ]
 
 
@@ -68,7 +68,7 @@ class Job(ctypes.Structure):
 
 
 class TuneChoice(ctypes.Structure):
-    _fields_ = [("bp_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("bp_tile", ctypes.c_int32), ("subset_mask", ctypes.c_uint32),
                 ("batch_shots", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
@@ -98,6 +98,8 @@ def lib():
         "tc3d_sweep_workspace_bytes": (sz, [lat, i64]),
         "tc3d_flip_sweep": (ctypes.c_int, [lat, vp, vp, i64, vp, sz, vp]),
         "tc3d_pflip_sweep": (ctypes.c_int, [lat, vp, vp, i64, u64, u32, u32, u64, vp, sz, vp]),
+        "tc3d_subset_pflip_sweep": (ctypes.c_int, [lat, vp, vp, i64, u64, u32, u32, u64, i32,
+                                                   vp, sz, vp]),
         "tc3d_bp_workspace_bytes": (sz, [lat, i64]),
         "tc3d_bp_decode": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, i32, vp, vp, vp, sz, vp]),
         "tc3d_bp_step": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, vp, vp, vp, vp]),
@@ -199,6 +201,15 @@ def pflip_sweep(lat, syn, corr, nw, seed, cycle, sweep, shot0, ws, stream=None):
                                   int(cycle), int(sweep), int(shot0), _ptr(ws),
                                   ws.numel() * ws.element_size(), _stream(stream)),
            "pflip_sweep")
+
+
+def subset_pflip_sweep(lat, syn, corr, nw, seed, cycle, sweep, shot0, edge_class, ws,
+                       stream=None):
+    _check(lib().tc3d_subset_pflip_sweep(ctypes.byref(lat), _ptr(syn), _ptr(corr), int(nw),
+                                         int(seed), int(cycle), int(sweep), int(shot0),
+                                         int(edge_class), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)),
+           "subset_pflip_sweep")
 
 
 def bp_workspace_bytes(lat, n_shots) -> int:
@@ -320,12 +331,13 @@ __all__ += ["cnn_param_count", "cnn_packed_bytes", "cnn_pack", "cnn_workspace_by
 
 def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,
                     shot0=0, p_dec=None, q_dec=None, perfect_final=1, final_qubit_noise=1,
-                    batch_shots=0, bp_tile=0) -> RunParams:
+                    batch_shots=0, bp_tile=0, subset_mask=0) -> RunParams:
     return RunParams(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                      q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                      perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                      bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
-                     shot0=shot0, n_shots=n_shots, batch_shots=batch_shots, bp_tile=bp_tile)
+                     shot0=shot0, n_shots=n_shots, batch_shots=batch_shots, bp_tile=bp_tile,
+                     subset_mask=subset_mask)
 
 
 __all__.append("make_run_params")

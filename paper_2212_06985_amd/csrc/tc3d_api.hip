@@ -187,6 +187,10 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
         prm->bp_tile > kMaxL)
         return TC3D_EINVAL;
     if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
+    // subset sweeps: within the schedule, and an edge colouring needs L even
+    if (prm->subset_mask != 0 &&
+        ((prm->n_sweeps < 32 && (prm->subset_mask >> prm->n_sweeps) != 0) || lat->L % 2 != 0))
+        return TC3D_EINVAL;
     if (prm->shot0 % 64 != 0 || prm->batch_shots % 64 != 0) return TC3D_EINVAL;
     if (prm->shot0 + (uint64_t)prm->n_shots >= (1ull << 34)) return TC3D_EINVAL;
     if (prm->bp_iters > 0 && !(prm->p_dec > 0.0 && prm->p_dec < 0.5 && prm->q_dec > 0.0 &&
@@ -311,10 +315,13 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
             } else {
                 if ((rc = launch_clear(c, C, rows, bw))) return rc;
             }
-            for (int32_t k = 0; k < prm->n_sweeps; ++k) {
-                const int pf = (int)((prm->pflip_mask >> k) & 1u);
+            const int n_subset = __builtin_popcount(prm->subset_mask);
+            for (int32_t k = 0, j = 0; k < prm->n_sweeps; ++k) {
+                const bool sub = (prm->subset_mask >> k) & 1u;
+                const int pf = sub ? 1 : (int)((prm->pflip_mask >> k) & 1u);
+                const int cls = sub ? (int)(((uint64_t)j++ + (uint64_t)t * n_subset) % 12u) : -1;
                 if ((rc = launch_sweep_decide(c, g, cS, C, F, bw, pf, gword0, (uint32_t)t,
-                                              (uint32_t)k, prm->seed)))
+                                              (uint32_t)k, prm->seed, cls)))
                     return rc;
                 if ((rc = launch_syndrome(c, g, cF, S, bw, 1, 0u, 0, 0, 0))) return rc;
             }
@@ -379,7 +386,7 @@ size_t tc3d_sweep_workspace_bytes(const tc3d_lattice* lat, int64_t n_words) {
 
 static int sweep_common(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int64_t n_words,
                         int pflip, uint64_t seed, uint32_t cycle, uint32_t sweep, uint64_t shot0,
-                        void* ws, size_t ws_bytes, void* stream) {
+                        void* ws, size_t ws_bytes, void* stream, int cls = -1) {
     if (!lattice_ok(lat) || n_words < 0 || shot0 % 64 != 0) return TC3D_EINVAL;
     if (n_words == 0) return TC3D_OK;
     if (!syn || !corr) return TC3D_EINVAL;
@@ -390,7 +397,8 @@ static int sweep_common(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, 
     const Geo g = geo_of(lat);
     uint64_t* F = (uint64_t*)ws;
     int rc = launch_sweep_decide(c, g, CPlane{syn, n_words}, Plane{corr, n_words},
-                                 Plane{F, n_words}, n_words, pflip, shot0 / 64, cycle, sweep, seed);
+                                 Plane{F, n_words}, n_words, pflip, shot0 / 64, cycle, sweep, seed,
+                                 cls);
     if (rc) return rc;
     return launch_syndrome(c, g, CPlane{F, n_words}, Plane{syn, n_words}, n_words, 1, 0u, 0, 0, 0);
 }
@@ -405,6 +413,16 @@ int tc3d_pflip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr, int
                      size_t ws_bytes, void* stream) {
     return sweep_common(lat, syn, corr, n_words, 1, seed, cycle, sweep, shot0, ws, ws_bytes,
                         stream);
+}
+
+int tc3d_subset_pflip_sweep(const tc3d_lattice* lat, uint64_t* syn, uint64_t* corr,
+                            int64_t n_words, uint64_t seed, uint32_t cycle, uint32_t sweep,
+                            uint64_t shot0, int32_t edge_class, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!lattice_ok(lat) || lat->L % 2 != 0 || edge_class < 0 || edge_class >= 12)
+        return TC3D_EINVAL;
+    return sweep_common(lat, syn, corr, n_words, 1, seed, cycle, sweep, shot0, ws, ws_bytes,
+                        stream, edge_class);
 }
 
 size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots) {

@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const uint64_t* __restrict__ s
                                                   uint64_t* __restrict__ corr, int64_t ld_c,
                                                   uint64_t* __restrict__ fpl, int64_t ld_f,
                                                   int64_t nw, int L, int N, int pflip,
-                                                  uint64_t word0, uint32_t cycle, uint32_t sweep,
-                                                  uint32_t k0, uint32_t k1) {
+                                                  int cls, uint64_t word0, uint32_t cycle,
+                                                  uint32_t sweep, uint32_t k0, uint32_t k1) {
     const int64_t G = gridDim.x;
     const int64_t blk = xcd_block(blockIdx.x, G);
     const int64_t idx = blk * kBlock + threadIdx.x;
@@ -62,8 +62,18 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const uint64_t* __restrict__ s
     if (idx >= rows * nw) return;
     const int64_t e = idx / nw, w = idx - e * nw;
     const int ax = (int)(e / N), v = (int)(e - (int64_t)ax * N);
+    const Coord cv = coord_of(v, L);
+    if (cls >= 0) {
+        // subset sweep: only edges of class cls = 4 ax + 2 (v_b & 1) + (v_c & 1),
+        // b < c the other two axes, may flip
+        const int cb = ax == 0 ? cv.y : cv.x, cc = ax == 2 ? cv.y : cv.z;
+        if (4 * ax + 2 * (cb & 1) + (cc & 1) != cls) {
+            fpl[e * ld_f + w] = 0;
+            return;
+        }
+    }
     int f[4];
-    edge_faces(ax, coord_of(v, L), L, N, f);
+    edge_faces(ax, cv, L, N, f);
     const uint64_t a = syn[f[0] * ld_s + w], b = syn[f[1] * ld_s + w];
     const uint64_t c = syn[f[2] * ld_s + w], d = syn[f[3] * ld_s + w];
     const uint64_t ab = a & b, cd = c & d;
@@ -170,14 +180,14 @@ int launch_syndrome(const Ctx& c, Geo g, CPlane src, Plane dst, int64_t nw, int 
 
 int launch_sweep_decide(const Ctx& c, Geo g, CPlane syn, Plane corr, Plane fplane, int64_t nw,
                         int pflip, uint64_t word0, uint32_t cycle, uint32_t sweep,
-                        uint64_t seed) {
+                        uint64_t seed, int cls) {
     if (nw == 0) return TC3D_OK;
     const int64_t rows = 3 * (int64_t)g.N;
     int rc = before_launch(c, TC3D_K_SWEEP);
     if (rc) return rc;
     k_sweep<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(
-        syn.p, syn.ld, corr.p, corr.ld, fplane.p, fplane.ld, nw, g.L, g.N, pflip, word0, cycle,
-        sweep, (uint32_t)seed, (uint32_t)(seed >> 32));
+        syn.p, syn.ld, corr.p, corr.ld, fplane.p, fplane.ld, nw, g.L, g.N, pflip, cls, word0,
+        cycle, sweep, (uint32_t)seed, (uint32_t)(seed >> 32));
     return after_launch(c);
 }
 

@@ -63,9 +63,11 @@ int launch_noise(const Ctx& c, Geo g, Plane plane, int64_t nw, uint64_t word0, u
 int launch_syndrome(const Ctx& c, Geo g, CPlane src, Plane dst, int64_t nw, int xor_into,
                     uint32_t th_meas, uint64_t word0, uint32_t cycle, uint64_t seed);
 // F = flip (pflip=0) or p-flip decisions; corr ^= F; F written to fplane.
+// One flip / p-flip decision pass; cls >= 0 restricts it to one edge class
+// (the subset sweep), cls < 0 lets every edge flip.
 int launch_sweep_decide(const Ctx& c, Geo g, CPlane syn, Plane corr, Plane fplane, int64_t nw,
                         int pflip, uint64_t word0, uint32_t cycle, uint32_t sweep,
-                        uint64_t seed);
+                        uint64_t seed, int cls = -1);
 // dst ^= src over rows x nw.
 int launch_xor(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw);
 // dst = 0 over rows x nw.

@@ -45,6 +45,17 @@ def flip_mask(n_a: int, lambda_p: int) -> int:
     return sum(1 << k for k in range(n_a) if (k + 1) % lambda_p == 0)
 
 
+def parse_schedule(sched: str):
+    """A sweep schedule written as letters, one per sweep: F flip, P p-flip,
+    C subset p-flip. Returns (n_sweeps, pflip_mask, subset_mask)."""
+    sched = sched.strip().upper()
+    if not sched or set(sched) - set("FPC") or len(sched) > 32:
+        raise ValueError(f"bad schedule {sched!r}: use up to 32 letters F, P, C")
+    pm = sum(1 << k for k, c in enumerate(sched) if c == "P")
+    sm = sum(1 << k for k, c in enumerate(sched) if c == "C")
+    return len(sched), pm, sm
+
+
 def decoder_params(decoder: str, n_a: int = 1, lambda_p: int = 0, bp_iters: int | None = None):
     """(bp_iters, n_sweeps, pflip_mask) of a named decoder."""
     if decoder == "flip":
@@ -57,13 +68,16 @@ def decoder_params(decoder: str, n_a: int = 1, lambda_p: int = 0, bp_iters: int 
 
 
 def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=0,
-               bp_iters=None, chunk_shots=None, shot0=0, q_dec=None):
+               bp_iters=None, chunk_shots=None, shot0=0, q_dec=None, schedule=None):
     """Logical error statistics of `shots` independent memory runs.
 
     Returns the mask histogram (index = bit x | bit y << 1 | bit z << 2), the
     per-axis failure counts, the majority-vote ties and the GPU time."""
     import torch
     it, ns, mask_bits = decoder_params(decoder, n_a, lambda_p, bp_iters)
+    sub_bits = 0
+    if schedule:
+        ns, mask_bits, sub_bits = parse_schedule(schedule)
     lat = tc.make_lattice(L)
     chunk = shots if chunk_shots is None else min(shots, chunk_shots)
     chunk = 64 * tc.n_words(chunk)
@@ -78,7 +92,8 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
     while done < shots:
         n = min(chunk, shots - done)
         prm = tc.make_run_params(p, p, cycles, it, ns, mask_bits, n_shots=n, seed=seed,
-                                 shot0=shot0 + done, perfect_final=0, q_dec=q_dec)
+                                 shot0=shot0 + done, perfect_final=0, q_dec=q_dec,
+                                 subset_mask=sub_bits)
         need = tc.run_workspace_bytes(lat, prm)
         if ws is None or ws.numel() < need:
             ws = tc.alloc_workspace(need)
@@ -92,7 +107,7 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
     fails = [int(hist[[k for k in range(8) if (k >> d) & 1]].sum()) for d in range(3)]
     return {"L": L, "p": p, "cycles": cycles, "decoder": decoder, "n_a": n_a,
             "lambda_p": lambda_p, "bp_iters": it, "shots": shots, "seed": seed,
-            "q_dec": p if q_dec is None else q_dec,
+            "q_dec": p if q_dec is None else q_dec, "schedule": schedule,
             "hist": hist.tolist(), "fails": fails, "ties": ties, "gpu_ms": ms,
             "qubit_cycles_per_s": 3 * L ** 3 * cycles * shots / (ms * 1e-3)}
 
@@ -155,13 +170,13 @@ def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500):
 
 
 def threshold(decoder, Ls, ps, cycles, shots, seed=1, n_a=1, lambda_p=0, bp_iters=None,
-              pooled=False, log=print, q_dec=None):
+              pooled=False, log=print, q_dec=None, schedule=None):
     rows = []
     for L in Ls:
         for p in ps:
             t0 = time.perf_counter()
             r = memory_run(L, p, cycles, decoder, shots, seed, n_a, lambda_p, bp_iters,
-                           q_dec=q_dec)
+                           q_dec=q_dec, schedule=schedule)
             f, s = pfail_pooled(r) if pooled else pfail(r)
             r["pfail"], r["pfail_sigma"] = f, s
             rows.append(r)
@@ -203,6 +218,9 @@ def main():
     th.add_argument("--seed", type=int, default=1)
     th.add_argument("--pooled", action="store_true",
                     help="pool the three logical qubits' failures")
+    th.add_argument("--schedule", default=None,
+                    help="sweep schedule letters (F flip, P p-flip, C subset p-flip); "
+                         "overrides the decoder's own")
     th.add_argument("--q-dec", type=float, default=None,
                     help="measurement-error rate BP assumes (default: q = p)")
     th.add_argument("--out", default=None)
@@ -212,8 +230,10 @@ def main():
         return
     res = threshold(args.decoder, args.L, args.p, args.cycles, args.shots, args.seed, args.n_a,
                     args.lambda_p, args.bp_iters, args.pooled,
-                    log=lambda m: print(m, flush=True), q_dec=args.q_dec)
+                    log=lambda m: print(m, flush=True), q_dec=args.q_dec,
+                    schedule=args.schedule)
     print(json.dumps({"fit": res["fit"], "decoder": res["decoder"], "n_a": res["n_a"],
+                      "schedule": args.schedule,
                       "lambda_p": res["lambda_p"], "cycles": res["cycles"]}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

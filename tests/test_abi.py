@@ -137,3 +137,20 @@ def test_batched_jobs_and_autotune_reject_bad_arguments(lib):
                            ctypes.byref(cnt), None) == -1            # probe_cycles 0
     assert L.tc3d_autotune(ctypes.byref(lat), ctypes.byref(prm), 1, None, 0, out, 4,
                            ctypes.byref(cnt), None) == -4            # no workspace
+
+
+def test_subset_sweeps_need_even_L_and_a_schedule_slot(lib):
+    import ctypes
+    import paper_2212_06985_amd as tc
+    L = tc.lib()
+    odd = tc.make_lattice(5)
+    even = tc.make_lattice(6)
+    prm = tc.make_run_params(0.03, 0.03, 2, 0, 5, 0, n_shots=64, subset_mask=0b00100)
+    assert L.tc3d_run_workspace_bytes(ctypes.byref(even), ctypes.byref(prm)) > 0
+    assert L.tc3d_run_workspace_bytes(ctypes.byref(odd), ctypes.byref(prm)) == 0
+    beyond = tc.make_run_params(0.03, 0.03, 2, 0, 5, 0, n_shots=64, subset_mask=0b100000)
+    assert L.tc3d_run_workspace_bytes(ctypes.byref(even), ctypes.byref(beyond)) == 0
+    ws = ctypes.c_void_p(1 << 20)
+    for lat, cls in ((odd, 0), (even, -1), (even, 12)):
+        assert L.tc3d_subset_pflip_sweep(ctypes.byref(lat), ws, ws, 1, 1, 0, 0, 0, cls, ws,
+                                         1 << 30, None) == -1

@@ -50,3 +50,15 @@ def test_pfail_sigma():
     assert f == 0.128 and abs(s - np.sqrt(0.128 * 0.872 / 1000)) < 1e-15
     f3, s3 = ex.pfail_pooled(r)
     assert abs(f3 - 0.4 / 3) < 1e-15 and s3 < s
+
+
+def test_schedule_strings():
+    assert ex.parse_schedule("PFFPFF") == (6, 0b001001, 0)
+    assert ex.parse_schedule("cffcff") == (6, 0, 0b001001)
+    assert ex.parse_schedule("FFPFF") == (5, ex.flip_mask(5, 3), 0)
+    for bad in ("", "PFX", "F" * 33):
+        try:
+            ex.parse_schedule(bad)
+        except ValueError:
+            continue
+        raise AssertionError(bad)
