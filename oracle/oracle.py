@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("final_qubit_noise", ctypes.c_int32), ("bp_iters", ctypes.c_int32),
         ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
         ("seed", ctypes.c_uint64), ("subset_mask", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("bp_meta", ctypes.c_int32),
     ]
 
 
@@ -71,6 +71,8 @@ def lib():
             "tco_flip_sweep": (None, [vp, vp, vp, i64]),
             "tco_pflip_sweep": (None, [vp, vp, vp, u64, u32, u32, u64, i64]),
             "tco_edge_class": (i32, [vp, i64]),
+            "tco_bp_meta_step": (None, [vp, vp, f64, f64, vp, vp, vp, vp, vp, vp, vp]),
+            "tco_bp_meta_decode": (None, [vp, vp, i64, f64, f64, i32, vp, vp]),
             "tco_subset_class": (i32, [i32, i32, u32]),
             "tco_subset_pflip_sweep": (None, [vp, vp, vp, u64, u32, u32, u64, i64, i32]),
             "tco_pflip_sweep_coins": (None, [vp, vp, vp, vp]),
@@ -223,6 +225,31 @@ class Oracle:
                             _p(post))
         return corr, post
 
+    def bp_meta_step(self, syn, p_dec, q_dec, state=None):
+        """One meta-check BP iteration of one shot; state = (nu [m][4],
+        lambda [m], kappa [N][6]) or None for the first. Returns (state, post)."""
+        _chk(syn, np.uint8, (self.n_faces,))
+        nu = np.zeros((self.n_faces, 4), np.float64)
+        lam = np.zeros(self.n_faces, np.float64)
+        kap = np.zeros((self.n_sites, 6), np.float64)
+        post = np.zeros(self.n_edges, np.float64)
+        if state is None:
+            a = b = c = None
+        else:
+            a, b, c = (np.ascontiguousarray(x, np.float64) for x in state)
+            assert a.shape == nu.shape and b.shape == lam.shape and c.shape == kap.shape
+        lib().tco_bp_meta_step(self._h, _p(syn), p_dec, q_dec, _p(a), _p(b), _p(c), _p(nu),
+                               _p(lam), _p(kap), _p(post))
+        return (nu, lam, kap), post
+
+    def bp_meta_decode(self, syn, p_dec, q_dec, iters):
+        _chk(syn, np.uint8)
+        S = syn.size // self.n_faces
+        corr = np.zeros((S, self.n_edges), np.uint8)
+        post = np.zeros((S, self.n_edges), np.float64)
+        lib().tco_bp_meta_decode(self._h, _p(syn), S, p_dec, q_dec, iters, _p(corr), _p(post))
+        return corr, post
+
     def logical_check(self, err):
         _chk(err, np.uint8)
         S = err.size // self.n_edges
@@ -300,12 +327,13 @@ _cnn_methods()
 
 
 def make_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, seed=1, p_dec=None,
-                q_dec=None, perfect_final=1, final_qubit_noise=1, subset_mask=0) -> Params:
+                q_dec=None, perfect_final=1, final_qubit_noise=1, subset_mask=0,
+                bp_meta=0) -> Params:
     return Params(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                   q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                   perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                   bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
-                  subset_mask=subset_mask)
+                  subset_mask=subset_mask, bp_meta=bp_meta)
 
 
 def subset_class(j, m, cycle):

@@ -389,6 +389,160 @@ void tco_bp_step(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
     free(mu);
 }
 
+/* ------------------------------------------------- BP with meta-checks */
+
+/* Face slot j (0..5) of cube c (the unit cube at corner site c): the lower
+ * face f(c,n) for j = 2n, the upper face f(c+unit(n), n) for j = 2n+1. */
+static int64_t cube_face(const tco_lattice* lat, int64_t c, int j) {
+    const int32_t L = lat->L;
+    const int n = j / 2;
+    int64_t x = c % L, y = (c / L) % L, z = c / ((int64_t)L * L);
+    if (j & 1) {
+        if (n == 0) x += 1;
+        if (n == 1) y += 1;
+        if (n == 2) z += 1;
+    }
+    return (int64_t)n * lat->n_sites + site_of(L, x, y, z);
+}
+
+/* The two cubes of face f(w,n): the one it is the lower face of (cube w,
+ * slot 2n) and the one it is the upper face of (cube w - unit(n), slot 2n+1). */
+static void face_cubes(const tco_lattice* lat, int64_t f, int64_t cube[2], int slot[2]) {
+    const int32_t L = lat->L;
+    const int n = (int)(f / lat->n_sites);
+    const int64_t w = f % lat->n_sites;
+    int64_t x = w % L, y = (w / L) % L, z = w / ((int64_t)L * L);
+    cube[0] = w;
+    slot[0] = 2 * n;
+    if (n == 0) x -= 1;
+    if (n == 1) y -= 1;
+    if (n == 2) z -= 1;
+    cube[1] = site_of(L, x, y, z);
+    slot[1] = 2 * n + 1;
+}
+
+static double clamp_msg(double x) {
+    return x > TCO_META_CLAMP ? TCO_META_CLAMP : (x < -TCO_META_CLAMP ? -TCO_META_CLAMP : x);
+}
+
+/* One flooding iteration of BP on the factor graph with meta-checks, the
+ * extension Section 4.1 describes and leaves out: besides the qubits and the
+ * checks, one measurement-error variable m_f per check (prior ln((1-q)/q))
+ * and one meta-check per cube, whose six measurement variables must have the
+ * parity of the six measured outcomes (valid syndromes are closed, so the
+ * measured parity of a cube is the parity of its measurement errors).
+ * Messages (LLRs; variable-to-factor ones clamped to +-TCO_META_CLAMP):
+ *   qubit e -> check f     Q  = l0 + sum of the other checks' nu
+ *   meas m_f -> check f    M  = lm + kappa from both cubes of f
+ *   meas m_f -> cube c     R  = lm + lambda_f + kappa from the other cube
+ *   check f -> qubit e     nu = (-1)^{s_f} 2 atanh(tanh(M/2) prod_{e' != e} tanh(Q/2))
+ *   check f -> meas m_f    lambda = (-1)^{s_f} 2 atanh(prod_{e} tanh(Q/2))
+ *   cube c -> meas m_f     kappa = (-1)^{mu_c} 2 atanh(prod_{f' != f} tanh(R/2))
+ *   posterior              l_e = l0 + sum of nu
+ * State: nu [n_faces][4] (member order), lambda [n_faces], kappa [n_sites][6]
+ * (cube slot order); *_in NULL = first iteration (all factor messages 0). */
+void tco_bp_meta_step(const tco_lattice* lat, const uint8_t* syn, double p_dec, double q_dec,
+                      const double* nu_in, const double* lam_in, const double* kap_in,
+                      double* nu_out, double* lam_out, double* kap_out, double* post) {
+    const int64_t n = lat->n_edges, m = lat->n_faces, N = lat->n_sites;
+    const double l0 = log((1.0 - p_dec) / p_dec);
+    const double lm = log((1.0 - q_dec) / q_dec);
+    double* Q = (double*)malloc(sizeof(double) * 4 * m);
+    double* M = (double*)malloc(sizeof(double) * m);
+    double* R = (double*)malloc(sizeof(double) * 6 * N);
+    for (int64_t f = 0; f < m; ++f)
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = lat->face_edge[4 * f + k];
+            double msg = l0;
+            if (nu_in)
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t g = lat->edge_face[4 * i + j];
+                    if (g != f) msg += nu_in[4 * g + lat->edge_slot[4 * i + j]];
+                }
+            Q[4 * f + k] = clamp_msg(msg);
+        }
+    for (int64_t f = 0; f < m; ++f) {
+        int64_t cb[2];
+        int sl[2];
+        face_cubes(lat, f, cb, sl);
+        double msg = lm;
+        if (kap_in) msg += kap_in[6 * cb[0] + sl[0]] + kap_in[6 * cb[1] + sl[1]];
+        M[f] = clamp_msg(msg);
+    }
+    for (int64_t c = 0; c < N; ++c)
+        for (int j = 0; j < 6; ++j) {
+            const int64_t f = cube_face(lat, c, j);
+            int64_t cb[2];
+            int sl[2];
+            face_cubes(lat, f, cb, sl);
+            const int other = (cb[0] == c && sl[0] == j) ? 1 : 0;
+            double msg = lm;
+            if (lam_in) msg += lam_in[f] + kap_in[6 * cb[other] + sl[other]];
+            R[6 * c + j] = clamp_msg(msg);
+        }
+    for (int64_t f = 0; f < m; ++f) {
+        const double sign = syn[f] ? -1.0 : 1.0;
+        double all = 1.0;
+        for (int k = 0; k < 4; ++k) all *= tanh(Q[4 * f + k] / 2.0);
+        lam_out[f] = sign * 2.0 * atanh(all);
+        for (int k = 0; k < 4; ++k) {
+            double prod = tanh(M[f] / 2.0);
+            for (int kk = 0; kk < 4; ++kk)
+                if (kk != k) prod *= tanh(Q[4 * f + kk] / 2.0);
+            nu_out[4 * f + k] = sign * 2.0 * atanh(prod);
+        }
+    }
+    for (int64_t c = 0; c < N; ++c) {
+        int par = 0;
+        for (int j = 0; j < 6; ++j) par ^= syn[cube_face(lat, c, j)];
+        const double sign = par ? -1.0 : 1.0;
+        for (int j = 0; j < 6; ++j) {
+            double prod = 1.0;
+            for (int jj = 0; jj < 6; ++jj)
+                if (jj != j) prod *= tanh(R[6 * c + jj] / 2.0);
+            kap_out[6 * c + j] = sign * 2.0 * atanh(prod);
+        }
+    }
+    if (post)
+        for (int64_t i = 0; i < n; ++i) {
+            double l = l0;
+            for (int j = 0; j < 4; ++j)
+                l += nu_out[4 * lat->edge_face[4 * i + j] + lat->edge_slot[4 * i + j]];
+            post[i] = l;
+        }
+    free(Q);
+    free(M);
+    free(R);
+}
+
+void tco_bp_meta_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
+                        double p_dec, double q_dec, int32_t iters, uint8_t* corr,
+                        double* post) {
+    const int64_t n = lat->n_edges, m = lat->n_faces, N = lat->n_sites;
+    double* buf = (double*)malloc(sizeof(double) * 2 * (4 * m + m + 6 * N));
+    double* l = (double*)malloc(sizeof(double) * n);
+    const double l0 = log((1.0 - p_dec) / p_dec);
+    for (int64_t s = 0; s < n_shots; ++s) {
+        const uint8_t* sy = syn + s * m;
+        int cur = -1;
+        for (int32_t it = 0; it < iters; ++it) {
+            const int nxt = cur == 0 ? 1 : 0;
+            double* o = buf + (size_t)nxt * (4 * m + m + 6 * N);
+            double* i_ = cur < 0 ? NULL : buf + (size_t)cur * (4 * m + m + 6 * N);
+            tco_bp_meta_step(lat, sy, p_dec, q_dec, i_, i_ ? i_ + 4 * m : NULL,
+                             i_ ? i_ + 5 * m : NULL, o, o + 4 * m, o + 5 * m, l);
+            cur = nxt;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            const double li = iters > 0 ? l[i] : l0;
+            corr[s * n + i] = (uint8_t)(li < 0.0);
+            if (post) post[s * n + i] = li;
+        }
+    }
+    free(buf);
+    free(l);
+}
+
 /* Local BP (Section 4.1): a fixed number of iterations, then every bit whose
  * posterior LLR is negative is flipped. */
 void tco_bp_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
@@ -479,8 +633,12 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
             tco_sample_noise(lat, syn, 1, qt, prm->seed, (uint32_t)t, shot, 1);
             memset(corr, 0, n);
             if (prm->bp_iters > 0) {
-                tco_bp_decode(lat, syn, 1, NULL, prm->p_dec, prm->q_dec, prm->bp_iters, cbp,
-                              NULL);
+                if (prm->bp_meta)
+                    tco_bp_meta_decode(lat, syn, 1, prm->p_dec, prm->q_dec, prm->bp_iters, cbp,
+                                       NULL);
+                else
+                    tco_bp_decode(lat, syn, 1, NULL, prm->p_dec, prm->q_dec, prm->bp_iters,
+                                  cbp, NULL);
                 for (int64_t i = 0; i < n; ++i) corr[i] = cbp[i];
                 tco_syndrome(lat, cbp, syn, 1, 1);
             }

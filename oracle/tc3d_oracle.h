@@ -44,7 +44,7 @@ typedef struct {
     uint64_t seed;            /* Philox key                                     */
     uint32_t subset_mask;     /* bit k set: sweep k is a subset p-flip sweep on
                                  the edge class tco_subset_class(j, m, t)        */
-    uint32_t reserved;
+    int32_t bp_meta;          /* 1: BP with meta-check factors (tco_bp_meta_*)   */
 } tco_params;
 
 tco_lattice* tco_lattice_new(int32_t L);
@@ -106,6 +106,21 @@ void tco_bp_step(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
 void tco_bp_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
                    const double* llr0, double p_dec, double q_dec, int32_t iters,
                    uint8_t* corr, double* post);
+
+/* BP with meta-check factors (see tco_bp_meta_step in the source for the
+ * messages): one measurement-error variable per check and one parity factor
+ * per cube over the six measurement variables of its faces. Variable-to-
+ * factor messages are clamped to +-TCO_META_CLAMP nats: the cube loops feed
+ * back and the messages grow without bound, which would reach atanh(1).
+ * nu: [n_faces][4], lambda: [n_faces], kappa: [n_sites][6] with cube slot j =
+ * 2n the face f(c,n), j = 2n+1 the face f(c+unit(n),n). */
+#define TCO_META_CLAMP 30.0
+void tco_bp_meta_step(const tco_lattice* lat, const uint8_t* syn, double p_dec, double q_dec,
+                      const double* nu_in, const double* lam_in, const double* kap_in,
+                      double* nu_out, double* lam_out, double* kap_out, double* post);
+void tco_bp_meta_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
+                        double p_dec, double q_dec, int32_t iters, uint8_t* corr,
+                        double* post);
 
 /* Majority-vote readout over the L^2 logical Z strings of each axis.
  * mask[s] bit d = logical X error on qubit d; odd[s][d] = odd strings. */
