@@ -160,6 +160,32 @@ int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
  * X error on qubit d when that count is at least L^2/2 (a tie counts as a
  * failure). mask_out[s] bit d records it; odd_out (NULL ok) is
  * [n_shots][3] int32 counts. err is an edge plane [3L^3][ceil(n_shots/64)]. */
+/* BP with meta-check factors: the extension of the factor graph that Section
+ * 4.1 describes and leaves out, and that the closing discussion names as a
+ * likely improvement. Each check has a measurement-error variable (prior
+ * ln((1-q_dec)/q_dec)), a member of its check and of the meta-checks of the
+ * two cubes that contain the check's face; a meta-check requires the six
+ * measurement variables of a cube to have the parity of its six measured
+ * outcomes. Flooding schedule, FP64, variable-to-factor messages clamped to
+ * +-30 nats (the cube loops feed back and the messages grow without bound).
+ *   syn       face plane [3L^3][W]
+ *   corr_out  edge plane [3L^3][W], [posterior < 0] after `iters` iterations
+ *   post_out  FP64 [W][3L^3][64] posterior LLRs, or NULL
+ * 0 < p_dec, q_dec < 0.5. Workspace: tc3d_bp_meta_workspace_bytes. */
+size_t tc3d_bp_meta_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
+int tc3d_bp_meta_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                        double p_dec, double q_dec, int32_t iters, uint64_t* corr_out,
+                        double* post_out, void* ws, size_t ws_bytes, void* stream);
+/* One iteration of it, for inspection. State: FP64 [W][L^3][21][64] of e^msg
+ * per site v: slots 0..11 the check -> qubit messages of faces f(v,0..2) (slot
+ * 4n+k: face f(v,n) to its member k, the order of tc3d_bp_step), 12..14 the
+ * check -> measurement messages of those faces, 15..20 the messages of cube
+ * v to its faces (slot 15 + 2n: f(v,n); 15 + 2n + 1: f(v + unit(n), n)).
+ * state_in NULL = first iteration. post_out as in tc3d_bp_meta_decode. */
+int tc3d_bp_meta_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                      double p_dec, double q_dec, const double* state_in, double* state_out,
+                      double* post_out, void* stream);
+
 int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_shots,
                        uint8_t* mask_out, int32_t* odd_out, void* stream);
 
@@ -187,6 +213,9 @@ typedef struct {
                                   (see tc3d_subset_pflip_sweep); the j-th of the
                                   m such sweeps of cycle t acts on edge class
                                   (j + t m) mod 12. Needs L even; 0 = none      */
+    int32_t bp_meta;           /* 1: BP with meta-check factors
+                                  (tc3d_bp_meta_decode) instead of the paper's */
+    int32_t reserved;          /* zero                                           */
 } tc3d_run_params;
 
 size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);

@@ -17,7 +17,8 @@ import os
 
 __all__ = [
     "Lattice", "RunParams", "Timing", "Tc3dError", "lib", "make_lattice", "sample_noise",
-    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "subset_pflip_sweep", "bp_workspace_bytes",
+    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "subset_pflip_sweep", "bp_meta_workspace_bytes",
+    "bp_meta_decode", "bp_meta_step", "bp_workspace_bytes",
     "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
     "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
 ]
@@ -48,6 +49,7 @@ class RunParams(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("shot0", ctypes.c_uint64),
         ("n_shots", ctypes.c_int64), ("batch_shots", ctypes.c_int64),
         ("bp_tile", ctypes.c_int32), ("subset_mask", ctypes.c_uint32),
+        ("bp_meta", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -104,6 +106,9 @@ def lib():
         "tc3d_bp_decode": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, i32, vp, vp, vp, sz, vp]),
         "tc3d_bp_step": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, vp, vp, vp, vp]),
         "tc3d_logical_check": (ctypes.c_int, [lat, vp, i64, vp, vp, vp]),
+        "tc3d_bp_meta_workspace_bytes": (sz, [lat, i64]),
+        "tc3d_bp_meta_decode": (ctypes.c_int, [lat, vp, i64, f64, f64, i32, vp, vp, vp, sz, vp]),
+        "tc3d_bp_meta_step": (ctypes.c_int, [lat, vp, i64, f64, f64, vp, vp, vp, vp]),
         "tc3d_run_workspace_bytes": (sz, [lat, prm]),
         "tc3d_run_cycles": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp]),
         "tc3d_run_cycles_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp,
@@ -231,6 +236,23 @@ def bp_step(lat, syn, n_shots, llr0, llr0_scalar, meas_factor, nu_in, nu_out, po
                               _ptr(post_out), _stream(stream)), "bp_step")
 
 
+def bp_meta_workspace_bytes(lat, n_shots) -> int:
+    return int(lib().tc3d_bp_meta_workspace_bytes(ctypes.byref(lat), int(n_shots)))
+
+
+def bp_meta_decode(lat, syn, n_shots, p_dec, q_dec, iters, corr_out, post_out, ws, stream=None):
+    _check(lib().tc3d_bp_meta_decode(ctypes.byref(lat), _ptr(syn), int(n_shots), float(p_dec),
+                                     float(q_dec), int(iters), _ptr(corr_out), _ptr(post_out),
+                                     _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "bp_meta_decode")
+
+
+def bp_meta_step(lat, syn, n_shots, p_dec, q_dec, state_in, state_out, post_out, stream=None):
+    _check(lib().tc3d_bp_meta_step(ctypes.byref(lat), _ptr(syn), int(n_shots), float(p_dec),
+                                   float(q_dec), _ptr(state_in), _ptr(state_out),
+                                   _ptr(post_out), _stream(stream)), "bp_meta_step")
+
+
 def logical_check(lat, err, n_shots, mask_out, odd_out=None, stream=None):
     _check(lib().tc3d_logical_check(ctypes.byref(lat), _ptr(err), int(n_shots), _ptr(mask_out),
                                     _ptr(odd_out), _stream(stream)), "logical_check")
@@ -331,13 +353,13 @@ __all__ += ["cnn_param_count", "cnn_packed_bytes", "cnn_pack", "cnn_workspace_by
 
 def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,
                     shot0=0, p_dec=None, q_dec=None, perfect_final=1, final_qubit_noise=1,
-                    batch_shots=0, bp_tile=0, subset_mask=0) -> RunParams:
+                    batch_shots=0, bp_tile=0, subset_mask=0, bp_meta=0) -> RunParams:
     return RunParams(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                      q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                      perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                      bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
                      shot0=shot0, n_shots=n_shots, batch_shots=batch_shots, bp_tile=bp_tile,
-                     subset_mask=subset_mask)
+                     subset_mask=subset_mask, bp_meta=int(bp_meta))
 
 
 __all__.append("make_run_params")

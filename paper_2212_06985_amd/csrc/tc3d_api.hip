@@ -187,6 +187,8 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
         prm->bp_tile > kMaxL)
         return TC3D_EINVAL;
     if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
+    if (prm->bp_meta != 0 && prm->bp_meta != 1) return TC3D_EINVAL;
+    if (prm->reserved != 0) return TC3D_EINVAL;
     // subset sweeps: within the schedule, and an edge colouring needs L even
     if (prm->subset_mask != 0 &&
         ((prm->n_sweeps < 32 && (prm->subset_mask >> prm->n_sweeps) != 0) || lat->L % 2 != 0))
@@ -197,6 +199,13 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
                                prm->q_dec < 0.5))
         return TC3D_EINVAL;
     return TC3D_OK;
+}
+
+// One BP state buffer for nw words: FP32 messages, or the FP64 state of BP
+// with meta-checks.
+size_t bp_state_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t nw) {
+    return prm->bp_meta ? round_up(bp_meta_state_bytes(geo_of(lat), nw), 256)
+                        : nu_bytes(lat, 64 * nw);
 }
 
 size_t llr_bytes(const tc3d_lattice* lat, int64_t nw) {
@@ -213,7 +222,7 @@ int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cn
         nb = std::min<int64_t>(W, prm->batch_shots / 64);
     } else {
         size_t per_word = (cnn ? 4 : 3) * plane_bytes(lat, 1) +
-                          (prm->bp_iters > 0 ? 2 * nu_bytes(lat, 64) : 0);
+                          (prm->bp_iters > 0 ? 2 * bp_state_bytes(lat, prm, 1) : 0);
         if (cnn) per_word += llr_bytes(lat, 1) + cnn_workspace_bytes(64 * lat->n_sites, 0);
         const size_t budget = (size_t)24 << 30;
         nb = std::max<int64_t>(1, std::min<int64_t>(W, (int64_t)(budget / per_word)));
@@ -228,7 +237,7 @@ size_t run_ws_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t
     if (nb_out) *nb_out = nb;
     if (nb == 0) return 256;
     size_t b = 3 * plane_bytes(lat, nb);  // syn, corr, flips
-    if (prm->bp_iters > 0) b += 2 * nu_bytes(lat, 64 * nb);
+    if (prm->bp_iters > 0) b += 2 * bp_state_bytes(lat, prm, nb);
     if (cnn)  // previous working syndrome, priors, CNN activations
         b += plane_bytes(lat, nb) + llr_bytes(lat, nb) +
              round_up(cnn_workspace_bytes(64 * nb * lat->n_sites, 0), 256);
@@ -243,7 +252,7 @@ int run_validate(const tc3d_lattice* lat, const tc3d_run_params* prm, const void
     int rc = check_run(lat, prm);
     if (rc) return rc;
     const bool cnn = packed != nullptr;
-    if (cnn && prm->bp_iters <= 0) return TC3D_EINVAL;
+    if (cnn && (prm->bp_iters <= 0 || prm->bp_meta)) return TC3D_EINVAL;
     if (prm->n_shots == 0) return TC3D_OK;
     if (!err || !mask) return TC3D_EINVAL;
     if (!aligned(err, 8) || (odd && !aligned(odd, 4)) || (cnn && !aligned(packed, 256)))
@@ -275,8 +284,8 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
     char* next = base + 3 * plane_bytes(lat, nb);
     if (prm->bp_iters > 0) {
         nu0 = (float*)next;
-        nu1 = (float*)(next + nu_bytes(lat, 64 * nb));
-        next += 2 * nu_bytes(lat, 64 * nb);
+        nu1 = (float*)(next + bp_state_bytes(lat, prm, nb));
+        next += 2 * bp_state_bytes(lat, prm, nb);
     }
     uint64_t* prev = nullptr;
     float* llr = nullptr;
@@ -309,8 +318,15 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
                     (rc = cnn_forward(c, g, syn, t == 0 ? nullptr : prev, bw, 64 * bw * g.N,
                                       packed, llr, cnn_ws)))
                     return rc;
-                const BpArgs a = make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw, prm->bp_tile);
-                if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
+                if (prm->bp_meta) {
+                    if ((rc = bp_meta_run(c, g, cS, bw, prm->p_dec, prm->q_dec, prm->bp_iters,
+                                          (double*)nu0, (double*)nu1, C, nullptr)))
+                        return rc;
+                } else {
+                    const BpArgs a =
+                        make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw, prm->bp_tile);
+                    if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
+                }
                 if ((rc = launch_syndrome(c, g, cC, S, bw, 1, 0u, 0, 0, 0))) return rc;
             } else {
                 if ((rc = launch_clear(c, C, rows, bw))) return rc;
@@ -475,6 +491,52 @@ int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
     if (rc || !post_out) return rc;
     // posterior of the new state; no correction plane (the store is skipped)
     return launch_bp_post(c, g, a, NU_LOAD, nu_out, Plane{nullptr, nw}, post_out);
+}
+
+static bool probs_open(double p_dec, double q_dec) {
+    return p_dec > 0.0 && p_dec < 0.5 && q_dec > 0.0 && q_dec < 0.5;
+}
+
+size_t tc3d_bp_meta_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots) {
+    if (!lattice_ok(lat) || n_shots < 0) return 0;
+    return 2 * round_up(bp_meta_state_bytes(geo_of(lat), words_of(n_shots)), 256);
+}
+
+int tc3d_bp_meta_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                        double p_dec, double q_dec, int32_t iters, uint64_t* corr_out,
+                        double* post_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0 || iters < 1 || !probs_open(p_dec, q_dec))
+        return TC3D_EINVAL;
+    if (n_shots == 0) return TC3D_OK;
+    if (!syn || !corr_out) return TC3D_EINVAL;
+    if (!aligned(syn, 8) || !aligned(corr_out, 8) || (post_out && !aligned(post_out, 8)))
+        return TC3D_EALIGN;
+    const int64_t nw = words_of(n_shots);
+    const Geo g = geo_of(lat);
+    const size_t half = round_up(bp_meta_state_bytes(g, nw), 256);
+    if (!ws || ws_bytes < 2 * half) return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return bp_meta_run(c, g, CPlane{syn, nw}, nw, p_dec, q_dec, iters, (double*)ws,
+                       (double*)((char*)ws + half), Plane{corr_out, nw}, post_out);
+}
+
+int tc3d_bp_meta_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
+                      double p_dec, double q_dec, const double* state_in, double* state_out,
+                      double* post_out, void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0 || !probs_open(p_dec, q_dec)) return TC3D_EINVAL;
+    if (n_shots == 0) return TC3D_OK;
+    if (!syn || !state_out || state_in == state_out) return TC3D_EINVAL;
+    if (!aligned(syn, 8) || !aligned(state_out, 8) || (state_in && !aligned(state_in, 8)) ||
+        (post_out && !aligned(post_out, 8)))
+        return TC3D_EALIGN;
+    const int64_t nw = words_of(n_shots);
+    const Ctx c{(hipStream_t)stream, nullptr};
+    const Geo g = geo_of(lat);
+    int rc = launch_bp_meta_iter(c, g, CPlane{syn, nw}, nw, p_dec, q_dec, state_in, state_out);
+    if (rc || !post_out) return rc;
+    return launch_bp_meta_post(c, g, CPlane{syn, nw}, nw, p_dec, q_dec, state_out,
+                               Plane{nullptr, nw}, post_out);
 }
 
 int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_shots,

@@ -103,6 +103,17 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
                    float* post);
 
+// ------------------------------------------------ BP with meta-check factors
+// FP64 state [W][N][21][64] (e^msg: 12 check->qubit, 3 check->measurement,
+// 6 cube->measurement per site).
+size_t bp_meta_state_bytes(Geo g, int64_t nw);
+int launch_bp_meta_iter(const Ctx& c, Geo g, CPlane syn, int64_t nw, double p_dec, double q_dec,
+                        const double* in, double* out);
+int launch_bp_meta_post(const Ctx& c, Geo g, CPlane syn, int64_t nw, double p_dec,
+                        double q_dec, const double* state, Plane corr, double* post);
+int bp_meta_run(const Ctx& c, Geo g, CPlane syn, int64_t nw, double p_dec, double q_dec,
+                int32_t iters, double* buf0, double* buf1, Plane corr, double* post);
+
 // ----------------------------------------------------------------- CNN prior
 int64_t cnn_param_count();
 size_t cnn_packed_bytes();

@@ -68,7 +68,7 @@ def decoder_params(decoder: str, n_a: int = 1, lambda_p: int = 0, bp_iters: int 
 
 
 def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=0,
-               bp_iters=None, chunk_shots=None, shot0=0, q_dec=None, schedule=None):
+               bp_iters=None, chunk_shots=None, shot0=0, q_dec=None, schedule=None, bp_meta=0):
     """Logical error statistics of `shots` independent memory runs.
 
     Returns the mask histogram (index = bit x | bit y << 1 | bit z << 2), the
@@ -93,7 +93,7 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
         n = min(chunk, shots - done)
         prm = tc.make_run_params(p, p, cycles, it, ns, mask_bits, n_shots=n, seed=seed,
                                  shot0=shot0 + done, perfect_final=0, q_dec=q_dec,
-                                 subset_mask=sub_bits)
+                                 subset_mask=sub_bits, bp_meta=bp_meta)
         need = tc.run_workspace_bytes(lat, prm)
         if ws is None or ws.numel() < need:
             ws = tc.alloc_workspace(need)
@@ -107,7 +107,7 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
     fails = [int(hist[[k for k in range(8) if (k >> d) & 1]].sum()) for d in range(3)]
     return {"L": L, "p": p, "cycles": cycles, "decoder": decoder, "n_a": n_a,
             "lambda_p": lambda_p, "bp_iters": it, "shots": shots, "seed": seed,
-            "q_dec": p if q_dec is None else q_dec, "schedule": schedule,
+            "q_dec": p if q_dec is None else q_dec, "schedule": schedule, "bp_meta": bp_meta,
             "hist": hist.tolist(), "fails": fails, "ties": ties, "gpu_ms": ms,
             "qubit_cycles_per_s": 3 * L ** 3 * cycles * shots / (ms * 1e-3)}
 
@@ -170,13 +170,13 @@ def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500):
 
 
 def threshold(decoder, Ls, ps, cycles, shots, seed=1, n_a=1, lambda_p=0, bp_iters=None,
-              pooled=False, log=print, q_dec=None, schedule=None):
+              pooled=False, log=print, q_dec=None, schedule=None, bp_meta=0):
     rows = []
     for L in Ls:
         for p in ps:
             t0 = time.perf_counter()
             r = memory_run(L, p, cycles, decoder, shots, seed, n_a, lambda_p, bp_iters,
-                           q_dec=q_dec, schedule=schedule)
+                           q_dec=q_dec, schedule=schedule, bp_meta=bp_meta)
             f, s = pfail_pooled(r) if pooled else pfail(r)
             r["pfail"], r["pfail_sigma"] = f, s
             rows.append(r)
@@ -221,6 +221,8 @@ def main():
     th.add_argument("--schedule", default=None,
                     help="sweep schedule letters (F flip, P p-flip, C subset p-flip); "
                          "overrides the decoder's own")
+    th.add_argument("--bp-meta", action="store_true",
+                    help="BP with meta-check factors (cube parities of the measurement errors)")
     th.add_argument("--q-dec", type=float, default=None,
                     help="measurement-error rate BP assumes (default: q = p)")
     th.add_argument("--out", default=None)
@@ -231,9 +233,9 @@ def main():
     res = threshold(args.decoder, args.L, args.p, args.cycles, args.shots, args.seed, args.n_a,
                     args.lambda_p, args.bp_iters, args.pooled,
                     log=lambda m: print(m, flush=True), q_dec=args.q_dec,
-                    schedule=args.schedule)
+                    schedule=args.schedule, bp_meta=int(args.bp_meta))
     print(json.dumps({"fit": res["fit"], "decoder": res["decoder"], "n_a": res["n_a"],
-                      "schedule": args.schedule,
+                      "schedule": args.schedule, "bp_meta": bool(args.bp_meta),
                       "lambda_p": res["lambda_p"], "cycles": res["cycles"]}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:
