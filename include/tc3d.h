@@ -207,8 +207,10 @@ typedef struct {
     int64_t batch_shots;       /* shots decoded together (multiple of 64);
                                   0 picks a size that keeps the workspace near
                                   24 GiB                                         */
-    int32_t bp_tile;           /* BP traversal tile edge in sites (a tuning knob
-                                  that never changes results); 0 = automatic    */
+    int32_t bp_tile;           /* BP traversal (a tuning knob that never changes
+                                  results): 0 = whole x-y planes in memory
+                                  order; T > 0: T x T site columns; T < 0:
+                                  bands of whole x rows, -T rows high          */
     uint32_t subset_mask;      /* bit k set: sweep k is a subset p-flip sweep
                                   (see tc3d_subset_pflip_sweep); the j-th of the
                                   m such sweeps of cycle t acts on edge class
@@ -336,8 +338,9 @@ size_t tc3d_run_jobs_workspace_bytes(const tc3d_job* jobs, int32_t n_jobs);
 int tc3d_run_jobs(const tc3d_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
                   int32_t flags, void* stream);
 
-/* Autotuning of the knobs that never change results: the BP traversal tile
- * (bp_tile) and the shots decoded together (batch_shots). Each candidate
+/* Autotuning of the knobs that never change results: the BP traversal
+ * (bp_tile: planes, square columns or x-row bands) and the shots decoded
+ * together (batch_shots). Each candidate
  * decodes the first probe_cycles noisy cycles of *prm's shots (timed with
  * HIP events, after one untimed warm-up run) and the fastest is written back
  * into prm->bp_tile and prm->batch_shots. The candidates tried (at most

@@ -183,7 +183,7 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
     if (!lattice_ok(lat) || !prm) return TC3D_EINVAL;
     if (!(prm->p >= 0.0 && prm->p < 0.5) || !(prm->q >= 0.0 && prm->q < 0.5)) return TC3D_EINVAL;
     if (prm->noisy_cycles < 0 || prm->n_sweeps < 0 || prm->n_sweeps > kMaxSweeps ||
-        prm->bp_iters < 0 || prm->n_shots < 0 || prm->batch_shots < 0 || prm->bp_tile < 0 ||
+        prm->bp_iters < 0 || prm->n_shots < 0 || prm->batch_shots < 0 || prm->bp_tile < -kMaxL ||
         prm->bp_tile > kMaxL)
         return TC3D_EINVAL;
     if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
@@ -805,9 +805,9 @@ int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_c
     (void)run_ws_bytes(lat, &probe, &nb_auto, false);
     // candidates: traversal tiles, then batches of the automatic size, 1/2, 1/4
     std::vector<int32_t> tiles{0};
-    if (prm->bp_iters > 0)
-        for (int32_t t : {4, 8, 12, 16, 24, 32})
-            if (t < lat->L) tiles.push_back(t);
+    if (prm->bp_iters > 0 && !prm->bp_meta)
+        for (int32_t t : {4, 8, 12, 16, 24, 32, -4, -8, -12, -16})
+            if ((t < 0 ? -t : t) < lat->L) tiles.push_back(t);
     std::vector<int64_t> batches;
     for (int64_t b : {nb_auto, nb_auto / 2, nb_auto / 4})
         if (b >= 1 && (batches.empty() || b != batches.back())) batches.push_back(b);

@@ -63,14 +63,15 @@ __device__ __forceinline__ uint32_t div_of(uint32_t n, const FastDiv& f) {
     return (uint32_t)(((uint64_t)t + n) >> f.l);
 }
 
-// Site order of one shot word: tile columns of T x T sites, z outermost
-// inside a column, x fastest. Sites outside the lattice (when T does not
-// divide L) are skipped. Logical indices stay below 2^31 (checked on launch).
+// Site order of one shot word: tile columns of TX x TY sites, z outermost
+// inside a column, x fastest. Sites outside the lattice (when a tile edge
+// does not divide L) are skipped. Logical indices stay below 2^31 (checked
+// on launch).
 struct Tiling {
-    int L, T, nT;
-    uint32_t per_word;          // nT * nT * T * T * L logical sites
+    int L, TX, TY, nTX, nTY;
+    uint32_t per_word;          // nTX * nTY * TX * TY * L logical sites
     FastDiv n_sg;               // site groups of kWaves per word
-    FastDiv col, plane, row, tiles_x;  // T*T*L, T*T, T, nT
+    FastDiv col, plane, row, tiles_x;  // TX*TY*L, TX*TY, TX, nTX
 };
 
 struct Src {
@@ -107,8 +108,8 @@ __device__ __forceinline__ Item item_of(const Tiling& tl) {
     const uint32_t yy = div_of(r2, tl.row), xx = r2 - yy * tl.row.d;
     const uint32_t ty = div_of(tile, tl.tiles_x), tx = tile - ty * tl.tiles_x.d;
     it.z = (int)z;
-    it.x = (int)(tx * tl.T + xx);
-    it.y = (int)(ty * tl.T + yy);
+    it.x = (int)(tx * tl.TX + xx);
+    it.y = (int)(ty * tl.TY + yy);
     it.ok = i < tl.per_word && it.x < tl.L && it.y < tl.L;
     it.v = it.ok ? site_of(it.x, it.y, it.z, tl.L) : 0;
     return it;
@@ -305,30 +306,33 @@ Src make_src(Geo g, const BpArgs& a, const float* nu) {
     return S;
 }
 
-// Tile edge: the request if given, else L (whole x-y planes in memory order,
-// the fastest order measured at L = 48 once the message stores stream past
-// L2; smaller tiles shorten the z reuse distance but break up the DRAM
-// streams).
-int tile_of(int L, int req) {
-    if (req > 0) return req < L ? req : L;
-    return L;
+// Tile of the traversal. req = 0: whole x-y planes in memory order; req > 0:
+// req x req columns; req < 0: bands of whole x rows, -req rows high. Smaller
+// tiles and bands shorten the z reuse distance (one tile plane instead of a
+// whole plane); bands keep whole x rows, i.e. long contiguous DRAM runs.
+void tile_of(int L, int req, int* tx, int* ty) {
+    const int r = req < 0 ? -req : req;
+    const int t = r < L ? r : L;
+    *tx = req > 0 ? t : L;
+    *ty = req != 0 ? t : L;
 }
 
 // Returns false when the launch's logical indices would not fit 31 bits.
 bool tiling_of(Geo g, const BpArgs& a, Tiling* out) {
     Tiling tl;
     tl.L = g.L;
-    tl.T = tile_of(g.L, a.tile);
-    tl.nT = (g.L + tl.T - 1) / tl.T;
-    const int64_t per_word = (int64_t)tl.nT * tl.nT * tl.T * tl.T * g.L;
+    tile_of(g.L, a.tile, &tl.TX, &tl.TY);
+    tl.nTX = (g.L + tl.TX - 1) / tl.TX;
+    tl.nTY = (g.L + tl.TY - 1) / tl.TY;
+    const int64_t per_word = (int64_t)tl.nTX * tl.nTY * tl.TX * tl.TY * g.L;
     const int64_t n_sg = (per_word + kWaves - 1) / kWaves;
     if (n_sg * a.nw > 0x7fffffff || per_word + kWaves > 0x7fffffff) return false;
     tl.per_word = (uint32_t)per_word;
     tl.n_sg = fastdiv((uint32_t)n_sg);
-    tl.col = fastdiv((uint32_t)(tl.T * tl.T * g.L));
-    tl.plane = fastdiv((uint32_t)(tl.T * tl.T));
-    tl.row = fastdiv((uint32_t)tl.T);
-    tl.tiles_x = fastdiv((uint32_t)tl.nT);
+    tl.col = fastdiv((uint32_t)(tl.TX * tl.TY * g.L));
+    tl.plane = fastdiv((uint32_t)(tl.TX * tl.TY));
+    tl.row = fastdiv((uint32_t)tl.TX);
+    tl.tiles_x = fastdiv((uint32_t)tl.nTX);
     *out = tl;
     return true;
 }
