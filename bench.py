@@ -419,6 +419,9 @@ def main():
                     help="plain p-BP or BP with the CNN prior (default: the workload's)")
     ap.add_argument("--compare", action=argparse.BooleanOptionalAction, default=None,
                     help="also decode the same shots with the other decoder")
+    ap.add_argument("--bp-iters", type=int, default=None,
+                    help="BP iterations of the main decoder (the comparison keeps the "
+                         "workload's)")
     ap.add_argument("--beta", type=float, default=0.2,
                     help="CNN prior strength: llr0 = l0 + beta (llr_cnn - l0)")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
@@ -478,8 +481,10 @@ def main():
     # shots decoded together: the whole step unless a smaller batch is asked for
     batch = min(64 * W, args.batch_shots) if args.batch_shots else 64 * W
 
-    wall, per_class, ler, resid = run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch,
-                                              args.bp_tile, args.beta, args.weights, "main")
+    main_cfg = dict(cfg, bp=args.bp_iters) if args.bp_iters else cfg
+    wall, per_class, ler, resid = run_decoder(tc, lat, main_cfg, decoder, steps, warmup, S,
+                                              batch, args.bp_tile, args.beta, args.weights,
+                                              "main")
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
     roof = roofline(per_class, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
@@ -525,11 +530,11 @@ def main():
         "data": "synthetic (phenomenological noise drawn from Philox counters, seed 1)",
         "config": {"workload": f"L={L} p=q={'/'.join(str(p) for p in cfg['ps'])} "
                                f"{cfg['noisy']}+1 cycles "
-                               f"{'BP' + str(cfg['bp']) + ' + ' if cfg['bp'] else ''}"
+                               f"{'BP' + str(main_cfg['bp']) + ' + ' if main_cfg['bp'] else ''}"
                                f"{cfg['sched']}"
                                f"{' with the CNN prior' if decoder == 'cnn' else ''}",
                    "L": L, "shots_per_step": S, "batch_shots": batch, "shots_total": S * steps,
-                   "cycles": cycles, "bp_iters": cfg["bp"], "schedule": cfg["sched"],
+                   "cycles": cycles, "bp_iters": main_cfg["bp"], "schedule": cfg["sched"],
                    "decoder": dec_name,
                    "parallelism": "shots (bit-sliced 64 per word; one lane per shot in BP)"},
         "roofline": roof,
