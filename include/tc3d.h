@@ -357,6 +357,15 @@ int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_c
                   void* ws, size_t ws_bytes, tc3d_tune_choice* out, int32_t max_out,
                   int32_t* n_out, void* stream);
 
+/* -------------------------------------------------- measurement utility
+ * Not part of the paper's method: a plain device copy of n_bytes (a multiple
+ * of 16; 16-byte aligned, non-overlapping buffers), 16 bytes per lane, with
+ * non-temporal stores if asked. Its rocprofv3 byte counters calibrate the
+ * counters of the other kernels, and its rate is the read + write streaming
+ * ceiling the BP iteration is compared with. */
+int tc3d_stream_copy(void* dst, const void* src, int64_t n_bytes, int32_t nontemporal,
+                     void* stream);
+
 /* Human-readable text of a return code. */
 const char* tc3d_strerror(int code);
 

@@ -125,6 +125,7 @@ def lib():
         "tc3d_run_cycles_cnn": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, vp, sz, vp]),
         "tc3d_run_cycles_cnn_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, vp, sz, vp,
                                                      ctypes.POINTER(Timing)]),
+        "tc3d_stream_copy": (ctypes.c_int, [vp, vp, i64, i32, vp]),
         "tc3d_run_jobs_workspace_bytes": (sz, [ctypes.POINTER(Job), i32]),
         "tc3d_run_jobs": (ctypes.c_int, [ctypes.POINTER(Job), i32, vp, sz, i32, vp]),
         "tc3d_autotune_workspace_bytes": (sz, [lat, prm]),
@@ -415,3 +416,15 @@ def autotune(lat, prm: RunParams, ws, probe_cycles=2, stream=None):
 
 __all__ += ["Job", "TuneChoice", "JOBS_CONCURRENT", "JOBS_GRAPH", "make_job",
             "run_jobs_workspace_bytes", "run_jobs", "autotune_workspace_bytes", "autotune"]
+
+
+def stream_copy(dst, src, nontemporal=True, stream=None):
+    """dst[:] = src[:] by the library's streaming copy kernel (same byte size)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("stream_copy: sizes differ")
+    _check(lib().tc3d_stream_copy(_ptr(dst), _ptr(src), int(n), 1 if nontemporal else 0,
+                                  _stream(stream)), "stream_copy")
+
+
+__all__.append("stream_copy")

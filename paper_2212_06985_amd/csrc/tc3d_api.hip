@@ -846,6 +846,20 @@ int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_c
     return TC3D_OK;
 }
 
+int tc3d_stream_copy(void* dst, const void* src, int64_t n_bytes, int32_t nontemporal,
+                     void* stream) {
+    if (n_bytes < 0 || n_bytes % 16 != 0 || (nontemporal != 0 && nontemporal != 1))
+        return TC3D_EINVAL;
+    if (n_bytes == 0) return TC3D_OK;
+    if (!dst || !src) return TC3D_EINVAL;
+    if (!aligned(dst, 16) || !aligned(src, 16)) return TC3D_EALIGN;
+    const char* s = (const char*)src;
+    const char* d = (const char*)dst;
+    if (s < d + n_bytes && d < s + n_bytes) return TC3D_EINVAL;  // overlap
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return launch_stream_copy(c, dst, src, n_bytes / 16, nontemporal);
+}
+
 const char* tc3d_strerror(int code) {
     switch (code) {
         case TC3D_OK: return "ok";

@@ -95,6 +95,22 @@ __global__ __launch_bounds__(kBlock) void k_xor(uint64_t* __restrict__ dst, int6
     dst[r * ld_d + w] ^= src[r * ld_s + w];
 }
 
+// Plain streaming copy, 16 bytes per lane (byte-counter calibration and the
+// read + write ceiling the BP kernel is compared with).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_stream_copy(u32x4* __restrict__ dst,
+                                                        const u32x4* __restrict__ src, int64_t n,
+                                                        int nontemporal) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const u32x4 v = src[i];
+    if (nontemporal)
+        __builtin_nontemporal_store(v, dst + i);
+    else
+        dst[i] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_clear(uint64_t* __restrict__ dst, int64_t ld,
                                                   int64_t rows, int64_t nw) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -197,6 +213,15 @@ int launch_xor(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw) {
     if (rc) return rc;
     k_xor<<<dim3((unsigned)blocks_for(rows * nw)), dim3(kBlock), 0, c.stream>>>(
         dst.p, dst.ld, src.p, src.ld, rows, nw);
+    return after_launch(c);
+}
+
+int launch_stream_copy(const Ctx& c, void* dst, const void* src, int64_t n16, int nontemporal) {
+    if (n16 == 0) return TC3D_OK;
+    int rc = before_launch(c, TC3D_K_APPLY);
+    if (rc) return rc;
+    k_stream_copy<<<dim3((unsigned)blocks_for(n16)), dim3(kBlock), 0, c.stream>>>(
+        (u32x4*)dst, (const u32x4*)src, n16, nontemporal);
     return after_launch(c);
 }
 

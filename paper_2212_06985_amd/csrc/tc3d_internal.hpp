@@ -72,6 +72,8 @@ int launch_sweep_decide(const Ctx& c, Geo g, CPlane syn, Plane corr, Plane fplan
 int launch_xor(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw);
 // dst = 0 over rows x nw.
 int launch_clear(const Ctx& c, Plane dst, int64_t rows, int64_t nw);
+// dst[i] = src[i] for n16 16-byte elements (non-temporal stores if asked).
+int launch_stream_copy(const Ctx& c, void* dst, const void* src, int64_t n16, int nontemporal);
 // Majority-vote readout of n_shots shots of an edge plane.
 int launch_readout(const Ctx& c, Geo g, CPlane err, int64_t n_shots, uint8_t* mask,
                    int32_t* odd);
