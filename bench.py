@@ -78,7 +78,7 @@ ALGO_BYTES = {
 # divided by its launches.
 CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
-DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_p05.npy")
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_mixed.npy")
 
 
 def log(msg):
@@ -456,7 +456,7 @@ def main():
     ap.add_argument("--bp-iters", type=int, default=None,
                     help="BP iterations of the main decoder (the comparison keeps the "
                          "workload's)")
-    ap.add_argument("--beta", type=float, default=0.2,
+    ap.add_argument("--beta", type=float, default=0.3,
                     help="CNN prior strength: llr0 = l0 + beta (llr_cnn - l0)")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")

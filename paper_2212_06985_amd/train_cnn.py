@@ -88,12 +88,16 @@ class Trainer:
         self.batch = 0
         self.t = 0
 
-    def new_batch(self):
+    def new_batch(self, p=None):
+        """Start a fresh batch of shots (error rate p = q, or unchanged)."""
         self.err.zero_()
         self.t = 0
         self.batch += 1
+        if p is not None:
+            self.p = self.q = float(p)
 
-    def train_cycle(self, lr, on_policy=False, n_sweeps=6, mask=0b001001, bp_iters=20):
+    def train_cycle(self, lr, on_policy=False, n_sweeps=6, mask=0b001001, bp_iters=20,
+                    beta=1.0):
         """One training step on one simulated cycle of the current batch."""
         L, S, W, lat = self.L, self.S, self.W, self.lat
         shot0 = 64 * W * self.batch
@@ -108,8 +112,11 @@ class Trainer:
         self.step += 1
         tc.cnn_adam(self.params, self.grad, self.m, self.v, self.step, lr, self.packed)
         # decode this cycle and carry the residual
-        if on_policy:  # priors of the updated network
+        if on_policy:  # priors of the updated network, blended as when decoding
             tc.cnn_forward(lat, self.syn, prev, S, self.packed, self.llr, self.ws_train)
+            if beta != 1.0:
+                l0p = math.log((1 - self.p) / self.p)
+                self.llr.mul_(beta).add_((1.0 - beta) * l0p)
             llr = self.llr
         else:
             llr = None
@@ -131,17 +138,22 @@ class Trainer:
 
 
 def train(L=12, shots=4096, p=0.05, cycles=13, snapshots=10_000_000, on_policy_frac=0.2,
-          lr_max=2e-3, lr_min=5e-5, seed=12345, log=print):
+          lr_max=2e-3, lr_min=5e-5, seed=12345, log=print, p_max=None, on_policy_iters=20,
+          on_policy_beta=1.0):
+    """p_max: draw each batch's error rate uniformly from [p, p_max] (seeded)."""
     steps = max(1, snapshots // shots)
     tr = Trainer(L, shots, p, p, seed)
+    rng = np.random.default_rng(seed + 1)
     t0 = time.perf_counter()
     history = []
     for step in range(steps):
         if tr.t == cycles:
-            tr.new_batch()
+            tr.new_batch(None if p_max is None else rng.uniform(p, p_max))
         frac = step / max(1, steps - 1)
         lr = lr_min + 0.5 * (lr_max - lr_min) * (1 + math.cos(math.pi * frac))
-        tr.train_cycle(lr, on_policy=frac >= 1.0 - on_policy_frac)
+        on = frac >= 1.0 - on_policy_frac
+        tr.train_cycle(lr, on_policy=on, bp_iters=on_policy_iters if on else 20,
+                       beta=on_policy_beta)
         if step % 100 == 0 or step == steps - 1:
             loss = float(tr.loss.item())
             history.append((step, loss))
@@ -160,9 +172,20 @@ def main():
     ap.add_argument("--cycles", type=int, default=13)
     ap.add_argument("--snapshots", type=int, default=10_000_000)
     ap.add_argument("--seed", type=int, default=12345)
+    ap.add_argument("--p-max", type=float, default=None,
+                    help="draw each batch's p = q uniformly from [p, p_max]")
+    ap.add_argument("--on-policy-frac", type=float, default=0.2,
+                    help="last fraction of steps that decode with the network being trained")
+    ap.add_argument("--on-policy-iters", type=int, default=20,
+                    help="BP iterations of that decoder")
+    ap.add_argument("--on-policy-beta", type=float, default=1.0,
+                    help="prior strength of that decoder (see blend_prior)")
     args = ap.parse_args()
     tr, hist, secs = train(args.L, args.shots, args.p, args.cycles, args.snapshots,
-                           seed=args.seed, log=lambda m: print(m, flush=True))
+                           args.on_policy_frac, seed=args.seed,
+                           log=lambda m: print(m, flush=True), p_max=args.p_max,
+                           on_policy_iters=args.on_policy_iters,
+                           on_policy_beta=args.on_policy_beta)
     np.save(args.out, tr.params_numpy(), allow_pickle=False)
     print(json.dumps({"out": args.out, "seconds": secs, "steps": tr.step,
                       "snapshots": tr.step * args.shots, "final_loss": hist[-1][1]}), flush=True)

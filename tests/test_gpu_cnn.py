@@ -234,17 +234,18 @@ def test_cnn_run_equals_composed_stages():
 
 def test_trained_prior_lowers_the_logical_error_rate():
     """The committed network (trained by paper_2212_06985_amd.train_cnn at
-    L = 12, p = q = 0.05 on 10^7 simulated snapshots), blended with the channel
-    prior at beta = 0.2, decodes better than the paper's p-BP on the same
-    shots: L = 12, p = q = 0.065, 40 noisy cycles + 1 perfect, 32768 shots."""
+    L = 12 on 3x10^7 simulated snapshots with p = q drawn from [4.5%, 7%]),
+    blended with the channel prior at beta = 0.3, decodes better than the
+    paper's p-BP on the same shots: L = 12, p = q = 0.065, 40 noisy cycles + 1
+    perfect, 32768 shots."""
     import os
     from paper_2212_06985_amd import eval_cnn
     from paper_2212_06985_amd.train_cnn import blend_prior
-    path = os.path.join(os.path.dirname(tc.__file__), "weights", "cnn_L12_p05.npy")
+    path = os.path.join(os.path.dirname(tc.__file__), "weights", "cnn_L12_mixed.npy")
     w = np.load(path, allow_pickle=False)
     assert w.shape == (cnn_param_count(),)
     base = eval_cnn.run(12, 32768, 0.065, 40, None, seed=777)
-    cnn = eval_cnn.run(12, 32768, 0.065, 40, blend_prior(w, 0.2, 0.065), seed=777)
+    cnn = eval_cnn.run(12, 32768, 0.065, 40, blend_prior(w, 0.3, 0.065), seed=777)
     announce(f"  plain LER {base['ler_any']:.4f} residual syndrome {base['mean_residual_syndrome']:.2f}; "
              f"CNN LER {cnn['ler_any']:.4f} residual syndrome {cnn['mean_residual_syndrome']:.2f}")
     sig = math.sqrt(base["ler_any_sigma"] ** 2 + cnn["ler_any_sigma"] ** 2)
