@@ -195,7 +195,7 @@ struct ConvItems {
 //  EPI_MASK: y = acc where mask_act > 0 else 0, BF16 [R][32]
 // Every variant reads x[v + off(d)]; the backward-data blocks carry the
 // reversed taps in their packing.
-template <int CIN, int EPI, int NX>
+template <int CIN, int EPI, int NX, int BY>
 __global__ __launch_bounds__(kConvBlock) void k_conv(
     const bf16* __restrict__ x, const bf16* __restrict__ wp, const float* __restrict__ bias,
     const bf16* __restrict__ mask_act, bf16* __restrict__ y, float* __restrict__ llr,
@@ -203,7 +203,8 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
     constexpr int NT = EPI == EPI_LLR ? 1 : 2;
     constexpr int KS = CIN == 32 ? 27 : 9;
     constexpr int WELEMS = KS * NT * 64 * 8;
-    constexpr int NB = CIN == 32 ? NX + 2 : NX;  // B fragments per (dy, dz) column
+    constexpr int NB = CIN == 32 ? NX + 2 : NX;  // B fragments per pencil column
+    constexpr int NC = 3 * (BY + 2);             // pencil columns (dz, dy') per item
     __shared__ __attribute__((aligned(16))) bf16 wl[WELEMS];
     for (int i = threadIdx.x * 8; i < WELEMS; i += kConvBlock * 8)
         *reinterpret_cast<bf16x8*>(wl + i) = *reinterpret_cast<const bf16x8*>(wp + i);
@@ -212,6 +213,7 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int r16 = lane & 15, q = lane >> 4;
     const int L = it.L, N = it.N;
+    const int ny = (L + BY - 1) / BY;
     // per-lane channel block of the A/B fragments and output channels
     float bv[NT][4];
 #pragma unroll
@@ -224,12 +226,12 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
     for (int64_t base = lb * kConvWaves; base < it.n_items; base += G * kConvWaves) {
         const uint32_t item = (uint32_t)(base + wave);
         if (item >= it.n_items) break;
-        // wave-uniform decode
+        // wave-uniform decode: x-run, then BY-pencil row group, z, shot group
         uint32_t t = item;
         const int xr = (int)(t % (uint32_t)it.nxr);
         t /= (uint32_t)it.nxr;
-        const int yy = (int)(t % (uint32_t)L);
-        t /= (uint32_t)L;
+        const int y0 = BY * (int)(t % (uint32_t)ny);
+        t /= (uint32_t)ny;
         const int zz = (int)(t % (uint32_t)L);
         const uint32_t sg = it.sg0 + t / (uint32_t)L;
         const int64_t w = sg >> 2;
@@ -238,14 +240,16 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
         // row (w, v, l) = (w N + v) 64 + l; lane part of every fragment address
         const int64_t wrow = w * N;
         const int lane_off = (l0 + r16) * CIN + (CIN == 32 ? 8 * q : 0);
-        f32x4 acc[NX][NT];
+        f32x4 acc[BY][NX][NT];
 #pragma unroll
-        for (int i = 0; i < NX; ++i)
+        for (int by = 0; by < BY; ++by)
 #pragma unroll
-            for (int mt = 0; mt < NT; ++mt) acc[i][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // the B slabs of (dy, dz) column j: j = 3 (dz + 1) + (dy + 1)
-        auto load_col = [&](int j, bf16x8 (&b)[NB]) {
-            const int uy = wrap(yy + j % 3 - 1, L), uz = wrap(zz + j / 3 - 1, L);
+            for (int i = 0; i < NX; ++i)
+#pragma unroll
+                for (int mt = 0; mt < NT; ++mt) acc[by][i][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // the B slabs of pencil column c: dz = c / (BY + 2) - 1, rows y0 - 1 .. y0 + BY
+        auto load_col = [&](int c, bf16x8 (&b)[NB]) {
+            const int uy = wrap(y0 + c % (BY + 2) - 1, L), uz = wrap(zz + c / (BY + 2) - 1, L);
             const int64_t pencil = (wrow + (int64_t)L * (uy + (int64_t)L * uz)) * 64;
             if constexpr (CIN == 32) {
                 // slabs x0 - 1 .. x0 + NX
@@ -270,78 +274,94 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
                 }
             }
         };
-        auto mma_col = [&](int j, const bf16x8 (&b)[NB]) {
-            if constexpr (CIN == 32) {
+        // apply column c to every output pencil y0 + by it is a (dy, dz) neighbour of:
+        // taps j = 3 (dz + 1) + (dy + 1) with dy = dy' - by
+        auto mma_col = [&](int c, const bf16x8 (&b)[NB]) {
+            const int dzi = c / (BY + 2), dyp = c % (BY + 2) - 1;
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
+            for (int by = 0; by < BY; ++by) {
+                const int dy = dyp - by;
+                if (dy < -1 || dy > 1) continue;
+                const int j = 3 * dzi + dy + 1;
+                if constexpr (CIN == 32) {
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        bf16x8 a[NT];
+#pragma unroll
+                        for (int mt = 0; mt < NT; ++mt)
+                            a[mt] = *reinterpret_cast<const bf16x8*>(
+                                wl + (((3 * j + dx) * NT + mt) * 64 + lane) * 8);
+#pragma unroll
+                        for (int i = 0; i < NX; ++i)
+#pragma unroll
+                            for (int mt = 0; mt < NT; ++mt)
+                                acc[by][i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    a[mt], b[i + dx], acc[by][i][mt], 0, 0, 0);
+                    }
+                } else {
                     bf16x8 a[NT];
 #pragma unroll
                     for (int mt = 0; mt < NT; ++mt)
                         a[mt] = *reinterpret_cast<const bf16x8*>(
-                            wl + (((3 * j + dx) * NT + mt) * 64 + lane) * 8);
+                            wl + ((j * NT + mt) * 64 + lane) * 8);
 #pragma unroll
                     for (int i = 0; i < NX; ++i)
 #pragma unroll
                         for (int mt = 0; mt < NT; ++mt)
-                            acc[i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                a[mt], b[i + dx], acc[i][mt], 0, 0, 0);
+                            acc[by][i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                a[mt], b[i], acc[by][i][mt], 0, 0, 0);
                 }
-            } else {
-                bf16x8 a[NT];
-#pragma unroll
-                for (int mt = 0; mt < NT; ++mt)
-                    a[mt] = *reinterpret_cast<const bf16x8*>(wl + ((j * NT + mt) * 64 + lane) * 8);
-#pragma unroll
-                for (int i = 0; i < NX; ++i)
-#pragma unroll
-                    for (int mt = 0; mt < NT; ++mt)
-                        acc[i][mt] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[i], acc[i][mt], 0, 0, 0);
             }
         };
-        // software pipeline: the slabs of column j + 1 are in flight while the
-        // matrix cores work on column j
+        // software pipeline: the slabs of column c + 1 are in flight while the
+        // matrix cores work on column c
         bf16x8 b0[NB], b1[NB];
         load_col(0, b0);
 #pragma unroll
-        for (int j = 0; j < 9; j += 2) {
-            if (j + 1 < 9) load_col(j + 1, b1);
-            mma_col(j, b0);
-            if (j + 1 < 9) {
-                if (j + 2 < 9) load_col(j + 2, b0);
-                mma_col(j + 1, b1);
+        for (int c = 0; c < NC; c += 2) {
+            if (c + 1 < NC) load_col(c + 1, b1);
+            mma_col(c, b0);
+            if (c + 1 < NC) {
+                if (c + 2 < NC) load_col(c + 2, b0);
+                mma_col(c + 1, b1);
             }
         }
-        // epilogue: lane holds D[channel 16 mt + 4 q + i][shot l0 + r16] of site x0 + i
-        const int64_t vrow = (int64_t)L * (yy + (int64_t)L * zz);
+        // epilogue: lane holds D[channel 16 mt + 4 q + i][shot l0 + r16] of site
+        // (x0 + i, y0 + by)
 #pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            if (x0 + i >= L) break;
-            const int64_t v = vrow + x0 + i;
-            const int64_t row = (wrow + v) * 64 + l0 + r16;
-            if constexpr (EPI == EPI_LLR) {
-                if (q == 0) {
+        for (int by = 0; by < BY; ++by) {
+            if (y0 + by >= L) break;
+            const int64_t vrow = (int64_t)L * (y0 + by + (int64_t)L * zz);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        llr[((w * 3 + c) * N + v) * 64 + l0 + r16] = -(acc[i][0][c] + bv[0][c]);
-                }
-            } else {
+            for (int i = 0; i < NX; ++i) {
+                if (x0 + i >= L) break;
+                const int64_t v = vrow + x0 + i;
+                const int64_t row = (wrow + v) * 64 + l0 + r16;
+                if constexpr (EPI == EPI_LLR) {
+                    if (q == 0) {
 #pragma unroll
-                for (int mt = 0; mt < NT; ++mt) {
-                    const int64_t o = row * 32 + 16 * mt + 4 * q;
-                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                    bf16x4 out;
-                    if constexpr (EPI == EPI_RELU) {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            out[e] = (bf16)fmaxf(acc[i][mt][e] + bv[mt][e], 0.f);
-                    } else {
-                        const bf16x4 m = *reinterpret_cast<const bf16x4*>(mask_act + o);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            out[e] = (float)m[e] > 0.f ? (bf16)acc[i][mt][e] : (bf16)0.f;
+                        for (int c = 0; c < 3; ++c)
+                            llr[((w * 3 + c) * N + v) * 64 + l0 + r16] =
+                                -(acc[by][i][0][c] + bv[0][c]);
                     }
-                    *reinterpret_cast<bf16x4*>(y + o) = out;
+                } else {
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt) {
+                        const int64_t o = row * 32 + 16 * mt + 4 * q;
+                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                        bf16x4 out;
+                        if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                out[e] = (bf16)fmaxf(acc[by][i][mt][e] + bv[mt][e], 0.f);
+                        } else {
+                            const bf16x4 m = *reinterpret_cast<const bf16x4*>(mask_act + o);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                out[e] = (float)m[e] > 0.f ? (bf16)acc[by][i][mt][e] : (bf16)0.f;
+                        }
+                        *reinterpret_cast<bf16x4*>(y + o) = out;
+                    }
                 }
             }
         }
@@ -595,7 +615,8 @@ CnnWs carve(void* ws, int64_t R, int training) {
     return w;
 }
 
-constexpr int kConvNX = 4;  // sites per wavefront run along x
+constexpr int kConvNX = 2;  // sites per wavefront run along x
+constexpr int kConvBY = 2;  // y-pencils per wavefront (32-channel inputs)
 
 // Rows of shot groups sg0 .. sg0 + n_sg - 1 (16 shots each); one wavefront
 // item per (shot group, pencil, x-run).
@@ -605,8 +626,9 @@ int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     ConvItems it;
     it.L = g.L;
     it.N = g.N;
+    constexpr int BY = CIN == 32 ? kConvBY : 1;
     it.nxr = (g.L + kConvNX - 1) / kConvNX;
-    const int64_t items = n_sg * (int64_t)g.L * g.L * it.nxr;
+    const int64_t items = n_sg * (int64_t)g.L * ((g.L + BY - 1) / BY) * it.nxr;
     if (items >= (1ll << 32) || sg0 + n_sg >= (1ll << 32)) return TC3D_EINVAL;
     if (items == 0) return TC3D_OK;
     it.n_items = (uint32_t)items;
@@ -615,7 +637,7 @@ int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     const int grid = (int)(blocks < 1024 ? blocks : 1024);
     int rc = before_launch(c, TC3D_K_CNN);
     if (rc) return rc;
-    k_conv<CIN, EPI, kConvNX><<<dim3(grid), dim3(kConvBlock), 0, c.stream>>>(
+    k_conv<CIN, EPI, kConvNX, BY><<<dim3(grid), dim3(kConvBlock), 0, c.stream>>>(
         x, wp, bias, mask_act, y, llr, it);
     return after_launch(c);
 }
