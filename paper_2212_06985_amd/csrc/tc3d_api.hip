@@ -129,9 +129,13 @@ size_t nu_bytes(const tc3d_lattice* lat, int64_t n_shots) {
 // decision. With a scalar prior the first iteration's messages are
 // (-1)^s * nu1 for every check, so they are not stored: the second iteration
 // reads them straight from the syndrome.
-int bp_run(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, float* buf0, float* buf1,
+int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, float* buf1,
            Plane corr, float* post) {
     int rc;
+    // a whole decode keeps its state to itself, so per-edge priors can be
+    // folded into it (the one-step entry point keeps the plain state)
+    BpArgs a = args;
+    a.fold = a.llr0 != nullptr;
     int mode;
     const float* cur = nullptr;
     float* bufs[2] = {buf0, buf1};
@@ -174,6 +178,7 @@ BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw
     a.nw = nw;
     a.s_pad = 64 * nw;
     a.tile = tile;
+    a.fold = false;
     return a;
 }
 

@@ -24,6 +24,14 @@
 // and HBM channel. Each access is a wave-uniform 64-bit site base (scalar
 // registers) plus a 32-bit per-lane row offset held in vector registers.
 //
+// Per-edge priors (the learned prior) cost loads, not arithmetic: the check
+// rules of a site need the priors of its own three edges and of six edges of
+// its neighbours. Inside a whole decode the prior of edge e(v,a) is therefore
+// folded into one message that site v stores (slot 8 for a = x, 10 for y, 6
+// for z): the neighbours read that message anyway, and only the check that
+// excludes it needs the prior by itself, from its own site. The one-step
+// entry point keeps the plain state.
+//
 // One iteration is one kernel: a wavefront owns site v and its three faces.
 // The inputs of its 12 check-member messages need 6 of its own messages and
 // 24 messages of neighbouring sites; those come from L2 because each XCD
@@ -218,9 +226,12 @@ __device__ __forceinline__ void check_rule(const float a_in[4], float sK, float 
     for (int k = 0; k < 4; ++k) out[k] = (Dk[k] + Nk[k]) * __builtin_amdgcn_rcpf(Dk[k] - Nk[k]);
 }
 
-template <int MODE, bool EP>
+// FOLD: 0 plain state in and out; 1 plain in, folded out (the first
+// iteration of a decode with per-edge priors); 2 folded in and out.
+template <int MODE, bool EP, int FOLD>
 __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
                                                     float* __restrict__ b_out) {
+    static_assert(FOLD == 0 || EP, "only per-edge priors are folded");
     const Item it = item_of(tl);
     if (!it.ok) return;
     const Reader<MODE> R = reader_of<MODE>(S, it);
@@ -230,18 +241,31 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
     // excluded message of the member-k check and are not needed)
     const float o0 = R(0, v), o2 = R(2, v), o4 = R(4, v), o6 = R(6, v), o8 = R(8, v),
                 o10 = R(10, v);
-    // e^{l0} times the two incoming messages from faces of other sites, for
-    // the three edges at v (each is a member of two of v's faces)
-    const float px = prior<EP>(S, it, 0, v) * R(9, nb.ym) * R(5, nb.zm);
-    const float py = prior<EP>(S, it, 1, v) * R(11, nb.xm) * R(1, nb.zm);
-    const float pz = prior<EP>(S, it, 2, v) * R(7, nb.xm) * R(3, nb.ym);
+    // e^{l0} of the three edges at v, and the two incoming messages from
+    // faces of other sites for each of them (each is a member of two of v's faces)
+    const float ex = prior<EP>(S, it, 0, v), ey = prior<EP>(S, it, 1, v),
+                ez = prior<EP>(S, it, 2, v);
+    const float fx = R(9, nb.ym) * R(5, nb.zm);
+    const float fy = R(11, nb.xm) * R(1, nb.zm);
+    const float fz = R(7, nb.xm) * R(3, nb.ym);
+    const float px = ex * fx, py = ey * fy, pz = ez * fz;
     // e^{mu} of the six edges that are a member of one face of v
-    const float a_x_yp = prior<EP>(S, it, 0, nb.yp) * R(8, nb.yp) * R(4, nb.yp) * R(5, nb.yp_zm);
-    const float a_x_zp = prior<EP>(S, it, 0, nb.zp) * R(8, nb.zp) * R(4, nb.zp) * R(9, nb.zp_ym);
-    const float a_y_xp = prior<EP>(S, it, 1, nb.xp) * R(10, nb.xp) * R(0, nb.xp) * R(1, nb.xp_zm);
-    const float a_y_zp = prior<EP>(S, it, 1, nb.zp) * R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
-    const float a_z_xp = prior<EP>(S, it, 2, nb.xp) * R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
-    const float a_z_yp = prior<EP>(S, it, 2, nb.yp) * R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
+    float a_x_yp, a_x_zp, a_y_xp, a_y_zp, a_z_xp, a_z_yp;
+    if constexpr (FOLD == 2) {  // slots 8, 10, 6 of each site carry its edges' priors
+        a_x_yp = R(8, nb.yp) * R(4, nb.yp) * R(5, nb.yp_zm);
+        a_x_zp = R(8, nb.zp) * R(4, nb.zp) * R(9, nb.zp_ym);
+        a_y_xp = R(10, nb.xp) * R(0, nb.xp) * R(1, nb.xp_zm);
+        a_y_zp = R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
+        a_z_xp = R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
+        a_z_yp = R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
+    } else {
+        a_x_yp = prior<EP>(S, it, 0, nb.yp) * R(8, nb.yp) * R(4, nb.yp) * R(5, nb.yp_zm);
+        a_x_zp = prior<EP>(S, it, 0, nb.zp) * R(8, nb.zp) * R(4, nb.zp) * R(9, nb.zp_ym);
+        a_y_xp = prior<EP>(S, it, 1, nb.xp) * R(10, nb.xp) * R(0, nb.xp) * R(1, nb.xp_zm);
+        a_y_zp = prior<EP>(S, it, 1, nb.zp) * R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
+        a_z_xp = prior<EP>(S, it, 2, nb.xp) * R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
+        a_z_yp = prior<EP>(S, it, 2, nb.yp) * R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
+    }
     char* outb = reinterpret_cast<char*>(b_out + word_base(it.w, 12 * (int64_t)S.N)) +
                  (int64_t)v * R.site_bytes;
 #pragma unroll
@@ -250,14 +274,24 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
         if (n == 2) {  // normal z: e(v,x), e(v+y,x), e(v,y), e(v+x,y)
             a[0] = px * o4; a[1] = a_x_yp; a[2] = py * o0; a[3] = a_y_xp;
         } else if (n == 1) {  // normal y: e(v,x), e(v+z,x), e(v,z), e(v+x,z)
-            a[0] = px * o8; a[1] = a_x_zp; a[2] = pz * o2; a[3] = a_z_xp;
+            a[0] = FOLD == 2 ? fx * o8 : px * o8; a[1] = a_x_zp; a[2] = pz * o2;
+            a[3] = a_z_xp;
         } else {  // normal x: e(v,y), e(v+z,y), e(v,z), e(v+y,z)
-            a[0] = py * o10; a[1] = a_y_zp; a[2] = pz * o6; a[3] = a_z_yp;
+            a[0] = FOLD == 2 ? fy * o10 : py * o10; a[1] = a_y_zp;
+            a[2] = FOLD == 2 ? fz * o6 : pz * o6; a[3] = a_z_yp;
         }
         const uint64_t sw = S.syn[((int64_t)n * S.N + v) * S.ld_syn + it.w];
         const float sK = ((sw >> it.lane) & 1u) ? -K : K;
         float out[4];
         check_rule(a, sK, out);
+        if constexpr (FOLD != 0) {  // slots 8, 10, 6 carry the priors of e(v,x), e(v,y), e(v,z)
+            if (n == 2) {
+                out[0] *= ex;
+                out[2] *= ey;
+            } else if (n == 1) {
+                out[2] *= ez;
+            }
+        }
         // streaming stores: the new messages are read again only in the next
         // iteration, so they should not evict the neighbour rows from L2
 #pragma unroll
@@ -266,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
     }
 }
 
-template <int MODE, bool EP>
+template <int MODE, bool EP, bool FOLDED>
 __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
                                                     uint64_t* __restrict__ corr, int64_t ld_c,
                                                     float* __restrict__ post) {
@@ -275,11 +309,15 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
     const Reader<MODE> R = reader_of<MODE>(S, it);
     const Nbr nb = neighbours(it, tl.L);
     const int v = it.v;
-    // e^l = e^{l0} times the four incoming messages (E4)
+    // e^l = e^{l0} times the four incoming messages (E4); in a folded state
+    // slots 8, 10, 6 already carry the factor e^{l0}
+    const float ex = FOLDED ? 1.0f : prior<EP>(S, it, 0, v);
+    const float ey = FOLDED ? 1.0f : prior<EP>(S, it, 1, v);
+    const float ez = FOLDED ? 1.0f : prior<EP>(S, it, 2, v);
     float el[3];
-    el[0] = prior<EP>(S, it, 0, v) * R(8, v) * R(4, v) * R(9, nb.ym) * R(5, nb.zm);
-    el[1] = prior<EP>(S, it, 1, v) * R(10, v) * R(0, v) * R(11, nb.xm) * R(1, nb.zm);
-    el[2] = prior<EP>(S, it, 2, v) * R(6, v) * R(2, v) * R(7, nb.xm) * R(3, nb.ym);
+    el[0] = ex * R(8, v) * R(4, v) * R(9, nb.ym) * R(5, nb.zm);
+    el[1] = ey * R(10, v) * R(0, v) * R(11, nb.xm) * R(1, nb.zm);
+    el[2] = ez * R(6, v) * R(2, v) * R(7, nb.xm) * R(3, nb.ym);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int64_t e = (int64_t)c * S.N + v;
@@ -350,19 +388,23 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     const Src S = make_src(g, a, nu_in);
     const dim3 grid((unsigned)blocks), block(kBlock);
     if (a.llr0) {
-        if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        if (mode == NU_ZERO && a.fold)
+            k_bp_iter<NU_ZERO, true, 1><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        else if (mode == NU_ZERO)
+            k_bp_iter<NU_ZERO, true, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+        else if (mode == NU_LOAD && a.fold)
+            k_bp_iter<NU_LOAD, true, 2><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
         else if (mode == NU_LOAD)
-            k_bp_iter<NU_LOAD, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_LOAD, true, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
         else
             return TC3D_EINVAL;  // the syndrome-implied first state needs a scalar prior
     } else {
         if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, false><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_ZERO, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
         else if (mode == NU_SIGMA)
-            k_bp_iter<NU_SIGMA, false><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_SIGMA, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
         else
-            k_bp_iter<NU_LOAD, false><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_LOAD, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
     }
     return after_launch(c);
 }
@@ -378,17 +420,20 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     const Src S = make_src(g, a, nu);
     const dim3 grid((unsigned)blocks), block(kBlock);
     if (a.llr0) {
-        if (mode == NU_LOAD)
-            k_bp_post<NU_LOAD, true><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld, post);
+        if (mode != NU_LOAD) return TC3D_EINVAL;  // a posterior follows a stored iteration
+        if (a.fold)
+            k_bp_post<NU_LOAD, true, true><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld,
+                                                                        post);
         else
-            return TC3D_EINVAL;  // a posterior follows at least one stored iteration
+            k_bp_post<NU_LOAD, true, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
+                                                                         corr.ld, post);
     } else {
         if (mode == NU_SIGMA)
-            k_bp_post<NU_SIGMA, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld,
-                                                                    post);
+            k_bp_post<NU_SIGMA, false, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
+                                                                           corr.ld, post);
         else if (mode == NU_LOAD)
-            k_bp_post<NU_LOAD, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld,
-                                                                   post);
+            k_bp_post<NU_LOAD, false, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
+                                                                          corr.ld, post);
         else
             return TC3D_EINVAL;
     }

@@ -91,6 +91,7 @@ struct BpArgs {
     int64_t nw;          // words in the batch
     int64_t s_pad;       // 64 * nw
     int tile;            // site-tile edge of the traversal order (0: automatic)
+    bool fold;           // per-edge priors folded into the stored state (see tc3d_bp.hip)
 };
 
 // Fills the derived fields of BpArgs (in double precision, then rounded).

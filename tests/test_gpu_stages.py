@@ -299,6 +299,45 @@ def test_bp_decode_matches_chained_steps():
     assert np.allclose(a, b, rtol=1e-5, atol=1e-5), np.abs(a - b).max()
 
 
+@pytest.mark.parametrize("L,n_shots", [(5, 100), (6, 256)])
+def test_bp_decode_per_edge_prior(L, n_shots):
+    """A whole decode with per-edge priors keeps each edge's prior folded into
+    one stored message; its posteriors equal those of chained bp_step calls
+    (plain state) to FP32 rounding, and its hard decisions equal the oracle's
+    free-running FP64 decode except on posteriors within 1e-3 of zero."""
+    announce(f"bp decode per-edge prior L={L} S={n_shots}")
+    import torch
+    p = q = 0.05
+    o, syn, W, full = _bp_inputs(L, n_shots, 41 + L)
+    lat = tc.make_lattice(L)
+    N = L ** 3
+    d_syn = dev_plane_of_bits(syn)
+    K = 1 - 2 * q
+    llr_f32 = inputs.random_llr(L, full, o.n_edges, 0.5, 5.0).astype(np.float32)
+    d_llr = to_dev(inputs.rows_to_gpu(llr_f32))
+    iters = 12
+    post_a = torch.zeros((W, 3 * N, 64), dtype=torch.float32, device="cuda")
+    corr = torch.zeros((3 * N, W), dtype=torch.int64, device="cuda")
+    ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
+    tc.bp_decode(lat, d_syn, n_shots, d_llr, 0.0, K, iters, corr, post_a, ws)
+    nu = [torch.zeros((W, N, 12, 64), dtype=torch.float32, device="cuda") for _ in range(2)]
+    post_b = torch.zeros_like(post_a)
+    prev = None
+    for t in range(iters):
+        tc.bp_step(lat, d_syn, n_shots, d_llr, 0.0, K, prev, nu[t % 2], post_b)
+        prev = nu[t % 2]
+    sync()
+    a, b = post_a.cpu().numpy(), post_b.cpu().numpy()
+    assert np.allclose(a, b, rtol=1e-4, atol=1e-4), np.abs(a - b).max()
+    c_o, p_o = o.bp_decode(syn[:n_shots], p, q, iters,
+                           llr0=llr_f32[:n_shots].astype(np.float64))
+    c_g = bits_of_dev(corr, n_shots)
+    mism = c_g != c_o
+    announce(f"  hard-decision mismatches {int(mism.sum())}, max |post a-b| "
+             f"{np.abs(a - b).max():.3e}")
+    assert (np.abs(p_o[mism]) < LLR_TIE).all(), np.abs(p_o[mism]).max()
+
+
 def test_zero_syndrome_scalar_recursion_on_gpu():
     """With no unsatisfied check every posterior equals the closed-form scalar
     recursion l0 + 4 nu_T."""
