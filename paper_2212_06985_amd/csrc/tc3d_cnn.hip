@@ -16,16 +16,18 @@
 // weights as the A operand (16 output channels x 32 input channels of one
 // tap, or of the three x-taps of one (dy, dz) column for 8 input channels)
 // and the activations of 16 shots at one site as the B operand: each B
-// fragment is one contiguous 16-row slab. A wavefront owns a run of NX sites
-// along x of one pencil (y, z) for 16 shots; for each of the 9 (dy, dz)
-// columns it loads the NX + 2 neighbouring slabs once and applies the three
-// x-taps to them from registers, so every activation slab is fetched
-// (NX + 2) / NX times per column instead of 3. The weights of all taps sit in
-// LDS in lane order. The backward pass uses the same kernel with the taps
+// fragment is one contiguous 16-row slab. A wavefront owns NX sites along x
+// in each of BY adjacent y-pencils at one z, for 16 shots. It walks the
+// 3 (BY + 2) neighbouring pencil columns (dz, y), loads the NX + 2 slabs of
+// each once and applies to them, from registers, the three x-taps of every
+// output pencil the column neighbours: a 2 x 2 shape loads 12 slabs per
+// output site instead of 27. The weights of all taps sit in LDS in lane order. The backward pass uses the same kernel with the taps
 // reversed and the weights transposed (dX[u] = sum_d W[d]^T dY[u - off(d)]),
 // and a separate weight-gradient kernel (a GEMM over rows, staged transposed
 // in LDS).
 #include <math.h>
+
+#include <atomic>
 
 #include "tc3d_device.hpp"
 #include "tc3d_internal.hpp"
@@ -615,8 +617,37 @@ CnnWs carve(void* ws, int64_t R, int training) {
     return w;
 }
 
-constexpr int kConvNX = 2;  // sites per wavefront run along x
-constexpr int kConvBY = 2;  // y-pencils per wavefront (32-channel inputs)
+// Wavefront shape of each convolution, chosen by timing. The 32 -> 3 layer
+// keeps one output tile of accumulators per site, so it affords a larger
+// shape, which cuts its neighbour-slab loads per output site from 12 to 7.5.
+template <int CIN, int EPI>
+struct ConvShape {
+    static constexpr int NX = EPI == EPI_LLR ? 4 : 2;  // sites per wavefront run along x
+    static constexpr int BY = EPI == EPI_LLR ? 3 : 2;  // y-pencils per wavefront
+};
+
+// Workgroups of a persistent conv launch: as many as the GPU holds at once
+// (occupancy times compute units), found once per device. A grid of several
+// rounds of workgroups re-stages the weights and leaves a ragged last round.
+template <typename K>
+int resident_blocks(K kernel, int block, std::atomic<int>* cache, int n_cache) {
+    constexpr int kFallback = 512;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= n_cache) return kFallback;
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (c == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            per_cu < 1 || cus < 1)
+            return kFallback;
+        c = per_cu * cus;
+        cache[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
 
 // Rows of shot groups sg0 .. sg0 + n_sg - 1 (16 shots each); one wavefront
 // item per (shot group, pencil, x-run).
@@ -626,18 +657,20 @@ int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     ConvItems it;
     it.L = g.L;
     it.N = g.N;
-    constexpr int BY = CIN == 32 ? kConvBY : 1;
-    it.nxr = (g.L + kConvNX - 1) / kConvNX;
+    constexpr int NX = ConvShape<CIN, EPI>::NX, BY = ConvShape<CIN, EPI>::BY;
+    it.nxr = (g.L + NX - 1) / NX;
     const int64_t items = n_sg * (int64_t)g.L * ((g.L + BY - 1) / BY) * it.nxr;
     if (items >= (1ll << 32) || sg0 + n_sg >= (1ll << 32)) return TC3D_EINVAL;
     if (items == 0) return TC3D_OK;
     it.n_items = (uint32_t)items;
     it.sg0 = (uint32_t)sg0;
     const int64_t blocks = cdiv(items, kConvWaves);
-    const int grid = (int)(blocks < 1024 ? blocks : 1024);
+    static std::atomic<int> resident[64];
+    const int cap = resident_blocks(k_conv<CIN, EPI, NX, BY>, kConvBlock, resident, 64);
+    const int grid = (int)(blocks < cap ? blocks : cap);
     int rc = before_launch(c, TC3D_K_CNN);
     if (rc) return rc;
-    k_conv<CIN, EPI, kConvNX, BY><<<dim3(grid), dim3(kConvBlock), 0, c.stream>>>(
+    k_conv<CIN, EPI, NX, BY><<<dim3(grid), dim3(kConvBlock), 0, c.stream>>>(
         x, wp, bias, mask_act, y, llr, it);
     return after_launch(c);
 }

@@ -67,7 +67,7 @@ def z_from_llr(llr, L, S):
     return -rows.reshape(S, 3, N).transpose(0, 2, 1).astype(np.float64)
 
 
-@pytest.mark.parametrize("L,S", [(3, 64), (4, 100), (6, 64)])
+@pytest.mark.parametrize("L,S", [(3, 64), (4, 100), (5, 64), (6, 64), (7, 64)])
 def test_forward_parity(L, S):
     import torch
     announce(f"cnn forward L={L} S={S}")
@@ -97,7 +97,7 @@ def test_forward_parity(L, S):
     assert np.linalg.norm(z_from_llr(llr, L, full) - z_o0) / np.linalg.norm(z_o0) < 1e-2
 
 
-@pytest.mark.parametrize("L,S", [(3, 64), (4, 128)])
+@pytest.mark.parametrize("L,S", [(3, 64), (4, 128), (5, 64)])
 def test_gradient_parity(L, S):
     import torch
     announce(f"cnn gradient L={L} S={S}")
