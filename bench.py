@@ -293,10 +293,13 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
     return wall, per_class, ler, resid
 
 
-def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0):
+def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
+             per_edge_prior=False):
     """Roofline of the dominant kernel class, from the HIP-event launch times.
     For the CNN class, `forwards` forward passes over `shots_padded` shots
-    (whole 64-shot words) were timed."""
+    (whole 64-shot words) were timed. With a per-edge prior, the BP iterations
+    also read each edge's FP32 prior (4 more bytes per edge-shot); the
+    posterior reads none, as a decode keeps the priors folded into its state."""
     dom = max(per_class, key=lambda k: per_class[k]["ms"])
     d = per_class[dom]
     avg_ms = d["ms"] / max(d["launches"], 1)
@@ -311,6 +314,8 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0)
                 "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
                 "unit_of_work": "site-shot forward (passes of 5 launches)"}
     per_unit, unit = ALGO_BYTES[dom]
+    if per_edge_prior and dom in ("bp_iter", "bp_first"):
+        per_unit += 4.0
     # a launch covers one batch of shots; with uneven batches (the last one of
     # a step may be smaller) the average launch carries shots / batches
     shots = shots_padded if shots_padded else batch
@@ -466,9 +471,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(shots shard across GPUs with no exchange but a final 8-counter sum; "
-              "see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (shots "
+              "would shard across GPUs with no exchange but a final sum of 8 mask "
+              "counters). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -522,7 +527,7 @@ def main():
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
     roof = roofline(per_class, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
-                    shots_padded=64 * W)
+                    shots_padded=64 * W, per_edge_prior=decoder == "cnn")
     # with the CNN prior, the conv launches' own (MFMA) roofline as well
     cnn_roof = None
     if decoder == "cnn" and per_class["cnn"]["launches"]:
@@ -539,7 +544,8 @@ def main():
                       "ms_per_step": w2 / steps * 1e3, "ler": ler2,
                       "mean_residual_syndrome": resid2,
                       "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload,
-                                           forwards=cycles * steps, shots_padded=64 * W),
+                                           forwards=cycles * steps, shots_padded=64 * W,
+                                           per_edge_prior=other == "cnn"),
                       "kernel_ms": {k: round(v["ms"], 3) for k, v in pc2.items()}}
 
     cpu = None

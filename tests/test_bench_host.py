@@ -1,0 +1,59 @@
+"""Host logic of bench.py: the roofline arithmetic and the one-GPU refusal."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _cls(**kw):
+    base = {k: {"ms": 0.0, "launches": 0} for k in ("bp_iter", "bp_first", "bp_post", "cnn")}
+    base.update(kw)
+    return base
+
+
+def test_bp_roofline_counts_32_bytes_per_edge_shot():
+    # 10 launches of 2 ms, each over 3 * 1000 edges x 2048 shots
+    pc = _cls(bp_iter={"ms": 20.0, "launches": 10})
+    r = bench.roofline(pc, 3000, 2048, 1000, "none", shots_padded=2048)
+    assert r["kernel"] == "bp_iter" and r["bound"] == "hbm"
+    assert r["algo_bytes_per_launch"] == 32.0 * 3000 * 2048
+    assert r["achieved"] == pytest.approx(32.0 * 3000 * 2048 / 2e-3 / 1e9, rel=1e-3)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)  # rounded to 4 places
+
+
+def test_per_edge_prior_adds_the_prior_read():
+    pc = _cls(bp_iter={"ms": 20.0, "launches": 10})
+    r = bench.roofline(pc, 3000, 2048, 1000, "none", shots_padded=2048, per_edge_prior=True)
+    assert r["algo_bytes_per_unit"] == 36.0
+
+
+def test_uneven_batches_average_the_shots_per_launch():
+    # 5000 shots in batches of 2048: 3 launches per iteration carry 5000 / 3 shots each
+    pc = _cls(bp_iter={"ms": 30.0, "launches": 3})
+    r = bench.roofline(pc, 3000, 2048, 1000, "none", shots_padded=5000)
+    assert r["algo_bytes_per_launch"] == pytest.approx(32.0 * 3000 * 5000 / 3)
+
+
+def test_cnn_roofline_is_flop_over_all_forwards():
+    pc = _cls(cnn={"ms": 50.0, "launches": 25}, bp_iter={"ms": 1.0, "launches": 1})
+    r = bench.roofline(pc, 3000, 4096, 1000, "none", forwards=5, shots_padded=4096)
+    assert r["bound"] == "mfma"
+    flop = bench.CNN_FLOP_PER_SITE * 1000 * 4096 * 5
+    assert r["achieved"] == pytest.approx(flop / 50e-3 / 1e12, rel=1e-3)
+
+
+def test_cnn_flop_per_site_matches_the_network():
+    ch = [8, 32, 32, 32, 3]
+    assert bench.CNN_FLOP_PER_SITE == sum(2 * 27 * a * b for a, b in zip(ch, ch[1:]))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "--gpus 1" in r.stderr
