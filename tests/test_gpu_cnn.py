@@ -251,3 +251,67 @@ def test_trained_prior_lowers_the_logical_error_rate():
     sig = math.sqrt(base["ler_any_sigma"] ** 2 + cnn["ler_any_sigma"] ** 2)
     assert base["ler_any"] - cnn["ler_any"] > 3 * sig
     assert cnn["mean_residual_syndrome"] < base["mean_residual_syndrome"]
+
+
+def _roll_sites(a, L, t, site_axis):
+    """Translate the sites of a per-site array by t = (tx, ty, tz): the value
+    at v moves to v + t (periodic). `site_axis` holds 3 L^3 rows, class-major
+    (row c L^3 + v, v = x + L y + L^2 z)."""
+    shape = a.shape[:site_axis] + (3, L, L, L) + a.shape[site_axis + 1:]
+    b = a.reshape(shape)
+    tx, ty, tz = t
+    b = np.roll(b, (tz, ty, tx), axis=(site_axis + 1, site_axis + 2, site_axis + 3))
+    return b.reshape(a.shape)
+
+
+@pytest.mark.parametrize("L,S", [(24, 1024), (25, 256)])
+def test_forward_translation_equivariance_full_size(L, S):
+    """The network commutes with lattice translations, and the kernels compute
+    every site with the same operations in the same order, whatever its place
+    in a wavefront's tile or a pass: translating the syndromes translates the
+    priors bit for bit, at the workload's lattice size (L = 25: ragged tiles)."""
+    import torch
+    announce(f"cnn forward translation L={L} S={S}")
+    lat = tc.make_lattice(L)
+    W = inputs.n_words(S)
+    full = 64 * W
+    n = 3 * L ** 3
+    syn = inputs.random_bits(5 + L, full, n, 0.1)
+    prev = inputs.random_bits(6 + L, full, n, 0.05)
+    _, packed = packed_of(random_params(7 + L))
+    ws = tc.alloc_workspace(tc.cnn_workspace_bytes(lat, S))
+    t = (1, 2, 5)
+    outs = []
+    for a, b in ((syn, prev), (_roll_sites(syn, L, t, 1), _roll_sites(prev, L, t, 1))):
+        llr = torch.zeros((W, n, 64), dtype=torch.float32, device="cuda")
+        tc.cnn_forward(lat, dev_plane_of_bits(a), dev_plane_of_bits(b), S, packed, llr, ws)
+        sync()
+        outs.append(llr.cpu().numpy())
+    assert np.array_equal(_roll_sites(outs[0], L, t, 1), outs[1])
+
+
+def test_folded_bp_translation_equivariance_full_size():
+    """A whole decode with per-edge priors (folded into the state) commutes
+    with lattice translations bit for bit at L = 24: every site runs the same
+    arithmetic whatever the traversal order."""
+    import torch
+    L, S, iters = 24, 2048, 6
+    announce(f"folded bp translation L={L} S={S}")
+    lat = tc.make_lattice(L)
+    W = inputs.n_words(S)
+    n = 3 * L ** 3
+    syn = inputs.random_bits(11, S, n, 0.05)
+    llr = inputs.random_llr(12, S, n, 0.5, 5.0).astype(np.float32)
+    ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, S))
+    t = (3, 1, 2)
+    posts, corrs = [], []
+    for a, l0 in ((syn, llr), (_roll_sites(syn, L, t, 1), _roll_sites(llr, L, t, 1))):
+        post = torch.zeros((W, n, 64), dtype=torch.float32, device="cuda")
+        corr = torch.zeros((n, W), dtype=torch.int64, device="cuda")
+        tc.bp_decode(lat, dev_plane_of_bits(a), S, to_dev(inputs.rows_to_gpu(l0)), 0.0,
+                     1 - 2 * 0.05, iters, corr, post, ws)
+        sync()
+        posts.append(post.cpu().numpy())
+        corrs.append(bits_of_dev(corr, S))
+    assert np.array_equal(_roll_sites(posts[0], L, t, 1), posts[1])
+    assert np.array_equal(_roll_sites(corrs[0], L, t, 1), corrs[1])
