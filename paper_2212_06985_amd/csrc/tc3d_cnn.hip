@@ -14,17 +14,21 @@
 //
 // Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16 with the
 // weights as the A operand (16 output channels x 32 input channels of one
-// tap, or of the three x-taps of one (dy, dz) column for 8 input channels)
-// and the activations of 16 shots at one site as the B operand: each B
-// fragment is one contiguous 16-row slab. A wavefront owns NX sites along x
-// in each of BY adjacent y-pencils at one z, for 16 shots. It walks the
-// 3 (BY + 2) neighbouring pencil columns (dz, y), loads the NX + 2 slabs of
-// each once and applies to them, from registers, the three x-taps of every
-// output pencil the column neighbours: a 2 x 2 shape loads 12 slabs per
-// output site instead of 27. The weights of all taps sit in LDS in lane order. The backward pass uses the same kernel with the taps
-// reversed and the weights transposed (dX[u] = sum_d W[d]^T dY[u - off(d)]),
-// and a separate weight-gradient kernel (a GEMM over rows, staged transposed
-// in LDS).
+// tap, or of the three x-taps of one (dy, dz) column for 8 input channels),
+// read from LDS in lane order, and the activations of 16 shots at one site as
+// the B operand: each B fragment is one contiguous 16-row slab. A wavefront
+// reuses every slab it loads from registers for all the output sites of its
+// tile the slab neighbours:
+//   k_convz (the forward 32-channel layers) walks a column of NX x BY sites
+//   along z; each input plane is loaded once and feeds the three output
+//   planes around it, whose accumulators stay in registers: 7 slab loads per
+//   output site for the 32 -> 32 layers instead of 27;
+//   k_conv (the 8 -> 32 layer and the backward pass) owns NX x BY sites of
+//   one plane and loads the NX + 2 slabs of each of its 3 (BY + 2)
+//   neighbouring pencil columns once.
+// The backward pass uses k_conv with the taps reversed and the weights
+// transposed (dX[u] = sum_d W[d]^T dY[u - off(d)]), and a separate
+// weight-gradient kernel (a GEMM over rows, staged transposed in LDS).
 #include <math.h>
 
 #include <atomic>
@@ -191,18 +195,18 @@ struct ConvItems {
 };
 
 
-// x rows [R][CIN] BF16 (CIN = 8 or 32); packed block [KS][NT][64][8].
+// x rows [R][CIN] BF16 (CIN = 8 or 32); packed block [KS][2][64][8]. Used for
+// the 8 -> 32 forward layer and the backward-data convolutions.
 //  EPI_RELU: y = relu(acc + bias) as BF16 [R][32]
-//  EPI_LLR : llr[(w 3 + c) N + v][l] = -(acc + bias) for c < 3 (NT = 1)
 //  EPI_MASK: y = acc where mask_act > 0 else 0, BF16 [R][32]
 // Every variant reads x[v + off(d)]; the backward-data blocks carry the
 // reversed taps in their packing.
 template <int CIN, int EPI, int NX, int BY>
 __global__ __launch_bounds__(kConvBlock) void k_conv(
     const bf16* __restrict__ x, const bf16* __restrict__ wp, const float* __restrict__ bias,
-    const bf16* __restrict__ mask_act, bf16* __restrict__ y, float* __restrict__ llr,
-    ConvItems it) {
-    constexpr int NT = EPI == EPI_LLR ? 1 : 2;
+    const bf16* __restrict__ mask_act, bf16* __restrict__ y, ConvItems it) {
+    static_assert(EPI == EPI_RELU || EPI == EPI_MASK, "the 32 -> 3 layer runs in k_convz");
+    constexpr int NT = 2;
     constexpr int KS = CIN == 32 ? 27 : 9;
     constexpr int WELEMS = KS * NT * 64 * 8;
     constexpr int NB = CIN == 32 ? NX + 2 : NX;  // B fragments per pencil column
@@ -339,32 +343,199 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
                 if (x0 + i >= L) break;
                 const int64_t v = vrow + x0 + i;
                 const int64_t row = (wrow + v) * 64 + l0 + r16;
-                if constexpr (EPI == EPI_LLR) {
-                    if (q == 0) {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            llr[((w * 3 + c) * N + v) * 64 + l0 + r16] =
-                                -(acc[by][i][0][c] + bv[0][c]);
+                for (int mt = 0; mt < NT; ++mt) {
+                    const int64_t o = row * 32 + 16 * mt + 4 * q;
+                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                    bf16x4 out;
+                    if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            out[e] = (bf16)fmaxf(acc[by][i][mt][e] + bv[mt][e], 0.f);
+                    } else {
+                        const bf16x4 m = *reinterpret_cast<const bf16x4*>(mask_act + o);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            out[e] = (float)m[e] > 0.f ? (bf16)acc[by][i][mt][e] : (bf16)0.f;
                     }
-                } else {
+                    *reinterpret_cast<bf16x4*>(y + o) = out;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------- conv marching along z (MFMA)
+// The forward 32-channel layers walk columns of sites along z instead: a
+// wavefront owns NX x BY sites of an (x, y) column over a segment of zs
+// consecutive planes, for 16 shots. Every input plane of the segment and
+// its two neighbours is loaded once, row by row ((NX + 2)(BY + 2) slabs),
+// and feeds the output planes below, at and above it. Their accumulators
+// stay in registers as a ring of three: after input plane z the output
+// plane z - 1 has all 27 taps and is written. That is (NX + 2)(BY + 2)
+// (zs + 2) / (NX BY zs) slab loads per output site, 5 for 2 x 2 x 8, against
+// 12 when every output plane loads its three input planes itself.
+constexpr int kConvZWaves = 8;
+constexpr int kConvZBlock = 64 * kConvZWaves;
+
+struct ConvZItems {
+    int L, N;
+    int nxr, ny, nzs, zs;  // x-runs, y-groups, z-segments of zs planes (the last may be short)
+    uint32_t n_items;      // n_sg nzs ny nxr, for shot groups sg0 .. sg0 + n_sg - 1
+    uint32_t sg0;
+};
+
+template <int EPI, int NX, int BY>
+__global__ __launch_bounds__(kConvZBlock) void k_convz(
+    const bf16* __restrict__ x, const bf16* __restrict__ wp, const float* __restrict__ bias,
+    bf16* __restrict__ y, float* __restrict__ llr, ConvZItems it) {
+    static_assert(EPI == EPI_RELU || EPI == EPI_LLR, "forward layers only");
+    constexpr int CIN = 32;
+    constexpr int NT = EPI == EPI_LLR ? 1 : 2;
+    constexpr int WELEMS = 27 * NT * 64 * 8;
+    constexpr int NB = NX + 2;  // slabs per row
+    constexpr int NR = BY + 2;  // rows per input plane
+    __shared__ __attribute__((aligned(16))) bf16 wl[WELEMS];
+    for (int i = threadIdx.x * 8; i < WELEMS; i += kConvZBlock * 8)
+        *reinterpret_cast<bf16x8*>(wl + i) = *reinterpret_cast<const bf16x8*>(wp + i);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int r16 = lane & 15, q = lane >> 4;
+    const int L = it.L, N = it.N;
+    const int64_t G = gridDim.x;
+    const int64_t lb = xcd_block(blockIdx.x, G);
+    for (int64_t base = lb * kConvZWaves; base < it.n_items; base += G * kConvZWaves) {
+        const uint32_t item = (uint32_t)(base + wave);
+        if (item >= it.n_items) break;
+        // wave-uniform decode: x-run, y-group, z-segment, shot group
+        uint32_t t = item;
+        const int xr = (int)(t % (uint32_t)it.nxr);
+        t /= (uint32_t)it.nxr;
+        const int y0 = BY * (int)(t % (uint32_t)it.ny);
+        t /= (uint32_t)it.ny;
+        const int z0 = it.zs * (int)(t % (uint32_t)it.nzs);
+        t /= (uint32_t)it.nzs;
+        const uint32_t sg = it.sg0 + t;
+        const int zn = L - z0 < it.zs ? L - z0 : it.zs;  // output planes of this segment
+        const int64_t w = sg >> 2;
+        const int l0 = 16 * (int)(sg & 3);
+        const int x0 = xr * NX;
+        const int64_t wrow = w * N;
+        const int lane_off = (l0 + r16) * CIN + 8 * q;
+        int ux[NB];
 #pragma unroll
-                    for (int mt = 0; mt < NT; ++mt) {
-                        const int64_t o = row * 32 + 16 * mt + 4 * q;
-                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                        bf16x4 out;
-                        if constexpr (EPI == EPI_RELU) {
+        for (int i = 0; i < NB; ++i) ux[i] = wrap(x0 - 1 + i, L);
+        // acc[k]: output plane zi - 1 + k of the current input plane zi
+        f32x4 acc[3][BY][NX][NT];
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                out[e] = (bf16)fmaxf(acc[by][i][mt][e] + bv[mt][e], 0.f);
-                        } else {
-                            const bf16x4 m = *reinterpret_cast<const bf16x4*>(mask_act + o);
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                out[e] = (float)m[e] > 0.f ? (bf16)acc[by][i][mt][e] : (bf16)0.f;
+            for (int by = 0; by < BY; ++by)
+#pragma unroll
+                for (int i = 0; i < NX; ++i)
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt) acc[k][by][i][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // step s: input plane zi = z0 - 1 + s / NR, row y0 - 1 + s % NR
+        auto load_row = [&](int s, bf16x8 (&b)[NB]) {
+            const int uz = wrap(z0 - 1 + s / NR, L), uy = wrap(y0 - 1 + s % NR, L);
+            const int64_t pencil = (wrow + (int64_t)L * (uy + (int64_t)L * uz)) * 64;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                b[i] = *reinterpret_cast<const bf16x8*>(x + (pencil + (int64_t)ux[i] * 64) * CIN +
+                                                        lane_off);
+        };
+        auto store_plane = [&](int zo, const f32x4 (&a)[BY][NX][NT]) {
+            // the bias is read here, once per plane, to keep it out of the
+            // registers the accumulator ring needs
+            float bv[NT][4];
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bv[mt][i] = bias[16 * mt + 4 * q + i];
+#pragma unroll
+            for (int by = 0; by < BY; ++by) {
+                if (y0 + by >= L) break;
+                const int64_t vrow = (int64_t)L * (y0 + by + (int64_t)L * zo);
+#pragma unroll
+                for (int i = 0; i < NX; ++i) {
+                    if (x0 + i >= L) break;
+                    const int64_t v = vrow + x0 + i;
+                    if constexpr (EPI == EPI_LLR) {
+                        if (q == 0) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c)
+                                llr[((w * 3 + c) * N + v) * 64 + l0 + r16] =
+                                    -(a[by][i][0][c] + bv[0][c]);
                         }
-                        *reinterpret_cast<bf16x4*>(y + o) = out;
+                    } else {
+                        const int64_t row = (wrow + v) * 64 + l0 + r16;
+#pragma unroll
+                        for (int mt = 0; mt < NT; ++mt) {
+                            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                            bf16x4 out;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                out[e] = (bf16)fmaxf(a[by][i][mt][e] + bv[mt][e], 0.f);
+                            *reinterpret_cast<bf16x4*>(y + row * 32 + 16 * mt + 4 * q) = out;
+                        }
                     }
                 }
+            }
+        };
+        auto step = [&](int s, const bf16x8 (&b)[NB]) {
+            const int p = s / NR, r = s % NR;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int oz = p - 2 + k;  // output plane z0 + oz, tap dz = 1 - k
+                if (oz < 0 || oz >= zn) continue;
+#pragma unroll
+                for (int by = 0; by < BY; ++by) {
+                    const int dy = r - 1 - by;
+                    if (dy < -1 || dy > 1) continue;
+                    const int tap0 = 3 * (dy + 1) + 9 * (2 - k);
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        bf16x8 a[NT];
+#pragma unroll
+                        for (int mt = 0; mt < NT; ++mt)
+                            a[mt] = *reinterpret_cast<const bf16x8*>(
+                                wl + (((tap0 + dx) * NT + mt) * 64 + lane) * 8);
+#pragma unroll
+                        for (int i = 0; i < NX; ++i)
+#pragma unroll
+                            for (int mt = 0; mt < NT; ++mt)
+                                acc[k][by][i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    a[mt], b[i + dx], acc[k][by][i][mt], 0, 0, 0);
+                    }
+                }
+            }
+            if (r == NR - 1) {
+                // input plane done: output plane zi - 1 has all its taps
+                if (p >= 2 && p - 2 < zn) store_plane(z0 + p - 2, acc[0]);
+#pragma unroll
+                for (int by = 0; by < BY; ++by)
+#pragma unroll
+                    for (int i = 0; i < NX; ++i)
+#pragma unroll
+                        for (int mt = 0; mt < NT; ++mt) {
+                            acc[0][by][i][mt] = acc[1][by][i][mt];
+                            acc[1][by][i][mt] = acc[2][by][i][mt];
+                            acc[2][by][i][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                        }
+            }
+        };
+        // software pipeline over rows: the next row's slabs are in flight
+        // while the matrix cores work on the current one
+        const int n_steps = (zn + 2) * NR;
+        bf16x8 b0[NB], b1[NB];
+        load_row(0, b0);
+        for (int s = 0; s < n_steps; s += 2) {
+            if (s + 1 < n_steps) load_row(s + 1, b1);
+            step(s, b0);
+            if (s + 1 < n_steps) {
+                if (s + 2 < n_steps) load_row(s + 2, b0);
+                step(s + 1, b1);
             }
         }
     }
@@ -617,13 +788,11 @@ CnnWs carve(void* ws, int64_t R, int training) {
     return w;
 }
 
-// Wavefront shape of each convolution, chosen by timing. The 32 -> 3 layer
-// keeps one output tile of accumulators per site, so it affords a larger
-// shape, which cuts its neighbour-slab loads per output site from 12 to 7.5.
+// Wavefront shape of k_conv, chosen by timing.
 template <int CIN, int EPI>
 struct ConvShape {
-    static constexpr int NX = EPI == EPI_LLR ? 4 : 2;  // sites per wavefront run along x
-    static constexpr int BY = EPI == EPI_LLR ? 3 : 2;  // y-pencils per wavefront
+    static constexpr int NX = 2;  // sites per wavefront run along x
+    static constexpr int BY = 2;  // y-pencils per wavefront
 };
 
 // Workgroups of a persistent conv launch: as many as the GPU holds at once
@@ -653,7 +822,7 @@ int resident_blocks(K kernel, int block, std::atomic<int>* cache, int n_cache) {
 // item per (shot group, pencil, x-run).
 template <int CIN, int EPI>
 int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
-                const bf16* mask_act, bf16* y, float* llr, Geo g, int64_t sg0, int64_t n_sg) {
+                const bf16* mask_act, bf16* y, Geo g, int64_t sg0, int64_t n_sg) {
     ConvItems it;
     it.L = g.L;
     it.N = g.N;
@@ -671,7 +840,60 @@ int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     int rc = before_launch(c, TC3D_K_CNN);
     if (rc) return rc;
     k_conv<CIN, EPI, NX, BY><<<dim3(grid), dim3(kConvBlock), 0, c.stream>>>(
-        x, wp, bias, mask_act, y, llr, it);
+        x, wp, bias, mask_act, y, it);
+    return after_launch(c);
+}
+
+// Shape of the z-marching forward convolutions (x-sites x y-pencils).
+template <int EPI>
+struct ConvZShape {
+    static constexpr int NX = 2;
+    static constexpr int BY = EPI == EPI_LLR ? 2 : 1;
+};
+
+// Planes per z-segment: long segments load fewer extra planes ((zs + 2) / zs)
+// but make fewer work items; take the length that minimises the rounds of
+// resident wavefronts times the planes each item walks.
+int choose_zs(int L, int64_t columns, int64_t slots) {
+    int best = L;
+    int64_t best_cost = -1;
+    for (int zs = L; zs >= 1; --zs) {
+        const int64_t rounds = cdiv(columns * cdiv(L, zs), slots);
+        const int64_t cost = rounds * (zs + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best = zs;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+// Forward 32-channel layer over shot groups sg0 .. sg0 + n_sg - 1, marching
+// along z; one wavefront item per (shot group, z-segment, y-group, x-run).
+template <int EPI>
+int launch_convz(const Ctx& c, const bf16* x, const bf16* wp, const float* bias, bf16* y,
+                 float* llr, Geo g, int64_t sg0, int64_t n_sg) {
+    constexpr int NX = ConvZShape<EPI>::NX, BY = ConvZShape<EPI>::BY;
+    ConvZItems it;
+    it.L = g.L;
+    it.N = g.N;
+    it.nxr = (g.L + NX - 1) / NX;
+    it.ny = (g.L + BY - 1) / BY;
+    static std::atomic<int> resident[64];
+    const int cap = resident_blocks(k_convz<EPI, NX, BY>, kConvZBlock, resident, 64);
+    const int64_t columns = n_sg * it.ny * it.nxr;
+    it.zs = choose_zs(g.L, columns, (int64_t)cap * kConvZWaves);
+    it.nzs = (g.L + it.zs - 1) / it.zs;
+    const int64_t items = columns * it.nzs;
+    if (items >= (1ll << 32) || sg0 + n_sg >= (1ll << 32)) return TC3D_EINVAL;
+    if (items == 0) return TC3D_OK;
+    it.n_items = (uint32_t)items;
+    it.sg0 = (uint32_t)sg0;
+    const int64_t blocks = cdiv(items, kConvZWaves);
+    const int grid = (int)(blocks < cap ? blocks : cap);
+    int rc = before_launch(c, TC3D_K_CNN);
+    if (rc) return rc;
+    k_convz<EPI, NX, BY><<<dim3(grid), dim3(kConvZBlock), 0, c.stream>>>(x, wp, bias, y, llr, it);
     return after_launch(c);
 }
 
@@ -703,16 +925,16 @@ int cnn_forward_impl(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* p
         const int64_t k = n_sg - sg0 < per ? n_sg - sg0 : per;
         if ((rc = launch_input(c, g, syn, prev, ld, sg0, k, w.x0))) return rc;
         if ((rc = launch_conv<8, EPI_RELU>(c, w.x0, blk(packed, 0), bias_of(packed, 0), nullptr,
-                                           w.a[0], nullptr, g, sg0, k)))
+                                           w.a[0], g, sg0, k)))
             return rc;
-        if ((rc = launch_conv<32, EPI_RELU>(c, w.a[0], blk(packed, 1), bias_of(packed, 1),
-                                            nullptr, w.a[1], nullptr, g, sg0, k)))
+        if ((rc = launch_convz<EPI_RELU>(c, w.a[0], blk(packed, 1), bias_of(packed, 1), w.a[1],
+                                         nullptr, g, sg0, k)))
             return rc;
-        if ((rc = launch_conv<32, EPI_RELU>(c, w.a[1], blk(packed, 2), bias_of(packed, 2),
-                                            nullptr, w.a[2], nullptr, g, sg0, k)))
+        if ((rc = launch_convz<EPI_RELU>(c, w.a[1], blk(packed, 2), bias_of(packed, 2), w.a[2],
+                                         nullptr, g, sg0, k)))
             return rc;
-        if ((rc = launch_conv<32, EPI_LLR>(c, w.a[2], blk(packed, 3), bias_of(packed, 3), nullptr,
-                                           nullptr, llr, g, sg0, k)))
+        if ((rc = launch_convz<EPI_LLR>(c, w.a[2], blk(packed, 3), bias_of(packed, 3), nullptr,
+                                        llr, g, sg0, k)))
             return rc;
     }
     return TC3D_OK;
@@ -777,20 +999,20 @@ int cnn_loss_grad(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev
     // layer 4 (32 -> 3): weight gradient, then dy of layer 3 through its ReLU
     if ((rc = launch_wgrad<32, 3>(c, w.a[2], w.dy8, g, R, w, grad + param_offset(3)))) return rc;
     const int64_t n_sg = R / (16 * (int64_t)g.N);
-    if ((rc = launch_conv<8, EPI_MASK>(c, w.dy8, blk(packed, 4), nullptr, w.a[2], w.dyb[0],
-                                       nullptr, g, 0, n_sg)))
+    if ((rc = launch_conv<8, EPI_MASK>(c, w.dy8, blk(packed, 4), nullptr, w.a[2], w.dyb[0], g,
+                                       0, n_sg)))
         return rc;
     // layer 3 (32 -> 32)
     if ((rc = launch_wgrad<32, 32>(c, w.a[1], w.dyb[0], g, R, w, grad + param_offset(2))))
         return rc;
     if ((rc = launch_conv<32, EPI_MASK>(c, w.dyb[0], blk(packed, 5), nullptr, w.a[1],
-                                        w.dyb[1], nullptr, g, 0, n_sg)))
+                                        w.dyb[1], g, 0, n_sg)))
         return rc;
     // layer 2 (32 -> 32)
     if ((rc = launch_wgrad<32, 32>(c, w.a[0], w.dyb[1], g, R, w, grad + param_offset(1))))
         return rc;
     if ((rc = launch_conv<32, EPI_MASK>(c, w.dyb[1], blk(packed, 6), nullptr, w.a[0],
-                                        w.dyb[0], nullptr, g, 0, n_sg)))
+                                        w.dyb[0], g, 0, n_sg)))
         return rc;
     // layer 1 (8 -> 32): weight gradient only
     return launch_wgrad<8, 32>(c, w.x0, w.dyb[0], g, R, w, grad + param_offset(0));
