@@ -48,8 +48,10 @@ WORKLOADS = {
     "c3": dict(Ls=[8, 12, 16, 20, 24], ps=[0.045, 0.05, 0.055, 0.06, 0.065], bp=20, sweeps=6,
                mask=0b001001, sched="PFFPFF", shots=20_032, steps=2, warmup=1, L=24, noisy=24),
     # CNN prior vs plain: L = 24 (41,472 qubits), p = q = 0.05, 24 + 1 cycles,
-    # BP 20 + P F F P F F, 10^5 shots (5 steps of 20,032), both decoders on the same shots
-    "c4": dict(L=24, ps=[0.05], noisy=24, bp=20, sweeps=6, mask=0b001001,
+    # P F F P F F, 10^5 shots (5 steps of 20,032), both decoders on the same shots.
+    # Plain p-BP runs its 20 BP iterations; the CNN decoder runs at its
+    # matched-throughput point, 6 iterations with the prior blended at 0.5
+    "c4": dict(L=24, ps=[0.05], noisy=24, bp=20, cnn_bp=6, beta=0.5, sweeps=6, mask=0b001001,
                sched="PFFPFF", shots=20_032, steps=5, warmup=1, decoder="cnn", compare=True),
     # L = 6 (648 qubits), p = q = 0.02, 6 + 1 cycles, flip + p-flip F F P F F,
     # no BP, 10^4 shots
@@ -461,8 +463,9 @@ def main():
     ap.add_argument("--bp-iters", type=int, default=None,
                     help="BP iterations of the main decoder (the comparison keeps the "
                          "workload's)")
-    ap.add_argument("--beta", type=float, default=0.3,
-                    help="CNN prior strength: llr0 = l0 + beta (llr_cnn - l0)")
+    ap.add_argument("--beta", type=float, default=None,
+                    help="CNN prior strength: llr0 = l0 + beta (llr_cnn - l0) "
+                         "(default: the workload's, else 0.3)")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -520,9 +523,19 @@ def main():
     # shots decoded together: the whole step unless a smaller batch is asked for
     batch = min(64 * W, args.batch_shots) if args.batch_shots else 64 * W
 
-    main_cfg = dict(cfg, bp=args.bp_iters) if args.bp_iters else cfg
+    beta = args.beta if args.beta is not None else cfg.get("beta", 0.3)
+
+    def cfg_for(dec, main):
+        """BP iterations of a decoder: the CNN decoder may run fewer than
+        plain p-BP; --bp-iters sets the main decoder's."""
+        bp = cfg.get("cnn_bp", cfg["bp"]) if dec == "cnn" else cfg["bp"]
+        if main and args.bp_iters:
+            bp = args.bp_iters
+        return dict(cfg, bp=bp)
+
+    main_cfg = cfg_for(decoder, True)
     wall, per_class, ler, resid = run_decoder(tc, lat, main_cfg, decoder, steps, warmup, S,
-                                              batch, args.bp_tile, args.beta, args.weights,
+                                              batch, args.bp_tile, beta, args.weights,
                                               "main")
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
@@ -538,9 +551,11 @@ def main():
     comparison = None
     if compare:
         other = "plain" if decoder == "cnn" else "cnn"
-        w2, pc2, ler2, resid2 = run_decoder(tc, lat, cfg, other, steps, warmup, S, batch,
-                                            args.bp_tile, args.beta, args.weights, "compare")
-        comparison = {"decoder": other, "value": qubit_cycles / w2, "unit": "qubit-cycles/s",
+        other_cfg = cfg_for(other, False)
+        w2, pc2, ler2, resid2 = run_decoder(tc, lat, other_cfg, other, steps, warmup, S, batch,
+                                            args.bp_tile, beta, args.weights, "compare")
+        comparison = {"decoder": other, "bp_iters": other_cfg["bp"],
+                      "value": qubit_cycles / w2, "unit": "qubit-cycles/s",
                       "ms_per_step": w2 / steps * 1e3, "ler": ler2,
                       "mean_residual_syndrome": resid2,
                       "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload,
@@ -553,7 +568,7 @@ def main():
         log("[bench] timing the oracle on the host")
         cpu = cpu_baseline(cfg, args.cpu_seconds)
 
-    dec_name = "plain p-BP" if decoder == "plain" else f"CNN prior (beta={args.beta}) + p-BP"
+    dec_name = "plain p-BP" if decoder == "plain" else f"CNN prior (beta={beta}) + p-BP"
     out = {
         "metric": "decoded qubit-cycles/s at fixed logical error rate; CNN-prior vs plain "
                   "BP+p-flip",
