@@ -91,6 +91,7 @@ def log(msg):
 # these are unchanged)
 KERNEL_SOURCES = {
     "bp_iter": ["tc3d_bp.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
+    "bp_iter_prior": ["tc3d_bp.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
     "cnn": ["tc3d_cnn.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
 }
 
@@ -316,8 +317,12 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
                 "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
                 "unit_of_work": "site-shot forward (passes of 5 launches)"}
     per_unit, unit = ALGO_BYTES[dom]
+    # counters are kept per kernel variant: the per-edge-prior BP iteration's
+    # under the name bp_iter_prior
+    key = dom
     if per_edge_prior and dom in ("bp_iter", "bp_first"):
         per_unit += 4.0
+        key = dom + "_prior"
     # a launch covers one batch of shots; with uneven batches (the last one of
     # a step may be smaller) the average launch carries shots / batches
     shots = shots_padded if shots_padded else batch
@@ -325,10 +330,10 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
     units = n * shots / n_batches if unit == "edge-shot" else n * (shots // 64) / n_batches
     algo_bytes = per_unit * units
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
-    ceiling = stored_ceiling(dom, workload)
+    ceiling = stored_ceiling(key, workload)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic(dom, workload), "kernel": dom,
+            "traffic": stored_traffic(key, workload), "kernel": dom,
             "stream_ceiling": ceiling,
             "frac_of_stream_ceiling": round(achieved / ceiling, 4) if ceiling else None,
             "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],

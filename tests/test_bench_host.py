@@ -57,3 +57,27 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "--gpus 1" in r.stderr
+
+
+def test_traffic_is_looked_up_per_kernel_variant(tmp_path, monkeypatch):
+    """The per-edge-prior BP iteration has counters of its own: a plain BP
+    line never reports them, and counters taken on other sources are not
+    reported at all."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    for wl, h in (("cx", _HASHES["bp_iter_prior"]), ("cy", "0123456789abcdef")):
+        (prof / f"bp_iter_prior_{wl}_traffic.txt").write_text(
+            f"hbm_bytes_per_launch: 123.0\nstream_ceiling_GBps: 6000\nsource_sha256: {h}\n")
+    # the sources stay where they are; only the profiles folder moves
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda k="bp_iter": _HASHES[k])
+    pc = _cls(bp_iter={"ms": 20.0, "launches": 10})
+    r = bench.roofline(pc, 3000, 2048, 1000, "cx", shots_padded=2048, per_edge_prior=True)
+    assert r["traffic"] == 123.0 and r["stream_ceiling"] == 6000.0
+    r = bench.roofline(pc, 3000, 2048, 1000, "cx", shots_padded=2048)
+    assert r["traffic"] is None and r["stream_ceiling"] is None
+    r = bench.roofline(pc, 3000, 2048, 1000, "cy", shots_padded=2048, per_edge_prior=True)
+    assert r["traffic"] is None
+
+
+_HASHES = {k: bench.kernel_source_hash(k) for k in bench.KERNEL_SOURCES}
