@@ -858,9 +858,8 @@ int tc3d_stream_copy(void* dst, const void* src, int64_t n_bytes, int32_t nontem
     if (n_bytes == 0) return TC3D_OK;
     if (!dst || !src) return TC3D_EINVAL;
     if (!aligned(dst, 16) || !aligned(src, 16)) return TC3D_EALIGN;
-    const char* s = (const char*)src;
-    const char* d = (const char*)dst;
-    if (s < d + n_bytes && d < s + n_bytes) return TC3D_EINVAL;  // overlap
+    const uintptr_t s = (uintptr_t)src, d = (uintptr_t)dst;
+    if (s < d + (uintptr_t)n_bytes && d < s + (uintptr_t)n_bytes) return TC3D_EINVAL;  // overlap
     const Ctx c{(hipStream_t)stream, nullptr};
     return launch_stream_copy(c, dst, src, n_bytes / 16, nontemporal);
 }

@@ -154,3 +154,18 @@ def test_subset_sweeps_need_even_L_and_a_schedule_slot(lib):
     for lat, cls in ((odd, 0), (even, -1), (even, 12)):
         assert L.tc3d_subset_pflip_sweep(ctypes.byref(lat), ws, ws, 1, 1, 0, 0, 0, cls, ws,
                                          1 << 30, None) == -1
+
+
+def test_stream_copy_rejects_bad_arguments(lib):
+    """Checked on the host before any launch: size a multiple of 16, the
+    store flag 0 or 1, buffers present, 16-byte aligned and disjoint."""
+    cp = lib.tc3d_stream_copy
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21)  # never dereferenced
+    assert cp(b, a, 0, 1, None) == 0                    # nothing to copy
+    assert cp(b, a, 24, 1, None) == -1                  # not a multiple of 16
+    assert cp(b, a, -16, 1, None) == -1
+    assert cp(b, a, 64, 2, None) == -1                  # store flag
+    assert cp(None, a, 64, 1, None) == -1
+    assert cp(ctypes.c_void_p((1 << 21) + 8), a, 64, 1, None) == -2   # misaligned
+    assert cp(ctypes.c_void_p((1 << 20) + 32), a, 64, 0, None) == -1  # overlap
+    assert cp(a, ctypes.c_void_p((1 << 20) + 48), 64, 0, None) == -1  # overlap
