@@ -155,11 +155,13 @@ def fit_threshold(L, p, f, sigma, p_th0=None):
             "dof": int(len(f) - len(popt))}
 
 
-def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500):
+def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec=None):
     """Logical error configurations after 500 cycles of p-BP at L = 14,
-    p = q = 0.0544, next to the paper's counts out of 1000 (Table 2)."""
+    p = q = 0.0544, next to the paper's counts out of 1000 (Table 2).
+    bp_iters and q_dec change the BP the decoder runs (default: 20 iterations,
+    measurement-error rate q_dec = p)."""
     from scipy.stats import chi2_contingency
-    r = memory_run(L, p, cycles, "pbp", shots, seed)
+    r = memory_run(L, p, cycles, "pbp", shots, seed, bp_iters=bp_iters, q_dec=q_dec)
     ours = {format(k & 1, "d") + format((k >> 1) & 1, "d") + format((k >> 2) & 1, "d"):
             int(r["hist"][k]) for k in range(8)}
     keys = list(TABLE2_COUNTS)
@@ -206,6 +208,9 @@ def main():
     t2.add_argument("--seed", type=int, default=1)
     t2.add_argument("--p", type=float, default=0.0544,
                     help="error rate (the paper's point is 5.44%%, just below its threshold)")
+    t2.add_argument("--bp-iters", type=int, default=None)
+    t2.add_argument("--q-dec", type=float, default=None,
+                    help="measurement-error rate BP assumes (default: q = p)")
     th = sub.add_parser("threshold")
     th.add_argument("--decoder", choices=["flip", "bp", "pbp"], default="pbp")
     th.add_argument("--n-a", type=int, default=1)
@@ -228,7 +233,8 @@ def main():
     th.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.cmd == "table2":
-        print(json.dumps(table2(args.shots, args.seed, p=args.p)), flush=True)
+        print(json.dumps(table2(args.shots, args.seed, p=args.p, bp_iters=args.bp_iters,
+                                q_dec=args.q_dec)), flush=True)
         return
     res = threshold(args.decoder, args.L, args.p, args.cycles, args.shots, args.seed, args.n_a,
                     args.lambda_p, args.bp_iters, args.pooled,
