@@ -183,14 +183,14 @@ int launch_input(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev,
 // ------------------------------------------------------------ conv (MFMA)
 enum { EPI_RELU = 0, EPI_LLR = 1, EPI_MASK = 2 };
 
-// Work item of a wavefront: 16 shots (group sg, shots 16 sg .. 16 sg + 15),
-// the pencil (y, z) and the run of NX sites x0 .. x0 + NX - 1 along x
-// (clipped at L). Items are numbered with the x-run fastest, then y, z and
-// the shot group, so that consecutive items share most of their neighbour
-// slabs.
+// Work item of a k_conv wavefront: 16 shots (group sg, shots 16 sg .. 16 sg +
+// 15), the BY pencils y0 .. y0 + BY - 1 at one z and the run of NX sites
+// x0 .. x0 + NX - 1 along x (both clipped at L). Items are numbered with the
+// x-run fastest, then the y-group, z and the shot group, so that consecutive
+// items share most of their neighbour slabs.
 struct ConvItems {
     int L, N, nxr;       // lattice, sites, x-runs per pencil
-    uint32_t n_items;    // n_sg L^2 nxr, for shot groups sg0 .. sg0 + n_sg - 1
+    uint32_t n_items;    // n_sg L ceil(L / BY) nxr, for shot groups sg0 .. sg0 + n_sg - 1
     uint32_t sg0;
 };
 
@@ -373,8 +373,9 @@ __global__ __launch_bounds__(kConvBlock) void k_conv(
 // and feeds the output planes below, at and above it. Their accumulators
 // stay in registers as a ring of three: after input plane z the output
 // plane z - 1 has all 27 taps and is written. That is (NX + 2)(BY + 2)
-// (zs + 2) / (NX BY zs) slab loads per output site, 5 for 2 x 2 x 8, against
-// 12 when every output plane loads its three input planes itself.
+// (zs + 2) / (NX BY zs) slab loads per output site, 7 for 2 x 1 sites and 12
+// planes, against 12 when every output plane loads its three input planes
+// itself (k_conv with 2 x 2 sites).
 constexpr int kConvZWaves = 8;
 constexpr int kConvZBlock = 64 * kConvZWaves;
 
@@ -844,7 +845,10 @@ int launch_conv(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     return after_launch(c);
 }
 
-// Shape of the z-marching forward convolutions (x-sites x y-pencils).
+// Shape of the z-marching forward convolutions (x-sites x y-pencils), chosen
+// by timing: the ring of three output planes must leave 4 wavefronts per SIMD,
+// which 2 x 1 sites of 32 channels do (111 registers) and 2 x 2 do not; the
+// 32 -> 3 layer holds a third of the accumulators and affords 2 x 2.
 template <int EPI>
 struct ConvZShape {
     static constexpr int NX = 2;
