@@ -97,6 +97,37 @@ def test_forward_parity(L, S):
     assert np.linalg.norm(z_from_llr(llr, L, full) - z_o0) / np.linalg.norm(z_o0) < 1e-2
 
 
+@pytest.mark.parametrize("L,S", [(7, 1024), (5, 1536)])
+def test_forward_parity_multi_plane_segments(L, S):
+    """Enough shots that the z-marching layers walk segments of several planes
+    with a short last one (on MI355X: 4 + 3 planes at L = 7, 3 + 2 at L = 5
+    for the 32 -> 32 layers; 2 + 2 + 2 + 1 and 2 + 2 + 1 for 32 -> 3), so the
+    ring of accumulators carries partial sums across planes. Sampled shots
+    against the oracle, at the bars of test_forward_parity."""
+    import torch
+    announce(f"cnn forward multi-plane L={L} S={S}")
+    o = Oracle(L)
+    lat = tc.make_lattice(L)
+    W = inputs.n_words(S)
+    full = 64 * W
+    syn = inputs.random_bits(40 + L, full, o.n_faces, 0.3)
+    prev = inputs.random_bits(50 + L, full, o.n_faces, 0.2)
+    p32 = random_params(60 + L)
+    _, packed = packed_of(p32)
+    llr = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
+    ws = tc.alloc_workspace(tc.cnn_workspace_bytes(lat, S))
+    tc.cnn_forward(lat, dev_plane_of_bits(syn), dev_plane_of_bits(prev), S, packed, llr, ws)
+    sync()
+    z_g = z_from_llr(llr, L, full)
+    idx = np.array([0, 15, 16, 333, S // 2 + 7, S - 1])
+    z_o = o.cnn_forward(o.cnn_input(syn[idx], prev[idx]), oracle_params(p32))
+    err = np.abs(z_g[idx] - z_o)
+    rel = np.linalg.norm(err) / np.linalg.norm(z_o)
+    announce(f"  relative L2 error {rel:.2e}, max abs {err.max():.3e}")
+    assert rel < 1e-2
+    assert err.max() < 0.05 * np.abs(z_o).max()
+
+
 @pytest.mark.parametrize("L,S", [(3, 64), (4, 128), (5, 64)])
 def test_gradient_parity(L, S):
     import torch
