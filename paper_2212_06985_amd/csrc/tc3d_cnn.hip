@@ -584,133 +584,320 @@ __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ llr,
 
 // -------------------------------------------------- weight gradient
 // dW[d][ci][co] = sum_g x[g + off(d)][ci] dy[g][co]; db[co] = sum_g dy[g][co].
-// A workgroup walks chunks of 256 rows; for each chunk it stages dy^T and,
-// per offset, x^T of the neighbour rows in LDS, then MFMA tiles (ci x co of
-// 16 x 16) accumulate over the chunk's rows. Work items (tile, offset) are
-// dealt round-robin to the 4 wavefronts. Partials per workgroup are written
-// to part[block][27][CI][CO] and part_b[block][CO] and summed in a fixed
-// order by k_reduce.
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ x,
-                                               const bf16* __restrict__ dy, int L, int N,
-                                               uint32_t R, uint32_t n_chunks,
-                                               float* __restrict__ part,
-                                               float* __restrict__ part_b) {
-    constexpr int CIP = CIN < 16 ? 16 : CIN;   // padded M
-    constexpr int COP = COUT < 16 ? 16 : 32;   // padded N
-    constexpr int DYC = COUT <= 8 ? 8 : 32;    // stored channels of dy rows
-    constexpr int MT = CIP / 16, NT = COP / 16, TILES = MT * NT;
-    constexpr int ITEMS = 27 * TILES;
-    constexpr int PER_WAVE = (ITEMS + 3) / 4;
-    constexpr int STR = 256 + 8;  // LDS row stride (bf16), padded
-    __shared__ __attribute__((aligned(16))) bf16 dyT[COP][STR];
-    __shared__ __attribute__((aligned(16))) bf16 xT[CIP][STR];
-    __shared__ float bred[256][COP > 16 ? 32 : 16];
+// The contraction runs over rows, i.e. over the 64 shots of each site-word,
+// so both MFMA operands need 8 consecutive shots of one channel per lane,
+// while activations are stored channel-contiguous for the forward pass.
+// k_rows_to_shots makes a shot-contiguous copy of x and of dy first
+// ([(w N + v) C + c][64 shots]); k_wgradT then reads every fragment with one
+// 16-byte load.
+
+// One 256-thread workgroup per 256 / (8 C) site-words, staged through LDS.
+template <int C>
+__global__ __launch_bounds__(256) void k_rows_to_shots(const bf16* __restrict__ in,
+                                                       bf16* __restrict__ out, int64_t n_sw) {
+    constexpr int TPS = 8 * C;      // threads per site-word: 16 bytes each way
+    constexpr int SPB = 256 / TPS;  // site-words per workgroup
+    constexpr int STR = C + 2;      // LDS row stride (bf16)
+    __shared__ bf16 t[SPB][64][STR];
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int r16 = lane & 15, q = lane >> 4;
-    const int LL = L * L;
-    f32x4 acc[PER_WAVE];
+    const int s = tid / TPS, r = tid % TPS;
+    const int64_t sw = (int64_t)blockIdx.x * SPB + s;
+    if (sw < n_sw) {
+        // row r / (C / 8) of the site-word, channels 8 (r % (C / 8)) .. + 7
+        const int row = r / (C / 8), c8 = 8 * (r % (C / 8));
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(in + (sw * 64 + row) * C + c8);
 #pragma unroll
-    for (int j = 0; j < PER_WAVE; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum[COP];
-#pragma unroll
-    for (int c = 0; c < COP; ++c) bsum[c] = 0.f;
-    // zero the padding rows of the transposed tiles once
-    for (int c = CIN; c < CIP; ++c) xT[c][tid] = (bf16)0.f;
-    for (int c = COUT; c < COP; ++c) dyT[c][tid] = (bf16)0.f;
-    for (uint32_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
-        const uint32_t g = chunk * 256 + tid;
-        const bool ok = g < R;
-        uint32_t w = 0;
-        int vx = 0, vy = 0, vz = 0;
-        if (ok) {
-            const uint32_t wv = g >> 6;
-            w = wv / (uint32_t)N;
-            const int v = (int)(wv - w * (uint32_t)N);
-            vx = v % L;
-            vy = (v / L) % L;
-            vz = v / LL;
-        }
-        __syncthreads();
-        // dy^T
-#pragma unroll
-        for (int c = 0; c < COUT; ++c) {
-            const float val = ok ? (float)dy[(int64_t)g * DYC + c] : 0.f;
-            dyT[c][tid] = (bf16)val;
-            bsum[c] += val;
-        }
-        for (int d = 0; d < 27; ++d) {
-            // x^T of the neighbour rows at offset d
-            if (ok) {
-                const int ux = wrap(vx + off_x(d), L), uy = wrap(vy + off_y(d), L),
-                          uz = wrap(vz + off_z(d), L);
-                const int64_t row =
-                    ((int64_t)w * N + ux + L * (uy + L * uz)) * 64 + (g & 63);
-#pragma unroll
-                for (int c8 = 0; c8 < CIN; c8 += 8) {
-                    const bf16x8 v8 = *reinterpret_cast<const bf16x8*>(x + row * CIN + c8);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) xT[c8 + j][tid] = v8[j];
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < CIN; ++c) xT[c][tid] = (bf16)0.f;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < PER_WAVE; ++j) {
-                const int item = wave + 4 * j;
-                if (item >= ITEMS || item / TILES != d) continue;
-                const int tile = item % TILES;
-                const int mt = tile / NT, nt = tile % NT;
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const bf16x8 a =
-                        *reinterpret_cast<const bf16x8*>(&xT[16 * mt + r16][32 * ks + 8 * q]);
-                    const bf16x8 b =
-                        *reinterpret_cast<const bf16x8*>(&dyT[16 * nt + r16][32 * ks + 8 * q]);
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-                }
-            }
-            __syncthreads();
-        }
+        for (int e = 0; e < 8; ++e) t[s][row][c8 + e] = v[e];
     }
-    // partial weight gradient of this workgroup: lane holds D[ci 4q+i][co r16]
-    float* pb = part + (int64_t)blockIdx.x * 27 * CIN * COUT;
-#pragma unroll
-    for (int j = 0; j < PER_WAVE; ++j) {
-        const int item = wave + 4 * j;
-        if (item >= ITEMS) continue;
-        const int d = item / TILES, tile = item % TILES;
-        const int mt = tile / NT, nt = tile % NT;
-        const int co = 16 * nt + r16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ci = 16 * mt + 4 * q + i;
-            if (ci < CIN && co < COUT) pb[((int64_t)d * CIN + ci) * COUT + co] = acc[j][i];
-        }
-    }
-    // bias partial: sum of the per-thread sums in a fixed order
-#pragma unroll
-    for (int c = 0; c < COP; ++c) bred[tid][c] = bsum[c];
     __syncthreads();
-    if (tid < COUT) {
-        float sum = 0.f;
-        for (int t = 0; t < 256; ++t) sum += bred[t][tid];
-        part_b[(int64_t)blockIdx.x * COUT + tid] = sum;
+    if (sw < n_sw) {
+        // channel r / 8, shots 8 (r % 8) .. + 7
+        const int ch = r / 8, l8 = 8 * (r % 8);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = t[s][l8 + e][ch];
+        *reinterpret_cast<bf16x8*>(out + (sw * C + ch) * 64 + l8) = o;
     }
 }
 
-// out[i] = sum over blocks b of part[b][i], in block order.
-__global__ void k_reduce(const float* __restrict__ part, int64_t n, int nblocks,
-                         float* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * n + i];
-    out[i] = s;
+// MFMA 16x16x32 with M = ci, N = co and K = 32 shots of one site: A lane
+// (ci = 16 mt + lane % 16, shots 8 (lane / 16) ..) is a 16-byte load of the
+// neighbour site's x copy, B likewise of this site's dy copy. Wavefront k of
+// the 4 in a workgroup owns the offsets d = k, k + 4, ... for every channel
+// tile (at most 7 x 2 x 2 accumulator tiles); wavefront 0 also owns the bias
+// gradient, as the product of an all-ones A with dy. A workgroup walks a
+// contiguous range of site-words (x fastest, so neighbour copies stay in
+// cache) and writes its partial sums to part[block][27][CIN][COUT] and
+// part_b[block][COUT]; k_reduce8 adds the partials in a fixed order.
+template <int CIN, int COUT, int CXS, int CYS>
+// (At least two wavefronts per SIMD: left alone, the compiler hoists the loads
+// of all seven offsets and takes 270 registers.)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_wgradT(
+    const bf16* __restrict__ xT, const bf16* __restrict__ dyT, int L, int N, int64_t n_sw,
+    int64_t per_block, float* __restrict__ part, float* __restrict__ part_b) {
+    constexpr int MT = CIN > 16 ? 2 : 1, NT = COUT > 16 ? 2 : 1;
+    constexpr int ND = 7;  // offsets per wavefront: 27 = 7 + 7 + 7 + 6
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int r16 = lane & 15, q = lane >> 4;
+    f32x4 acc[ND][MT][NT];
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[j][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 accb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) accb[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones, zero;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        ones[e] = (bf16)1.f;
+        zero[e] = (bf16)0.f;
+    }
+    const int64_t sw0 = (int64_t)blockIdx.x * per_block;
+    const int64_t sw1 = sw0 + per_block < n_sw ? sw0 + per_block : n_sw;
+    for (int64_t sw = sw0; sw < sw1; ++sw) {
+        const int64_t w = sw / N;
+        const int v = (int)(sw - w * N);
+        const int vx = v % L, vy = (v / L) % L, vz = v / (L * L);
+        bf16x8 b[NT][2];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = 16 * nt + r16;
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                b[nt][kb] = co < CYS ? *reinterpret_cast<const bf16x8*>(
+                                           dyT + (sw * CYS + co) * 64 + 32 * kb + 8 * q)
+                                     : zero;
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+                    accb[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, b[nt][kb], accb[nt],
+                                                                       0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            const int d = wave + 4 * j;
+            if (d >= 27) break;
+            const int u = wrap(vx + off_x(d), L) + L * (wrap(vy + off_y(d), L) +
+                                                        L * wrap(vz + off_z(d), L));
+            const int64_t urow = (w * N + u) * CXS;
+            bf16x8 a[MT][2];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int ci = 16 * mt + r16;
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+                    a[mt][kb] = ci < CXS ? *reinterpret_cast<const bf16x8*>(
+                                               xT + (urow + ci) * 64 + 32 * kb + 8 * q)
+                                         : zero;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb)
+                        acc[j][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[mt][kb], b[nt][kb], acc[j][mt][nt], 0, 0, 0);
+        }
+    }
+    // lane holds D[ci = 16 mt + 4 q + i][co = 16 nt + r16]
+    float* pb = part + (int64_t)blockIdx.x * 27 * CIN * COUT;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        const int d = wave + 4 * j;
+        if (d >= 27) break;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + r16;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int ci = 16 * mt + 4 * q + i;
+                    if (ci < CIN && co < COUT)
+                        pb[((int64_t)d * CIN + ci) * COUT + co] = acc[j][mt][nt][i];
+                }
+            }
+    }
+    // every row of the all-ones product holds the bias sum; row 0 is lane q = 0
+    if (wave == 0 && q == 0) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = 16 * nt + r16;
+            if (co < COUT) part_b[(int64_t)blockIdx.x * COUT + co] = accb[nt][0];
+        }
+    }
+}
+
+// The same contraction walking x-pencils: wavefront c of 9 owns the (dy, dz)
+// column c (dy = c % 3 - 1, dz = c / 3 - 1) and its three offsets d = 3 c + dx.
+// Along the pencil it keeps the x copies of sites x - 1, x, x + 1 of the
+// neighbour pencil in registers and loads one new site per step, so a site's
+// x fragments feed three offsets and its dy fragments are read once per
+// wavefront: 8 loads per 24 MFMAs instead of 32 per 56. Wavefront 0 also owns
+// the bias gradient.
+template <int CIN, int COUT, int CXS, int CYS>
+__global__ __launch_bounds__(576) void k_wgradP(const bf16* __restrict__ xT,
+                                                const bf16* __restrict__ dyT, int L, int N,
+                                                int64_t n_pencils, int64_t per_block,
+                                                float* __restrict__ part,
+                                                float* __restrict__ part_b) {
+    constexpr int MT = CIN > 16 ? 2 : 1, NT = COUT > 16 ? 2 : 1;
+    const int lane = threadIdx.x & 63;
+    const int col = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int r16 = lane & 15, q = lane >> 4;
+    const int dy = col % 3 - 1, dz = col / 3 - 1;
+    f32x4 acc[3][MT][NT];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[k][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 accb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) accb[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones, zero;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        ones[e] = (bf16)1.f;
+        zero[e] = (bf16)0.f;
+    }
+    const int64_t LL = (int64_t)L * L;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = p0 + per_block < n_pencils ? p0 + per_block : n_pencils;
+    for (int64_t pn = p0; pn < p1; ++pn) {
+        const int64_t w = pn / LL;
+        const int r = (int)(pn - w * LL);
+        const int y = r % L, z = r / L;
+        const int uy = wrap(y + dy, L), uz = wrap(z + dz, L);
+        // site x = 0 of the neighbour pencil and of this pencil
+        const bf16* xs = xT + (w * N + (int64_t)L * (uy + (int64_t)L * uz)) * CXS * 64;
+        const bf16* ds = dyT + (w * N + (int64_t)L * (y + (int64_t)L * z)) * CYS * 64;
+        auto load_x = [&](int x, bf16x8 (&a)[MT][2]) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int ci = 16 * mt + r16;
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+                    a[mt][kb] = ci < CXS ? *reinterpret_cast<const bf16x8*>(
+                                               xs + ((int64_t)x * CXS + ci) * 64 + 32 * kb + 8 * q)
+                                         : zero;
+            }
+        };
+        bf16x8 am[MT][2], a0[MT][2], ap[MT][2], b[NT][2];
+        load_x(L - 1, am);
+        load_x(0, a0);
+        for (int x = 0; x < L; ++x) {
+            load_x(x + 1 < L ? x + 1 : 0, ap);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + r16;
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+                    b[nt][kb] = co < CYS ? *reinterpret_cast<const bf16x8*>(
+                                               ds + ((int64_t)x * CYS + co) * 64 + 32 * kb + 8 * q)
+                                         : zero;
+            }
+            if (col == 0) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb)
+                        accb[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, b[nt][kb],
+                                                                           accb[nt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb) {
+                        acc[0][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            am[mt][kb], b[nt][kb], acc[0][mt][nt], 0, 0, 0);
+                        acc[1][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a0[mt][kb], b[nt][kb], acc[1][mt][nt], 0, 0, 0);
+                        acc[2][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            ap[mt][kb], b[nt][kb], acc[2][mt][nt], 0, 0, 0);
+                    }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    am[mt][kb] = a0[mt][kb];
+                    a0[mt][kb] = ap[mt][kb];
+                }
+        }
+    }
+    // lane holds D[ci = 16 mt + 4 q + i][co = 16 nt + r16] of offset 3 col + dx
+    float* pb = part + (int64_t)blockIdx.x * 27 * CIN * COUT;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        const int d = 3 * col + dx;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + r16;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int ci = 16 * mt + 4 * q + i;
+                    if (ci < CIN && co < COUT)
+                        pb[((int64_t)d * CIN + ci) * COUT + co] = acc[dx][mt][nt][i];
+                }
+            }
+    }
+    if (col == 0 && q == 0) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = 16 * nt + r16;
+            if (co < COUT) part_b[(int64_t)blockIdx.x * COUT + co] = accb[nt][0];
+        }
+    }
+}
+
+// out[i] = sum_b part[b][i] in a fixed order: 8 threads per output each add
+// every 8th partial (consecutive outputs across lanes, so loads coalesce),
+// then the 8 sums are added in order.
+__global__ __launch_bounds__(256) void k_reduce8(const float* __restrict__ part, int64_t n,
+                                                 int nblocks, float* __restrict__ out) {
+    __shared__ float s[8][32];
+    const int ii = threadIdx.x % 32, k = threadIdx.x / 32;
+    const int64_t i = (int64_t)blockIdx.x * 32 + ii;
+    float acc = 0.f;
+    if (i < n)
+        for (int b = k; b < nblocks; b += 8) acc += part[(int64_t)b * n + i];
+    s[k][ii] = acc;
+    __syncthreads();
+    if (k == 0 && i < n) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t += s[j][ii];
+        out[i] = t;
+    }
+}
+
+// *out = sum of part[0 .. n - 1] in a fixed order: thread t adds every 256th
+// value from t on, then a tree over the 256 sums.
+__global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int64_t n,
+                                             float* __restrict__ out) {
+    __shared__ float s[256];
+    float acc = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
 }
 
 // Adam on the FP32 parameters (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t).
@@ -744,19 +931,22 @@ struct CnnWs {
     bf16* a[3];  // post-ReLU activations of layers 1-3, [R][32] each
     bf16* dy8;   // [R][8]: d loss / d logits (training)
     bf16* dyb[2];  // [R][32] ping-pong gradients (training)
+    bf16* xT;      // shot-contiguous copies for the weight gradient, [R / 64][32][64]
+    bf16* dyT;
     float* part;   // weight-gradient partials (training)
     float* part_b;
     float* loss_part;
 };
 
 constexpr int kWgradBlocks = 512;
+constexpr bool kWgradPencils = true;
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 size_t cnn_ws_bytes(int64_t R, int training) {
     size_t b = align_up((size_t)R * 8 * 2) + 3 * align_up((size_t)R * 32 * 2);
     if (training) {
-        b += align_up((size_t)R * 8 * 2) + 2 * align_up((size_t)R * 32 * 2);
+        b += align_up((size_t)R * 8 * 2) + 4 * align_up((size_t)R * 32 * 2);
         b += align_up((size_t)kWgradBlocks * 27 * 32 * 32 * 4);
         b += align_up((size_t)kWgradBlocks * 32 * 4);
         b += align_up((size_t)cdiv(R, 256) * 4);
@@ -780,6 +970,10 @@ CnnWs carve(void* ws, int64_t R, int training) {
             w.dyb[i] = (bf16*)p;
             p += align_up((size_t)R * 32 * 2);
         }
+        w.xT = (bf16*)p;
+        p += align_up((size_t)R * 32 * 2);
+        w.dyT = (bf16*)p;
+        p += align_up((size_t)R * 32 * 2);
         w.part = (float*)p;
         p += align_up((size_t)kWgradBlocks * 27 * 32 * 32 * 4);
         w.part_b = (float*)p;
@@ -944,23 +1138,51 @@ int cnn_forward_impl(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* p
     return TC3D_OK;
 }
 
+template <int C>
+int launch_rows_to_shots(const Ctx& c, const bf16* in, bf16* out, int64_t n_sw) {
+    constexpr int SPB = 256 / (8 * C);
+    int rc = before_launch(c, TC3D_K_CNN);
+    if (rc) return rc;
+    k_rows_to_shots<C><<<dim3((unsigned)cdiv(n_sw, SPB)), dim3(256), 0, c.stream>>>(in, out,
+                                                                                   n_sw);
+    return after_launch(c);
+}
+
+// Weight and bias gradient of one layer from its input rows x ([R][CIN]) and
+// output gradient rows dy ([R][8] for the 3-channel layer, else [R][32]).
 template <int CIN, int COUT>
 int launch_wgrad(const Ctx& c, const bf16* x, const bf16* dy, Geo g, int64_t R, const CnnWs& w,
                  float* grad_layer) {
-    const int64_t chunks = cdiv(R, 256);
-    const int nb = (int)(chunks < kWgradBlocks ? chunks : kWgradBlocks);
-    int rc = before_launch(c, TC3D_K_CNN);
-    if (rc) return rc;
-    k_wgrad<CIN, COUT><<<dim3(nb), dim3(256), 0, c.stream>>>(x, dy, g.L, g.N, (uint32_t)R,
-                                                            (uint32_t)chunks, w.part, w.part_b);
+    constexpr int CXS = CIN, CYS = COUT == 3 ? 8 : 32;  // stored channels of the rows
+    const int64_t n_sw = R / 64;
+    if (n_sw == 0) return TC3D_OK;
+    int rc;
+    if ((rc = launch_rows_to_shots<CXS>(c, x, w.xT, n_sw))) return rc;
+    if ((rc = launch_rows_to_shots<CYS>(c, dy, w.dyT, n_sw))) return rc;
+    int nb;
+    if (kWgradPencils) {
+        const int64_t n_pencils = n_sw / g.L;  // W L^2 x-pencils
+        const int64_t per = cdiv(n_pencils, kWgradBlocks);
+        nb = (int)cdiv(n_pencils, per);
+        if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
+        k_wgradP<CIN, COUT, CXS, CYS><<<dim3(nb), dim3(576), 0, c.stream>>>(
+            w.xT, w.dyT, g.L, g.N, n_pencils, per, w.part, w.part_b);
+    } else {
+        const int64_t per = cdiv(n_sw, kWgradBlocks);
+        nb = (int)cdiv(n_sw, per);
+        if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
+        k_wgradT<CIN, COUT, CXS, CYS><<<dim3(nb), dim3(256), 0, c.stream>>>(
+            w.xT, w.dyT, g.L, g.N, n_sw, per, w.part, w.part_b);
+    }
     if ((rc = after_launch(c))) return rc;
     const int64_t nw = 27 * CIN * COUT;
     if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
-    k_reduce<<<dim3((unsigned)cdiv(nw, 256)), dim3(256), 0, c.stream>>>(w.part, nw, nb,
-                                                                         grad_layer);
+    k_reduce8<<<dim3((unsigned)cdiv(nw, 32)), dim3(256), 0, c.stream>>>(w.part, nw, nb,
+                                                                        grad_layer);
     if ((rc = after_launch(c))) return rc;
     if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
-    k_reduce<<<dim3(1), dim3(64), 0, c.stream>>>(w.part_b, COUT, nb, grad_layer + nw);
+    k_reduce8<<<dim3((unsigned)cdiv(COUT, 32)), dim3(256), 0, c.stream>>>(w.part_b, COUT, nb,
+                                                                          grad_layer + nw);
     return after_launch(c);
 }
 
@@ -998,7 +1220,7 @@ int cnn_loss_grad(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev
                                                           inv_count, w.dy8, w.loss_part);
     if ((rc = after_launch(c))) return rc;
     if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
-    k_reduce<<<dim3(1), dim3(64), 0, c.stream>>>(w.loss_part, 1, (int)lb, loss);
+    k_sum<<<dim3(1), dim3(256), 0, c.stream>>>(w.loss_part, lb, loss);
     if ((rc = after_launch(c))) return rc;
     // layer 4 (32 -> 3): weight gradient, then dy of layer 3 through its ReLU
     if ((rc = launch_wgrad<32, 3>(c, w.a[2], w.dy8, g, R, w, grad + param_offset(3)))) return rc;
