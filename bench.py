@@ -80,7 +80,7 @@ ALGO_BYTES = {
 # divided by its launches.
 CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
-DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_mixed.npy")
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_long.npy")
 
 
 def log(msg):
