@@ -257,8 +257,10 @@ typedef struct {
     double total_ms;                /* first to last event of the call      */
 } tc3d_timing;
 
-/* tc3d_run_cycles with a HIP event recorded on `stream` before and after
- * every kernel launch; blocks until the work is done and fills *timing. */
+/* tc3d_run_cycles with HIP events recorded on `stream` around every run of
+ * consecutive launches of one kernel class (ms[k] then includes the short
+ * gaps between the launches of a run; launches[k] counts every launch);
+ * blocks until the work is done and fills *timing. */
 int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
                           uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
                           size_t ws_bytes, void* stream, tc3d_timing* timing);

@@ -27,8 +27,16 @@ int Timer::drain(Slot& s) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s.start, s.stop) != hipSuccess) return TC3D_EHIP;
     ms_[s.kclass] += ms;
-    launches_[s.kclass] += 1;
     s.pending = false;
+    return TC3D_OK;
+}
+
+int Timer::close() {
+    if (!open_) return TC3D_OK;
+    Slot& s = slots_[cur_];
+    if (hipEventRecord(s.stop, stream_) != hipSuccess) return TC3D_EHIP;
+    s.pending = true;
+    open_ = false;
     return TC3D_OK;
 }
 
@@ -39,6 +47,10 @@ int Timer::begin(int kclass) {
             return TC3D_EHIP;
         if (hipEventRecord(first_, stream_) != hipSuccess) return TC3D_EHIP;
     }
+    launches_[kclass] += 1;
+    if (open_ && slots_[cur_].kclass == kclass) return TC3D_OK;  // the run continues
+    int rc = close();
+    if (rc) return rc;
     if (slots_.size() < kSlots) {
         Slot s;
         if (hipEventCreate(&s.start) != hipSuccess || hipEventCreate(&s.stop) != hipSuccess)
@@ -48,24 +60,22 @@ int Timer::begin(int kclass) {
     cur_ = (int)(next_ % slots_.size());
     next_++;
     Slot& s = slots_[cur_];
-    int rc = drain(s);  // reuse: wait for the launch recorded kSlots launches ago
+    rc = drain(s);  // reuse: wait for the interval recorded kSlots intervals ago
     if (rc) return rc;
     s.kclass = kclass;
     if (hipEventRecord(s.start, stream_) != hipSuccess) return TC3D_EHIP;
+    open_ = true;
     return TC3D_OK;
 }
 
-int Timer::end() {
-    Slot& s = slots_[cur_];
-    if (hipEventRecord(s.stop, stream_) != hipSuccess) return TC3D_EHIP;
-    s.pending = true;
-    return TC3D_OK;
-}
+int Timer::end() { return TC3D_OK; }
 
 int Timer::finish(tc3d_timing* out) {
+    int rc = close();
+    if (rc) return rc;
     if (first_ && hipEventRecord(last_, stream_) != hipSuccess) return TC3D_EHIP;
     for (auto& s : slots_) {
-        int rc = drain(s);
+        rc = drain(s);
         if (rc) return rc;
     }
     memset(out, 0, sizeof(*out));

@@ -10,14 +10,17 @@
 
 namespace tc3d {
 
-// Optional per-launch HIP-event timing (used by tc3d_run_cycles_timed).
+// Optional HIP-event timing (used by tc3d_run_cycles_timed). Consecutive
+// launches of one kernel class share one pair of events: an event pair per
+// launch costs a few microseconds of GPU time each, which the CNN path, with
+// hundreds of short launches per cycle, would feel (about 9%).
 class Timer {
   public:
     explicit Timer(hipStream_t s) : stream_(s) {}
     ~Timer();
-    int begin(int kclass);  // records the start event of the next launch
-    int end();              // records its stop event
-    int finish(tc3d_timing* out);  // waits for all events and sums them
+    int begin(int kclass);  // before a launch: opens an interval unless one of this class is open
+    int end();              // after a launch (the interval stays open)
+    int finish(tc3d_timing* out);  // closes the last interval, waits for all events, sums them
 
   private:
     struct Slot {
@@ -26,10 +29,12 @@ class Timer {
         bool pending = false;
     };
     int drain(Slot& s);
+    int close();  // records the stop event of the open interval
     hipStream_t stream_;
     std::vector<Slot> slots_;
     size_t next_ = 0;
     int cur_ = -1;
+    bool open_ = false;  // slot cur_ has its start event and awaits its stop
     hipEvent_t first_ = nullptr, last_ = nullptr;
     double ms_[TC3D_K_COUNT] = {};
     int64_t launches_[TC3D_K_COUNT] = {};

@@ -143,6 +143,8 @@ def test_timed_run_counts_launches():
     assert d["bp_post"]["launches"] == cycles
     assert d["sweep"]["launches"] == cycles * 6
     assert d["readout"]["launches"] == 1
+    # class intervals are disjoint runs of launches inside the call's span
+    assert sum(v["ms"] for v in d.values()) <= t.total_ms * 1.001 + 1e-3
     assert t.total_ms >= sum(v["ms"] for v in d.values()) * 0.5
 
 
