@@ -1095,15 +1095,40 @@ int launch_convz(const Ctx& c, const bf16* x, const bf16* wp, const float* bias,
     return after_launch(c);
 }
 
-// Shot groups per pass of the forward network: one pass keeps its input and
+// Shot groups per pass of the forward network. A pass keeps its input and
 // output activations (2 x 16 x N x 64 bytes per group) within the 256 MB
 // Infinity Cache, so the neighbour re-reads of the convolutions are served
-// from it rather than from HBM.
-constexpr int64_t kPassBytes = 96ll << 20;
-int64_t groups_per_pass(Geo g) {
+// from it rather than from HBM: 64 to 128 MB of input per pass (96 MB timed
+// best where the count below does not decide). Within that range take the
+// count whose z-marching 32 -> 32 launches fill the resident wavefronts best:
+// time per group ~ rounds x (zs + 2) / groups.
+constexpr int64_t kPassBytesLo = 64ll << 20, kPassBytesHi = 128ll << 20;
+int64_t groups_per_pass(Geo g, int64_t n_sg) {
     const int64_t per = (int64_t)g.N * 16 * 64;
-    const int64_t c = kPassBytes / per;
-    return c < 1 ? 1 : c;
+    int64_t hi = kPassBytesHi / per < 1 ? 1 : kPassBytesHi / per;
+    if (hi > n_sg) hi = n_sg < 1 ? 1 : n_sg;
+    int64_t lo = kPassBytesLo / per < 1 ? 1 : kPassBytesLo / per;
+    if (lo > hi) lo = hi;
+    constexpr int NX = ConvZShape<EPI_RELU>::NX, BY = ConvZShape<EPI_RELU>::BY;
+    static std::atomic<int> resident[64];
+    const int64_t slots =
+        (int64_t)resident_blocks(k_convz<EPI_RELU, NX, BY>, kConvZBlock, resident, 64) *
+        kConvZWaves;
+    const int64_t cols = cdiv(g.L, BY) * cdiv(g.L, NX);  // z-columns per shot group
+    int64_t best = (96ll << 20) / per;
+    if (best < lo) best = lo;
+    if (best > hi) best = hi;
+    int64_t best_cost = -1;  // rounds x (zs + 2) of the best count
+    for (int64_t gp = lo; gp <= hi; ++gp) {
+        const int zs = choose_zs(g.L, gp * cols, slots);
+        const int64_t cost = cdiv(gp * cols * cdiv(g.L, zs), slots) * (zs + 2);
+        // cost / gp < best_cost / best, in integers
+        if (best_cost < 0 || cost * best < best_cost * gp) {
+            best = gp;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 const bf16* blk(const void* packed, int i) { return (const bf16*)packed + block_offset(i); }
@@ -1118,7 +1143,7 @@ int cnn_forward_impl(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* p
                      int64_t R, const void* packed, float* llr, const CnnWs& w) {
     int rc;
     const int64_t n_sg = R / (16 * (int64_t)g.N);
-    const int64_t per = groups_per_pass(g);
+    const int64_t per = groups_per_pass(g, n_sg);
     for (int64_t sg0 = 0; sg0 < n_sg; sg0 += per) {
         const int64_t k = n_sg - sg0 < per ? n_sg - sg0 : per;
         if ((rc = launch_input(c, g, syn, prev, ld, sg0, k, w.x0))) return rc;
