@@ -101,9 +101,6 @@ constexpr int64_t kPackedElems = block_offset(kBlocks);
 constexpr int64_t kBiasOffsetBytes = ((kPackedElems * 2 + 255) / 256) * 256;
 constexpr int64_t kPackedBytes = kBiasOffsetBytes + 4 * 32 * 4;
 
-__device__ __forceinline__ int off_x(int d) { return d % 3 - 1; }
-__device__ __forceinline__ int off_y(int d) { return (d / 3) % 3 - 1; }
-__device__ __forceinline__ int off_z(int d) { return d / 9 - 1; }
 
 __device__ __forceinline__ int wrap(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
@@ -588,7 +585,7 @@ __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ llr,
 // so both MFMA operands need 8 consecutive shots of one channel per lane,
 // while activations are stored channel-contiguous for the forward pass.
 // k_rows_to_shots makes a shot-contiguous copy of x and of dy first
-// ([(w N + v) C + c][64 shots]); k_wgradT then reads every fragment with one
+// ([(w N + v) C + c][64 shots]); k_wgradP then reads every fragment with one
 // 16-byte load.
 
 // One 256-thread workgroup per 256 / (8 C) site-words, staged through LDS.
@@ -620,129 +617,18 @@ __global__ __launch_bounds__(256) void k_rows_to_shots(const bf16* __restrict__ 
     }
 }
 
-// MFMA 16x16x32 with M = ci, N = co and K = 32 shots of one site: A lane
-// (ci = 16 mt + lane % 16, shots 8 (lane / 16) ..) is a 16-byte load of the
-// neighbour site's x copy, B likewise of this site's dy copy. Wavefront k of
-// the 4 in a workgroup owns the offsets d = k, k + 4, ... for every channel
-// tile (at most 7 x 2 x 2 accumulator tiles); wavefront 0 also owns the bias
-// gradient, as the product of an all-ones A with dy. A workgroup walks a
-// contiguous range of site-words (x fastest, so neighbour copies stay in
-// cache) and writes its partial sums to part[block][27][CIN][COUT] and
-// part_b[block][COUT]; k_reduce8 adds the partials in a fixed order.
-template <int CIN, int COUT, int CXS, int CYS>
-// (At least two wavefronts per SIMD: left alone, the compiler hoists the loads
-// of all seven offsets and takes 270 registers.)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_wgradT(
-    const bf16* __restrict__ xT, const bf16* __restrict__ dyT, int L, int N, int64_t n_sw,
-    int64_t per_block, float* __restrict__ part, float* __restrict__ part_b) {
-    constexpr int MT = CIN > 16 ? 2 : 1, NT = COUT > 16 ? 2 : 1;
-    constexpr int ND = 7;  // offsets per wavefront: 27 = 7 + 7 + 7 + 6
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int r16 = lane & 15, q = lane >> 4;
-    f32x4 acc[ND][MT][NT];
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[j][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    f32x4 accb[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) accb[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 ones, zero;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        ones[e] = (bf16)1.f;
-        zero[e] = (bf16)0.f;
-    }
-    const int64_t sw0 = (int64_t)blockIdx.x * per_block;
-    const int64_t sw1 = sw0 + per_block < n_sw ? sw0 + per_block : n_sw;
-    for (int64_t sw = sw0; sw < sw1; ++sw) {
-        const int64_t w = sw / N;
-        const int v = (int)(sw - w * N);
-        const int vx = v % L, vy = (v / L) % L, vz = v / (L * L);
-        bf16x8 b[NT][2];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = 16 * nt + r16;
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb)
-                b[nt][kb] = co < CYS ? *reinterpret_cast<const bf16x8*>(
-                                           dyT + (sw * CYS + co) * 64 + 32 * kb + 8 * q)
-                                     : zero;
-        }
-        if (wave == 0) {
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb)
-                    accb[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, b[nt][kb], accb[nt],
-                                                                       0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            const int d = wave + 4 * j;
-            if (d >= 27) break;
-            const int u = wrap(vx + off_x(d), L) + L * (wrap(vy + off_y(d), L) +
-                                                        L * wrap(vz + off_z(d), L));
-            const int64_t urow = (w * N + u) * CXS;
-            bf16x8 a[MT][2];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const int ci = 16 * mt + r16;
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb)
-                    a[mt][kb] = ci < CXS ? *reinterpret_cast<const bf16x8*>(
-                                               xT + (urow + ci) * 64 + 32 * kb + 8 * q)
-                                         : zero;
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                    for (int kb = 0; kb < 2; ++kb)
-                        acc[j][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            a[mt][kb], b[nt][kb], acc[j][mt][nt], 0, 0, 0);
-        }
-    }
-    // lane holds D[ci = 16 mt + 4 q + i][co = 16 nt + r16]
-    float* pb = part + (int64_t)blockIdx.x * 27 * CIN * COUT;
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-        const int d = wave + 4 * j;
-        if (d >= 27) break;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = 16 * nt + r16;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int ci = 16 * mt + 4 * q + i;
-                    if (ci < CIN && co < COUT)
-                        pb[((int64_t)d * CIN + ci) * COUT + co] = acc[j][mt][nt][i];
-                }
-            }
-    }
-    // every row of the all-ones product holds the bias sum; row 0 is lane q = 0
-    if (wave == 0 && q == 0) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = 16 * nt + r16;
-            if (co < COUT) part_b[(int64_t)blockIdx.x * COUT + co] = accb[nt][0];
-        }
-    }
-}
-
-// The same contraction walking x-pencils: wavefront c of 9 owns the (dy, dz)
-// column c (dy = c % 3 - 1, dz = c / 3 - 1) and its three offsets d = 3 c + dx.
-// Along the pencil it keeps the x copies of sites x - 1, x, x + 1 of the
-// neighbour pencil in registers and loads one new site per step, so a site's
-// x fragments feed three offsets and its dy fragments are read once per
-// wavefront: 8 loads per 24 MFMAs instead of 32 per 56. Wavefront 0 also owns
-// the bias gradient.
+// MFMA 16x16x32 with M = ci, N = co and K = 32 shots of one site: an A lane
+// (ci = 16 mt + lane % 16, shots 8 (lane / 16) ..) is a 16-byte load of a
+// neighbour site's x copy, a B lane likewise of this site's dy copy. A
+// workgroup walks x-pencils; wavefront c of its 9 owns the (dy, dz) column c
+// (dy = c % 3 - 1, dz = c / 3 - 1) and the three offsets d = 3 c + dx. Along
+// the pencil it keeps the x copies of sites x - 1, x, x + 1 of the neighbour
+// pencil in registers and loads one new site per step, so a site's x
+// fragments feed three offsets: 8 loads per 24 MFMAs. Wavefront 0 also owns
+// the bias gradient, as the product of an all-ones A with dy. Each workgroup
+// walks a contiguous range of pencils and writes its partial sums to
+// part[block][27][CIN][COUT] and part_b[block][COUT]; k_reduce8 adds the
+// partials in a fixed order.
 template <int CIN, int COUT, int CXS, int CYS>
 __global__ __launch_bounds__(576) void k_wgradP(const bf16* __restrict__ xT,
                                                 const bf16* __restrict__ dyT, int L, int N,
@@ -939,7 +825,6 @@ struct CnnWs {
 };
 
 constexpr int kWgradBlocks = 512;
-constexpr bool kWgradPencils = true;
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -1184,21 +1069,12 @@ int launch_wgrad(const Ctx& c, const bf16* x, const bf16* dy, Geo g, int64_t R, 
     int rc;
     if ((rc = launch_rows_to_shots<CXS>(c, x, w.xT, n_sw))) return rc;
     if ((rc = launch_rows_to_shots<CYS>(c, dy, w.dyT, n_sw))) return rc;
-    int nb;
-    if (kWgradPencils) {
-        const int64_t n_pencils = n_sw / g.L;  // W L^2 x-pencils
-        const int64_t per = cdiv(n_pencils, kWgradBlocks);
-        nb = (int)cdiv(n_pencils, per);
-        if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
-        k_wgradP<CIN, COUT, CXS, CYS><<<dim3(nb), dim3(576), 0, c.stream>>>(
-            w.xT, w.dyT, g.L, g.N, n_pencils, per, w.part, w.part_b);
-    } else {
-        const int64_t per = cdiv(n_sw, kWgradBlocks);
-        nb = (int)cdiv(n_sw, per);
-        if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
-        k_wgradT<CIN, COUT, CXS, CYS><<<dim3(nb), dim3(256), 0, c.stream>>>(
-            w.xT, w.dyT, g.L, g.N, n_sw, per, w.part, w.part_b);
-    }
+    const int64_t n_pencils = n_sw / g.L;  // W L^2 x-pencils
+    const int64_t per = cdiv(n_pencils, kWgradBlocks);
+    const int nb = (int)cdiv(n_pencils, per);
+    if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
+    k_wgradP<CIN, COUT, CXS, CYS><<<dim3(nb), dim3(576), 0, c.stream>>>(
+        w.xT, w.dyT, g.L, g.N, n_pencils, per, w.part, w.part_b);
     if ((rc = after_launch(c))) return rc;
     const int64_t nw = 27 * CIN * COUT;
     if ((rc = before_launch(c, TC3D_K_CNN))) return rc;
