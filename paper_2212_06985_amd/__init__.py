@@ -17,8 +17,8 @@ import os
 
 __all__ = [
     "Lattice", "RunParams", "Timing", "Tc3dError", "lib", "make_lattice", "sample_noise",
-    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "subset_pflip_sweep", "bp_meta_workspace_bytes",
-    "bp_meta_decode", "bp_meta_step", "bp_workspace_bytes",
+    "syndrome", "sweep_workspace_bytes", "flip_sweep", "pflip_sweep", "subset_pflip_sweep",
+    "bp_meta_workspace_bytes", "bp_meta_decode", "bp_meta_step", "bp_workspace_bytes",
     "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
     "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
 ]
