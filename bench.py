@@ -312,7 +312,8 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
         achieved = flop / (avg_ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": "cnn (forward: input + 4 BF16 conv launches)",
+                "traffic": stored_traffic("cnn", workload),
+                "kernel": "cnn (forward: input + 4 BF16 conv launches)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
                 "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
                 "unit_of_work": "site-shot forward (passes of 5 launches)"}
