@@ -1,5 +1,5 @@
 // C ABI (include/tc3d.h): argument checks, workspace carving, the BP
-// iteration schedule and the multi-cycle driver. Every step of the decoding
+// iteration schedule and the multi-cycle loop. Every step of the decoding
 // path runs in the kernels of tc3d_bits.hip and tc3d_bp.hip.
 #include <math.h>
 #include <string.h>

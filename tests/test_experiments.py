@@ -1,4 +1,4 @@
-"""Host logic of the experiment driver: the flip / p-flip schedules of
+"""Host logic of experiments.py: the flip / p-flip schedules of
 Sections 3-4 and 6 and the threshold fit of Section 4 (no GPU needed)."""
 import numpy as np
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's majority-vote readout and multi-cycle driver."""
+"""Pins of the oracle's majority-vote readout and multi-cycle loop."""
 import itertools
 
 import numpy as np
@@ -57,7 +57,7 @@ def test_noiseless_run_stays_clean():
 
 
 def test_run_matches_composed_stages():
-    """One cycle of the driver equals noise, syndrome, measurement noise, BP,
+    """One cycle of the multi-cycle run equals noise, syndrome, measurement noise, BP,
     working-syndrome update, the sweep schedule and the final correction."""
     L = 4
     o = Oracle(L)
