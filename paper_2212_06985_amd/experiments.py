@@ -68,13 +68,25 @@ def decoder_params(decoder: str, n_a: int = 1, lambda_p: int = 0, bp_iters: int 
 
 
 def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=0,
-               bp_iters=None, chunk_shots=None, shot0=0, q_dec=None, schedule=None, bp_meta=0):
+               bp_iters=None, chunk_shots=None, shot0=0, q_dec=None, schedule=None, bp_meta=0,
+               cnn_weights=None, beta=0.5):
     """Logical error statistics of `shots` independent memory runs.
 
+    cnn_weights: path of a trained network (.npy); BP then starts from its
+    per-edge prior, blended with the channel prior at strength beta.
     Returns the mask histogram (index = bit x | bit y << 1 | bit z << 2), the
     per-axis failure counts, the majority-vote ties and the GPU time."""
     import torch
     it, ns, mask_bits = decoder_params(decoder, n_a, lambda_p, bp_iters)
+    packed = None
+    if cnn_weights is not None:
+        if it == 0:
+            raise ValueError("the CNN prior feeds BP: pick a decoder with BP iterations")
+        from paper_2212_06985_amd.train_cnn import blend_prior
+        w = np.load(cnn_weights, allow_pickle=False)
+        d = torch.from_numpy(blend_prior(w, beta, p).astype(np.float32)).cuda()
+        packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
+        tc.cnn_pack(d, packed)
     sub_bits = 0
     if schedule:
         ns, mask_bits, sub_bits = parse_schedule(schedule)
@@ -94,11 +106,15 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
         prm = tc.make_run_params(p, p, cycles, it, ns, mask_bits, n_shots=n, seed=seed,
                                  shot0=shot0 + done, perfect_final=0, q_dec=q_dec,
                                  subset_mask=sub_bits, bp_meta=bp_meta)
-        need = tc.run_workspace_bytes(lat, prm)
+        need = (tc.run_workspace_bytes(lat, prm) if packed is None
+                else tc.run_cnn_workspace_bytes(lat, prm))
         if ws is None or ws.numel() < need:
             ws = tc.alloc_workspace(need)
         err.zero_()
-        t = tc.run_cycles_timed(lat, prm, err, mask, odd, ws)
+        if packed is None:
+            t = tc.run_cycles_timed(lat, prm, err, mask, odd, ws)
+        else:
+            t = tc.run_cycles_cnn_timed(lat, prm, packed, err, mask, odd, ws)
         ms += t.total_ms
         m = mask[:n].cpu().numpy()
         hist += np.bincount(m, minlength=8)
@@ -108,6 +124,7 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
     return {"L": L, "p": p, "cycles": cycles, "decoder": decoder, "n_a": n_a,
             "lambda_p": lambda_p, "bp_iters": it, "shots": shots, "seed": seed,
             "q_dec": p if q_dec is None else q_dec, "schedule": schedule, "bp_meta": bp_meta,
+            "cnn_weights": cnn_weights, "beta": beta if cnn_weights else None,
             "hist": hist.tolist(), "fails": fails, "ties": ties, "gpu_ms": ms,
             "qubit_cycles_per_s": 3 * L ** 3 * cycles * shots / (ms * 1e-3)}
 
@@ -172,13 +189,15 @@ def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec
 
 
 def threshold(decoder, Ls, ps, cycles, shots, seed=1, n_a=1, lambda_p=0, bp_iters=None,
-              pooled=False, log=print, q_dec=None, schedule=None, bp_meta=0):
+              pooled=False, log=print, q_dec=None, schedule=None, bp_meta=0, cnn_weights=None,
+              beta=0.5):
     rows = []
     for L in Ls:
         for p in ps:
             t0 = time.perf_counter()
             r = memory_run(L, p, cycles, decoder, shots, seed, n_a, lambda_p, bp_iters,
-                           q_dec=q_dec, schedule=schedule, bp_meta=bp_meta)
+                           q_dec=q_dec, schedule=schedule, bp_meta=bp_meta,
+                           cnn_weights=cnn_weights, beta=beta)
             f, s = pfail_pooled(r) if pooled else pfail(r)
             r["pfail"], r["pfail_sigma"] = f, s
             rows.append(r)
@@ -230,6 +249,10 @@ def main():
                     help="BP with meta-check factors (cube parities of the measurement errors)")
     th.add_argument("--q-dec", type=float, default=None,
                     help="measurement-error rate BP assumes (default: q = p)")
+    th.add_argument("--cnn-weights", default=None,
+                    help="trained network (.npy): BP starts from its per-edge prior")
+    th.add_argument("--beta", type=float, default=0.5,
+                    help="strength of the CNN prior (with --cnn-weights)")
     th.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.cmd == "table2":
@@ -239,7 +262,8 @@ def main():
     res = threshold(args.decoder, args.L, args.p, args.cycles, args.shots, args.seed, args.n_a,
                     args.lambda_p, args.bp_iters, args.pooled,
                     log=lambda m: print(m, flush=True), q_dec=args.q_dec,
-                    schedule=args.schedule, bp_meta=int(args.bp_meta))
+                    schedule=args.schedule, bp_meta=int(args.bp_meta),
+                    cnn_weights=args.cnn_weights, beta=args.beta)
     print(json.dumps({"fit": res["fit"], "decoder": res["decoder"], "n_a": res["n_a"],
                       "schedule": args.schedule, "bp_meta": bool(args.bp_meta),
                       "lambda_p": res["lambda_p"], "cycles": res["cycles"]}), flush=True)

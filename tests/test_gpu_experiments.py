@@ -45,3 +45,33 @@ def test_threshold_is_bracketed(n_a, lam, p_lo, p_hi, paper):
                  f"L=32 {f32:.4f}+-{s32:.4f}")
         gap = (f14 - f32) if below else (f32 - f14)
         assert gap > 3 * math.sqrt(s14 ** 2 + s32 ** 2), (p, f14, f32)
+
+
+def test_memory_run_with_the_cnn_prior_is_run_cycles_cnn():
+    """The experiment runner's CNN option is tc3d_run_cycles_cnn on the same
+    shots: the same network blended the same way, the same failure masks."""
+    import os
+
+    import numpy as np
+    import torch
+
+    import paper_2212_06985_amd as tc
+    from paper_2212_06985_amd.train_cnn import blend_prior
+    L, p, cycles, shots, beta, it = 6, 0.06, 20, 512, 0.5, 8
+    w = os.path.join(os.path.dirname(tc.__file__), "weights", "cnn_L12_long.npy")
+    r = ex.memory_run(L, p, cycles, "pbp", shots, seed=5, bp_iters=it, cnn_weights=w,
+                      beta=beta)
+    d = torch.from_numpy(blend_prior(np.load(w), beta, p).astype(np.float32)).cuda()
+    packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
+    tc.cnn_pack(d, packed)
+    lat = tc.make_lattice(L)
+    prm = tc.make_run_params(p, p, cycles, it, 6, 0b001001, n_shots=shots, seed=5,
+                             perfect_final=0)
+    err = torch.zeros((lat.n_edges, tc.n_words(shots)), dtype=torch.int64, device="cuda")
+    mask = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+    ws = tc.alloc_workspace(tc.run_cnn_workspace_bytes(lat, prm))
+    tc.run_cycles_cnn(lat, prm, packed, err, mask, None, ws)
+    hist = np.bincount(mask.cpu().numpy(), minlength=8)
+    announce(f"  cnn memory run L={L}: {r['hist']}")
+    assert r["hist"] == hist.tolist()
+    assert r["cnn_weights"] == w and r["beta"] == beta
