@@ -154,7 +154,7 @@ int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                  const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
                  float* nu_out, float* post_out, void* stream);
 
-/* Majority-vote readout (Section 3.1 and Fig. 1 caption): for each axis d,
+/* Majority-vote readout (Section 3.1 and Fig. 2 caption): for each axis d,
  * count the L^2 disjoint logical Z strings along d (the L d-edges through
  * fixed other coordinates) whose error parity is odd; the shot has a logical
  * X error on qubit d when that count is at least L^2/2 (a tie counts as a
@@ -312,7 +312,7 @@ int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* pr
 
 /* -------------------------------------------------------- batched jobs
  * Many experiments of Sections 3-4 at once: any mix of lattice sizes, error
- * rates, cycle counts, decoders and seeds (the sweeps behind Figs. 2, 5, 6
+ * rates, cycle counts, decoders and seeds (the sweeps behind Figs. 2, 6, 7
  * and Table 1 are such mixes). Every job is exactly tc3d_run_cycles on its
  * own buffers, so its results do not depend on the other jobs or the flags. */
 typedef struct {

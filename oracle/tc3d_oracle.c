@@ -578,7 +578,7 @@ void tco_bp_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,
 /* Section 2: a logical Z operator of qubit d is a string of the L edges along
  * axis d through fixed values of the other two coordinates; the L^2 such
  * strings are disjoint. A logical X error flips all of them. The readout is a
- * majority vote over the strings' parities (Section 3.1, Fig. 1 caption). */
+ * majority vote over the strings' parities (Section 3.1, Fig. 2 caption). */
 void tco_logical_check(const tco_lattice* lat, const uint8_t* err, int64_t n_shots,
                        uint8_t* mask, int32_t* odd) {
     const int32_t L = lat->L;

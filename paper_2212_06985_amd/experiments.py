@@ -6,12 +6,12 @@ readout of the three logical qubits (no extra perfect round: the paper reads
 the residual out right after the last decoded cycle). Decoders:
 
 * ``flip``: n_A sweeps per cycle; sweep k (counting from 1) is p-flip when k
-  is a multiple of lambda_p, else flip (Sections 3 and 4, Table 1; n_A = 1 is
+  is a multiple of lambda_p, else flip (Section 3.2, Table 1; n_A = 1 is
   the parallel flip decoder of Fig. 2).
-* ``bp``: BP alone, 30 iterations per cycle (Section 5, Fig. 5).
-* ``pbp``: 20 BP iterations, then P F F P F F (Section 6, Fig. 6, Table 2).
+* ``bp``: BP alone, 30 iterations per cycle (Section 4.1, Fig. 6).
+* ``pbp``: 20 BP iterations, then P F F P F F (Section 4.2, Fig. 7, Table 2).
 
-Thresholds are fitted as in Section 4: p_fail = a0 + a1 x + a2 x^2 with
+Thresholds are fitted as in Section 3.2: p_fail = a0 + a1 x + a2 x^2 with
 x = (p - p_th) L^(1/nu), by weighted least squares (scipy's curve_fit).
 
     python -m paper_2212_06985_amd.experiments table2 --shots 16384
@@ -172,6 +172,24 @@ def fit_threshold(L, p, f, sigma, p_th0=None):
             "dof": int(len(f) - len(popt))}
 
 
+def correlations(counts):
+    """Logical-error correlations of Appendix A.2 from configuration counts
+    ('xyz' bit strings, 1 = a logical error on that encoded qubit): the
+    per-qubit failure rates, the count each configuration would have if the
+    three qubits failed independently at those rates, and observed / expected
+    (None where the expectation is zero)."""
+    n = sum(counts.values())
+    rate = [sum(c for k, c in counts.items() if k[d] == "1") / n for d in range(3)]
+    expected = {}
+    for k in counts:
+        pr = 1.0
+        for d in range(3):
+            pr *= rate[d] if k[d] == "1" else 1.0 - rate[d]
+        expected[k] = n * pr
+    ratio = {k: (counts[k] / expected[k] if expected[k] > 0 else None) for k in counts}
+    return {"n": n, "rate": rate, "expected": expected, "ratio": ratio}
+
+
 def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec=None):
     """Logical error configurations after 500 cycles of p-BP at L = 14,
     p = q = 0.0544, next to the paper's counts out of 1000 (Table 2).
@@ -185,7 +203,8 @@ def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec
     table = np.array([[TABLE2_COUNTS[k] for k in keys], [ours[k] for k in keys]])
     stat, pval, dof, _ = chi2_contingency(table)
     return {"run": r, "ours": ours, "paper": TABLE2_COUNTS, "chi2": float(stat),
-            "dof": int(dof), "p_value": float(pval)}
+            "dof": int(dof), "p_value": float(pval),
+            "correlations": {"paper": correlations(TABLE2_COUNTS), "ours": correlations(ours)}}
 
 
 def threshold(decoder, Ls, ps, cycles, shots, seed=1, n_a=1, lambda_p=0, bp_iters=None,

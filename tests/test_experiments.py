@@ -1,12 +1,12 @@
 """Host logic of experiments.py: the flip / p-flip schedules of
-Sections 3-4 and 6 and the threshold fit of Section 4 (no GPU needed)."""
+Sections 3.2 and 4.2 and the threshold fit of Section 3.2 (no GPU needed)."""
 import numpy as np
 
 from paper_2212_06985_amd import experiments as ex
 
 
 def test_schedules():
-    # n_A = 5, lambda_p = 3: F F P F F, the worked schedule of Section 4
+    # n_A = 5, lambda_p = 3: F F P F F, the worked schedule of Section 3.2
     assert ex.flip_mask(5, 3) == 0b00100
     # lambda_p > n_A: only flip sweeps (the shaded cells of Table 1)
     assert ex.flip_mask(5, 6) == 0

@@ -12,6 +12,7 @@ import math
 
 import pytest
 
+import golden_data as gd
 from gpu_util import announce
 from paper_2212_06985_amd import experiments as ex
 
@@ -31,11 +32,18 @@ def _rate(L, p, n_a, lam, shots):
     return ex.pfail(r)
 
 
-@pytest.mark.parametrize("n_a,lam,p_lo,p_hi,paper", [
-    (1, 0, 0.0258, 0.0264, 0.02611),   # Fig. 2
-    (5, 3, 0.0440, 0.0450, 0.04445),   # Table 1
+def _printed(n_a, lam):
+    """The threshold Table 1 prints for (n_A, lambda_p) (tests/golden/)."""
+    cells = {(n, l): th for n, l, th, _ in gd.table1()}
+    return cells[(n_a, lam)]
+
+
+@pytest.mark.parametrize("n_a,lam,p_lo,p_hi", [
+    (1, 2, 0.0258, 0.0264),   # Fig. 2: flip once per cycle (the shaded n_A = 1 cell)
+    (5, 3, 0.0440, 0.0450),   # Table 1: F F P F F
 ])
-def test_threshold_is_bracketed(n_a, lam, p_lo, p_hi, paper):
+def test_threshold_is_bracketed(n_a, lam, p_lo, p_hi):
+    paper = _printed(n_a, lam)
     assert p_lo < paper < p_hi
     shots = 4096
     for p, below in ((p_lo, True), (p_hi, False)):

@@ -118,7 +118,7 @@ def test_sweeps_bit_exact(L, pflip):
 
 
 def test_pflip_clears_corner_at_the_enumerated_rate():
-    """The corner half-star of Fig. 2a, decoded by P then F on many shots:
+    """The corner half-star of Fig. 3(a), decoded by P then F on many shots:
     the cleared fraction matches the exhaustive 44/64 within 4 sigma."""
     import geom
     L = 6
@@ -143,6 +143,60 @@ def test_pflip_clears_corner_at_the_enumerated_rate():
     frac = cleared.mean()
     sigma = math.sqrt(44 / 64 * 20 / 64 / S)
     assert abs(frac - 44 / 64) < 4 * sigma, frac
+
+
+def test_flip_examples_of_the_paper():
+    """The worked examples of Figs. 3-5 and Section 3.2 (tests/golden/
+    flip_examples.txt), one per shot of one batch, through the GPU syndrome,
+    two parallel flip sweeps and the readout: the unsatisfied-check counts,
+    the errors after each sweep and the cleared cases are those the paper
+    states."""
+    import torch
+    import golden_data as gd
+    L = gd.EXAMPLE_L
+    examples = gd.flip_examples()
+    names = sorted(examples)
+    announce(f"flip examples L={L}: {' '.join(names)}")
+    lat = tc.make_lattice(L)
+    n_edges, n_faces = 3 * L ** 3, 3 * L ** 3
+    S = len(names)
+    err = np.zeros((64, n_edges), np.uint8)
+    for s, name in enumerate(names):
+        err[s, sorted(examples[name]["support"])] = 1
+    d_err = dev_plane_of_bits(err)
+    d_syn = dev_plane_of_bits(np.zeros((64, n_faces), np.uint8))
+    d_corr = dev_plane_of_bits(np.zeros((64, n_edges), np.uint8))
+    ws = tc.alloc_workspace(tc.sweep_workspace_bytes(lat, 1))
+    tc.syndrome(lat, d_err, d_syn, 1)
+    sync()
+    unsat = bits_of_dev(d_syn, 64).sum(axis=1)
+    for s, name in enumerate(names):
+        if "unsat" in examples[name]:
+            assert unsat[s] == examples[name]["unsat"], name
+    for key in ("after1", "after2"):
+        tc.flip_sweep(lat, d_syn, d_corr, 1, ws)
+        sync()
+        res = err ^ bits_of_dev(d_corr, 64)
+        for s, name in enumerate(names):
+            if key in examples[name]:
+                assert set(np.flatnonzero(res[s])) == examples[name][key], (name, key)
+        if key == "after1":
+            # the working syndrome is that of the residual error
+            d_res = dev_plane_of_bits(res)
+            d_chk = dev_plane_of_bits(np.zeros((64, n_faces), np.uint8))
+            tc.syndrome(lat, d_res, d_chk, 1)
+            mask = torch.zeros(S, dtype=torch.uint8, device="cuda")
+            odd = torch.zeros((S, 3), dtype=torch.int32, device="cuda")
+            tc.logical_check(lat, d_res, S, mask, odd)
+            sync()
+            syn1 = bits_of_dev(d_syn, 64)
+            assert np.array_equal(syn1, bits_of_dev(d_chk, 64))
+            odd = odd.cpu().numpy()
+            for s, name in enumerate(names):
+                if examples[name].get("cleared"):
+                    assert syn1[s].sum() == 0 and odd[s].sum() == 0, name
+    # padding shots stay empty
+    assert not res[S:].any()
 
 
 # ---------------------------------------------------------------- readout

@@ -1,5 +1,5 @@
 """Pins of the oracle's flip and p-flip (Section 3) against the behaviour the
-paper states for its catalogue of low-weight errors (Figs. 2-4 and the
+paper states for its catalogue of low-weight errors (Figs. 3-5 and the
 surrounding text), against an independent set-based brute force, and against
 exhaustive enumeration on L = 3."""
 import itertools
@@ -62,9 +62,9 @@ def cleared(o, err_bits):
     return o.syndrome(err_bits[None]).sum() == 0 and odd.sum() == 0
 
 
-# ------------------------------------------------------------ Figs. 2, 4
+# ------------------------------------------------------------ Figs. 3, 5
 def test_corner_half_star_is_stuck_and_ties_are_the_star():
-    # Fig. 2a: three of the six qubits of an X stabiliser, each in two
+    # Fig. 3(a): three of the six qubits of an X stabiliser, each in two
     # satisfied and two unsatisfied checks.
     e = bits([E(X), E(Y), E(Z)])
     u, w = unsat_counts(e)
@@ -81,7 +81,7 @@ def plane_block(cells, z=0):
 
 
 def test_planar_two_by_two_is_stuck_and_ties_are_its_support():
-    # Fig. 2b: four coplanar qubits, each in two satisfied and two unsatisfied
+    # Fig. 3(b): four coplanar qubits, each in two satisfied and two unsatisfied
     e_idx = plane_block([(0, 0), (1, 0), (0, 1), (1, 1)])
     e = bits(e_idx)
     u, w = unsat_counts(e)
@@ -93,7 +93,7 @@ def test_planar_two_by_two_is_stuck_and_ties_are_its_support():
 
 
 def test_parallel_flip_swaps_the_two_u_shapes():
-    # Fig. 4: four qubits (two with errors, two without) see three unsatisfied
+    # Fig. 5: four qubits (two with errors, two without) see three unsatisfied
     # checks; flipping them together rotates the error and keeps its weight.
     o = Oracle(L)
     e = bits([E(Z, -1), E(Z, +1), E(Y, +1)])
@@ -107,9 +107,9 @@ def test_parallel_flip_swaps_the_two_u_shapes():
     assert np.array_equal(twice, e)
 
 
-# ------------------------------------------------------------------ Fig. 3
+# ------------------------------------------------------------------ Fig. 4
 def test_fourth_face_makes_corner_correctable():
-    # Fig. 3a: an extra error on a fourth face of the cube
+    # Fig. 4(a): an extra error on a fourth face of the cube
     o = Oracle(L)
     e = bits([E(X), E(Y), E(Z), E(X, -1)])
     u, _ = unsat_counts(e)
@@ -120,7 +120,7 @@ def test_fourth_face_makes_corner_correctable():
 
 
 def test_neighbouring_error_is_removed_and_corner_restored():
-    # Fig. 3b: flip corrects the additional error and restores the original
+    # Fig. 4(b): flip corrects the additional error and restores the original
     o = Oracle(L)
     w = (V[0] - 1, V[1], V[2])
     e = bits([E(X), E(Y), E(Z), E(Z, +1, at=w)])
@@ -129,7 +129,7 @@ def test_neighbouring_error_is_removed_and_corner_restored():
 
 
 def test_two_cube_half_is_stuck():
-    # Fig. 3c: two more errors grow it into a five-qubit uncorrectable error
+    # Fig. 4(c): two more errors grow it into a five-qubit uncorrectable error
     w = (V[0] - 1, V[1], V[2])
     e = bits([E(X), E(Y), E(Z), E(Y, +1, at=w), E(Z, +1, at=w)])
     u, wt = unsat_counts(e)
@@ -139,18 +139,18 @@ def test_two_cube_half_is_stuck():
 
 def test_planar_variants():
     o = Oracle(L)
-    # Fig. 3d: three of the 2x2 are correctable (two sweeps)
+    # Fig. 4(d): three of the 2x2 are correctable (two sweeps)
     e = bits(plane_block([(0, 0), (1, 0), (0, 1)]))
     one, _ = oracle_sweep(o, e)
     assert set(np.flatnonzero(one)) == set(plane_block([(0, 0)]))
     two, _ = oracle_sweep(o, e, n=2)
     assert two.sum() == 0
-    # Fig. 3e: one extra coplanar error is removed, restoring the 2x2
+    # Fig. 4(e): one extra coplanar error is removed, restoring the 2x2
     sq = plane_block([(0, 0), (1, 0), (0, 1), (1, 1)])
     e = bits(sq + plane_block([(2, 0)]))
     one, _ = oracle_sweep(o, e)
     assert set(np.flatnonzero(one)) == set(sq)
-    # Fig. 3f: a 3x2 block is stuck
+    # Fig. 4(f): a 3x2 block is stuck
     e = bits(plane_block([(i, j) for i in range(3) for j in range(2)]))
     u, _ = unsat_counts(e)
     assert (u < 3).all()
@@ -255,7 +255,7 @@ def test_sequential_flip_strictly_lowers_syndrome_weight():
 
 
 def test_sequential_flip_corrects_u_shape():
-    # Section 3.2: the Fig. 4 error is correctable for the sequential version
+    # Section 3.2: the Fig. 5 error is correctable for the sequential version
     o = Oracle(L)
     e = bits([E(Z, -1), E(Z, +1), E(Y, +1)])
     syn = o.syndrome(e[None])[0]
