@@ -123,6 +123,16 @@ __device__ __forceinline__ Item item_of(const Tiling& tl) {
     return it;
 }
 
+// Bit `lane` of a 64-shot syndrome word, read as the 32-bit half that holds
+// it. The address differs between the two halves of the wavefront, so this is
+// a vector load: those return in order and can all be in flight together,
+// while scalar loads of a whole word return out of order and make the wave
+// wait for each batch in turn.
+__device__ __forceinline__ uint32_t shot_bit(const uint64_t* word, int lane) {
+    const uint32_t h = reinterpret_cast<const uint32_t*>(word)[lane >> 5];
+    return (h >> (lane & 31)) & 1u;
+}
+
 // Reads of one shot word: a wave-uniform site base plus a per-lane offset.
 template <int MODE>
 struct Reader {
@@ -138,8 +148,8 @@ struct Reader {
         if constexpr (MODE == NU_ZERO) {
             return 1.0f;
         } else if constexpr (MODE == NU_SIGMA) {
-            const uint64_t word = syn_w[(slot >> 2) * face_plane + (int64_t)site * ld_syn];
-            return ((word >> lane) & 1u) ? b1_inv : b1;
+            return shot_bit(syn_w + (slot >> 2) * face_plane + (int64_t)site * ld_syn, lane)
+                       ? b1_inv : b1;
         } else {
             const char* sb = base + (int64_t)site * site_bytes;
             return *reinterpret_cast<const float*>(sb + voff[slot]);
@@ -237,6 +247,11 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
     const Reader<MODE> R = reader_of<MODE>(S, it);
     const Nbr nb = neighbours(it, tl.L);
     const int v = it.v;
+    // syndrome bits of the three faces of v (read first, with the messages)
+    uint32_t sbit[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+        sbit[n] = shot_bit(S.syn + ((int64_t)n * S.N + v) * S.ld_syn + it.w, it.lane);
     // own messages to the members k = 0, 2 of each face (the others are the
     // excluded message of the member-k check and are not needed)
     const float o0 = R(0, v), o2 = R(2, v), o4 = R(4, v), o6 = R(6, v), o8 = R(8, v),
@@ -280,8 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
             a[0] = FOLD == 2 ? fy * o10 : py * o10; a[1] = a_y_zp;
             a[2] = FOLD == 2 ? fz * o6 : pz * o6; a[3] = a_z_yp;
         }
-        const uint64_t sw = S.syn[((int64_t)n * S.N + v) * S.ld_syn + it.w];
-        const float sK = ((sw >> it.lane) & 1u) ? -K : K;
+        const float sK = sbit[n] ? -K : K;
         float out[4];
         check_rule(a, sK, out);
         if constexpr (FOLD != 0) {  // slots 8, 10, 6 carry the priors of e(v,x), e(v,y), e(v,z)
