@@ -393,30 +393,31 @@ bool tiling_of(Geo g, const BpArgs& a, Tiling* out) {
 
 }  // namespace
 
-// Residency of the iterations that read stored messages. They run faster with
-// four workgroups (16 wavefronts) per CU than with the 32 wavefronts their
-// registers allow: 4.08 instead of 4.19 ms at L = 48 (2048 shots) and 1.92
-// instead of 2.03 ms at L = 12 (65,536 shots), measured in one run; three or
-// five per CU are between. The cap is dynamic LDS that the kernel does not touch: just over a
-// fifth of the CU's LDS each, so a fifth workgroup does not fit. 0 (no cap)
-// when the device cannot be queried.
-static constexpr int kLoadBlocksPerCu = 4;
-static std::atomic<int> g_load_lds[64];
+// Residency of the kernels that read stored messages. The iterations run
+// faster with four workgroups (16 wavefronts) per CU than with the 32
+// wavefronts their registers allow: 4.08 instead of 4.19 ms at L = 48 (2048
+// shots) and 1.92 instead of 2.03 ms at L = 12 (65,536 shots), measured in one
+// run; three or five per CU are between. The posterior is fastest with six
+// (2.14 instead of 2.20 ms at L = 48). The cap is dynamic LDS that the kernel
+// does not touch: just over 1/(n+1) of the CU's LDS per workgroup, so n fit
+// and n + 1 do not. 0 (no cap) when the device cannot be queried.
+static constexpr int kLoadIterBlocksPerCu = 4;
+static constexpr int kLoadPostBlocksPerCu = 6;
+static std::atomic<int> g_cu_lds[64];
 
-static size_t load_iter_lds() {
+static size_t residency_lds(int blocks_per_cu) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    int b = g_load_lds[dev].load(std::memory_order_relaxed);
-    if (b == 0) {
-        int per_cu = 0;
+    int per_cu = g_cu_lds[dev].load(std::memory_order_relaxed);
+    if (per_cu == 0) {
         if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
                                   dev) != hipSuccess ||
             per_cu < 4096)
             return 0;
-        b = per_cu / (kLoadBlocksPerCu + 1) + 1024;  // > 1/5 of the CU, <= 1/4
-        if (b > per_cu / kLoadBlocksPerCu) b = per_cu / kLoadBlocksPerCu;
-        g_load_lds[dev].store(b, std::memory_order_relaxed);
+        g_cu_lds[dev].store(per_cu, std::memory_order_relaxed);
     }
+    int b = per_cu / (blocks_per_cu + 1) + 1024;  // > 1/(n+1) of the CU
+    if (b > per_cu / blocks_per_cu) b = per_cu / blocks_per_cu;  // <= 1/n
     return (size_t)b;
 }
 
@@ -430,7 +431,7 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (rc) return rc;
     const Src S = make_src(g, a, nu_in);
     const dim3 grid((unsigned)blocks), block(kBlock);
-    const size_t lds = mode == NU_LOAD ? load_iter_lds() : 0;
+    const size_t lds = mode == NU_LOAD ? residency_lds(kLoadIterBlocksPerCu) : 0;
     if (a.llr0) {
         if (mode == NU_ZERO && a.fold)
             k_bp_iter<NU_ZERO, true, 1><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
@@ -463,21 +464,22 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (rc) return rc;
     const Src S = make_src(g, a, nu);
     const dim3 grid((unsigned)blocks), block(kBlock);
+    const size_t lds = mode == NU_LOAD ? residency_lds(kLoadPostBlocksPerCu) : 0;
     if (a.llr0) {
         if (mode != NU_LOAD) return TC3D_EINVAL;  // a posterior follows a stored iteration
         if (a.fold)
-            k_bp_post<NU_LOAD, true, true><<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld,
-                                                                        post);
+            k_bp_post<NU_LOAD, true, true><<<grid, block, lds, c.stream>>>(S, tl, corr.p, corr.ld,
+                                                                          post);
         else
-            k_bp_post<NU_LOAD, true, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
-                                                                         corr.ld, post);
+            k_bp_post<NU_LOAD, true, false><<<grid, block, lds, c.stream>>>(S, tl, corr.p,
+                                                                           corr.ld, post);
     } else {
         if (mode == NU_SIGMA)
             k_bp_post<NU_SIGMA, false, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
                                                                            corr.ld, post);
         else if (mode == NU_LOAD)
-            k_bp_post<NU_LOAD, false, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
-                                                                          corr.ld, post);
+            k_bp_post<NU_LOAD, false, false><<<grid, block, lds, c.stream>>>(S, tl, corr.p,
+                                                                            corr.ld, post);
         else
             return TC3D_EINVAL;
     }
