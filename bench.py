@@ -296,6 +296,24 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
     return wall, per_class, ler, resid
 
 
+def path_roofline(bp_iters, value, per_edge_prior=False):
+    """Whole-path HBM model: algorithmic bytes per decoded qubit-cycle times the
+    qubit-cycles/s, against the HBM peak. Per qubit and cycle, BP streams its
+    four FP32 messages once per iteration (written by the first, read and
+    written by the others, read by the posterior: 32 B per iteration) and one
+    syndrome bit per iteration; with a per-edge prior each iteration also reads
+    the 4-byte prior. The bit planes (noise, syndrome, correction, sweeps,
+    apply) add about 32 bits. None without BP, where the path is bound by
+    integer ALU work and launches."""
+    if not bp_iters:
+        return None
+    per_unit = (32.0 + (4.0 if per_edge_prior else 0.0)) * bp_iters + bp_iters / 8.0 + 4.0
+    achieved = value * per_unit / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_unit": per_unit,
+            "unit_of_work": "decoded qubit-cycle"}
+
+
 def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
              per_edge_prior=False):
     """Roofline of the dominant kernel class, from the HIP-event launch times.
@@ -443,6 +461,7 @@ def run_c3(args, cfg, tc):
                                   "bit-sliced 64 per word"},
         "roofline": roof,
         "cpu_baseline": None,
+        "path_roofline": path_roofline(cfg["bp"], qc * steps / wall),
         "comparison": {"decoder": "same jobs, one stream, no graph",
                        "value": qc * steps / wall_seq, "unit": "qubit-cycles/s",
                        "ms_per_step": wall_seq / steps * 1e3},
@@ -600,6 +619,7 @@ def main():
                    "parallelism": "shots (bit-sliced 64 per word; one lane per shot in BP)"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "path_roofline": path_roofline(main_cfg["bp"], value, per_edge_prior=decoder == "cnn"),
         "ler": ler,
         "mean_residual_syndrome": resid,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in per_class.items()},

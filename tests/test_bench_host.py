@@ -81,3 +81,16 @@ def test_traffic_is_looked_up_per_kernel_variant(tmp_path, monkeypatch):
 
 
 _HASHES = {k: bench.kernel_source_hash(k) for k in bench.KERNEL_SOURCES}
+
+
+def test_path_roofline_model():
+    # 20 BP iterations: 20 x 32 B of messages + 20 syndrome bits + 4 B of bit planes
+    r = bench.path_roofline(20, 1e10)
+    assert r["bytes_per_unit"] == 32.0 * 20 + 20 / 8 + 4 == 646.5
+    assert r["achieved"] == pytest.approx(1e10 * 646.5 / 1e9, rel=1e-6)
+    assert r["frac"] == pytest.approx(1e10 * 646.5 / 8e12, abs=1e-4)
+    # a per-edge prior adds its 4-byte read to every iteration
+    assert bench.path_roofline(6, 1e10, per_edge_prior=True)["bytes_per_unit"] == \
+        36.0 * 6 + 6 / 8 + 4
+    # without BP there is no HBM model
+    assert bench.path_roofline(0, 1e10) is None
