@@ -169,3 +169,22 @@ def test_stream_copy_rejects_bad_arguments(lib):
     assert cp(ctypes.c_void_p((1 << 21) + 8), a, 64, 1, None) == -2   # misaligned
     assert cp(ctypes.c_void_p((1 << 20) + 32), a, 64, 0, None) == -1  # overlap
     assert cp(a, ctypes.c_void_p((1 << 20) + 48), 64, 0, None) == -1  # overlap
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding raises instead of falling back
+    to anything else."""
+    import subprocess
+    import sys
+    code = ("import paper_2212_06985_amd as tc\n"
+            f"tc.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+            "tc._lib = None\n"
+            "try:\n"
+            "    tc.make_lattice(6)\n"
+            "except ImportError as e:\n"
+            "    print('raised:', e)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=root, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert "raised:" in out.stdout and "absent.so is missing" in out.stdout
