@@ -179,6 +179,8 @@ def correlations(counts):
     three qubits failed independently at those rates, and observed / expected
     (None where the expectation is zero)."""
     n = sum(counts.values())
+    if n <= 0:
+        raise ValueError("no runs to correlate")
     rate = [sum(c for k, c in counts.items() if k[d] == "1") / n for d in range(3)]
     expected = {}
     for k in counts:

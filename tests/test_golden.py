@@ -127,3 +127,5 @@ def test_correlations_of_no_failure():
     assert c["ratio"]["000"] == 1.0
     assert all(c["ratio"][k] is None for k in c["ratio"] if k != "000")
     assert not any(math.isnan(v) for v in c["expected"].values())
+    with pytest.raises(ValueError):
+        ex.correlations({format(k, "03b"): 0 for k in range(8)})
