@@ -136,7 +136,12 @@ size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
  *             llr0_scalar = ln((1-p)/p) on every edge
  *   post_out  posterior LLRs [W][3L^3][64], or NULL
  * 0 <= meas_factor < 1; |llr0_scalar| <= 40 (per-edge priors are clamped to
- * +-40 nats). */
+ * +-40 nats).
+ * With the scalar prior on lattices of at most 3072 sites (L <= 14) the whole
+ * decode of each shot runs inside one workgroup, its messages in LDS; the
+ * result is bit-identical to the streaming kernels used otherwise, and the
+ * environment variable TC3D_BP_RESIDENT=0 selects those. tc3d_run_cycles
+ * decodes the same way. */
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                    const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
                    uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes, void* stream);

@@ -146,6 +146,8 @@ int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, 
     // folded into it (the one-step entry point keeps the plain state)
     BpArgs a = args;
     a.fold = a.llr0 != nullptr;
+    // small lattices: the whole decode of a shot inside one workgroup's LDS
+    if (iters >= 1 && bp_resident_ok(g, a)) return launch_bp_resident(c, g, a, iters, corr, post);
     int mode;
     const float* cur = nullptr;
     float* bufs[2] = {buf0, buf1};

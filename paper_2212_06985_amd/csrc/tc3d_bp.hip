@@ -39,6 +39,8 @@
 // running slowest inside the column; T = L by default, i.e. plain memory
 // order), with the message stores streaming past L2 so that the rows loaded
 // for neighbours stay resident.
+#include <stdlib.h>
+
 #include <atomic>
 
 #include "tc3d_device.hpp"
@@ -346,6 +348,120 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
     }
 }
 
+// ---------------------------------------------- one shot per workgroup in LDS
+// On small lattices the whole message state of one shot, 12 FP32 per site,
+// fits a CU's LDS (83 KB at L = 12, 132 KB at L = 14). A workgroup then runs
+// a whole decode for one shot: the first iteration's messages from the
+// syndrome, iterations 2 .. T and the posterior, with HBM traffic only for the
+// syndrome bits in and the correction bits out. Each thread owns sites
+// t, t + 1024, t + 2048 (SPT of them) and evaluates exactly the expressions of
+// k_bp_iter and k_bp_post, in the same order, so the decode is bit-identical
+// to the streaming kernels; the state is laid out [slot][site], so that the
+// lanes of a wavefront read consecutive words.
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsMaxSites = 3 * kLdsThreads;  // L <= 14
+
+template <int SPT>
+__global__ __launch_bounds__(kLdsThreads) void k_bp_lds(
+    const uint64_t* __restrict__ syn, int64_t ld_syn, int L, float a0, float b1, float b1_inv,
+    float K, int more_iters, uint64_t* __restrict__ corr, int64_t ld_c, float* __restrict__ post) {
+    extern __shared__ float m[];  // [12][N]
+    const int N = L * L * L;
+    const int64_t w = blockIdx.x >> 6;
+    const int bit = (int)(blockIdx.x & 63);
+    const int t = (int)threadIdx.x;
+    int xyz[SPT];
+    uint32_t sbit[SPT][3];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int v = t + k * kLdsThreads;
+        xyz[k] = -1;
+        if (v < N) {
+            const int x = v % L, y = (v / L) % L, z = v / (L * L);
+            xyz[k] = x | (y << 8) | (z << 16);
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                sbit[k][n] = (uint32_t)(syn[((int64_t)n * N + v) * ld_syn + w] >> bit) & 1u;
+                // the first iteration's messages, implied by the check's syndrome bit
+                const float b = sbit[k][n] ? b1_inv : b1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) m[(4 * n + j) * N + v] = b;
+            }
+        }
+    }
+    __syncthreads();
+    auto R = [&](int slot, int site) { return m[slot * N + site]; };
+    for (int it = 0; it < more_iters; ++it) {
+        float out[SPT][12];
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            if (xyz[k] < 0) continue;
+            const int x = xyz[k] & 255, y = (xyz[k] >> 8) & 255, z = xyz[k] >> 16;
+            const int xm = dec(x, L), xp = inc(x, L), ym = dec(y, L), yp = inc(y, L);
+            const int zm = dec(z, L), zp = inc(z, L);
+            const int v = site_of(x, y, z, L);
+            const int s_xm = site_of(xm, y, z, L), s_xp = site_of(xp, y, z, L);
+            const int s_ym = site_of(x, ym, z, L), s_yp = site_of(x, yp, z, L);
+            const int s_zm = site_of(x, y, zm, L), s_zp = site_of(x, y, zp, L);
+            const float o0 = R(0, v), o2 = R(2, v), o4 = R(4, v), o6 = R(6, v), o8 = R(8, v),
+                        o10 = R(10, v);
+            const float fx = R(9, s_ym) * R(5, s_zm);
+            const float fy = R(11, s_xm) * R(1, s_zm);
+            const float fz = R(7, s_xm) * R(3, s_ym);
+            const float px = a0 * fx, py = a0 * fy, pz = a0 * fz;
+            const float a_x_yp = a0 * R(8, s_yp) * R(4, s_yp) * R(5, site_of(x, yp, zm, L));
+            const float a_x_zp = a0 * R(8, s_zp) * R(4, s_zp) * R(9, site_of(x, ym, zp, L));
+            const float a_y_xp = a0 * R(10, s_xp) * R(0, s_xp) * R(1, site_of(xp, y, zm, L));
+            const float a_y_zp = a0 * R(10, s_zp) * R(0, s_zp) * R(11, site_of(xm, y, zp, L));
+            const float a_z_xp = a0 * R(6, s_xp) * R(2, s_xp) * R(3, site_of(xp, ym, z, L));
+            const float a_z_yp = a0 * R(6, s_yp) * R(2, s_yp) * R(7, site_of(xm, yp, z, L));
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                float a[4];
+                if (n == 2) {
+                    a[0] = px * o4; a[1] = a_x_yp; a[2] = py * o0; a[3] = a_y_xp;
+                } else if (n == 1) {
+                    a[0] = px * o8; a[1] = a_x_zp; a[2] = pz * o2; a[3] = a_z_xp;
+                } else {
+                    a[0] = py * o10; a[1] = a_y_zp; a[2] = pz * o6; a[3] = a_z_yp;
+                }
+                const float sK = sbit[k][n] ? -K : K;
+                check_rule(a, sK, &out[k][4 * n]);
+            }
+        }
+        __syncthreads();  // every read of the old state is done
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            if (xyz[k] < 0) continue;
+            const int v = t + k * kLdsThreads;
+#pragma unroll
+            for (int slot = 0; slot < 12; ++slot) m[slot * N + v] = out[k][slot];
+        }
+        __syncthreads();  // the new state is complete
+    }
+    // posterior and hard decision (E4), as k_bp_post
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        if (xyz[k] < 0) continue;
+        const int x = xyz[k] & 255, y = (xyz[k] >> 8) & 255, z = xyz[k] >> 16;
+        const int v = site_of(x, y, z, L);
+        const int s_xm = site_of(dec(x, L), y, z, L), s_ym = site_of(x, dec(y, L), z, L);
+        const int s_zm = site_of(x, y, dec(z, L), L);
+        float el[3];
+        el[0] = a0 * R(8, v) * R(4, v) * R(9, s_ym) * R(5, s_zm);
+        el[1] = a0 * R(10, v) * R(0, v) * R(11, s_xm) * R(1, s_zm);
+        el[2] = a0 * R(6, v) * R(2, v) * R(7, s_xm) * R(3, s_ym);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t e = (int64_t)c * N + v;
+            if (post)
+                post[(w * 3 * (int64_t)N + e) * 64 + bit] =
+                    0.69314718055994531f * __builtin_amdgcn_logf(el[c]);
+            if (el[c] < 1.0f) atomicOr((unsigned long long*)(corr + e * ld_c + w), 1ull << bit);
+        }
+    }
+}
+
 Src make_src(Geo g, const BpArgs& a, const float* nu) {
     Src S;
     S.nu = nu;
@@ -452,6 +568,45 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
             k_bp_iter<NU_LOAD, false, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, nu_out);
     }
     return after_launch(c);
+}
+
+bool bp_resident_ok(Geo g, const BpArgs& a) {
+    if (a.llr0 || g.N > kLdsMaxSites || a.nw <= 0 || a.nw > (int64_t)1 << 24) return false;
+    const char* e = getenv("TC3D_BP_RESIDENT");
+    return !(e && e[0] == '0');
+}
+
+namespace {
+template <int SPT>
+int launch_lds(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr, float* post) {
+    const size_t lds = (size_t)12 * g.N * sizeof(float);
+    static std::atomic<int> opted[64];  // 1: the LDS size is allowed on that device
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TC3D_EHIP;
+    if (opted[dev].load(std::memory_order_relaxed) == 0) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bp_lds<SPT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(12 * kLdsMaxSites * sizeof(float))) != hipSuccess)
+            return TC3D_EHIP;
+        opted[dev].store(1, std::memory_order_relaxed);
+    }
+    int rc = launch_clear(c, corr, 3 * (int64_t)g.N, a.nw);
+    if (rc) return rc;
+    rc = before_launch(c, TC3D_K_BP_ITER);
+    if (rc) return rc;
+    k_bp_lds<SPT><<<dim3((unsigned)(64 * a.nw)), dim3(kLdsThreads), lds, c.stream>>>(
+        a.syn.p, a.syn.ld, g.L, a.a0, a.b1, a.b1_inv, a.K, iters - 1, corr.p, corr.ld, post);
+    return after_launch(c);
+}
+}  // namespace
+
+int launch_bp_resident(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr,
+                       float* post) {
+    if (!bp_resident_ok(g, a) || iters < 1) return TC3D_EINVAL;
+    const int spt = (g.N + kLdsThreads - 1) / kLdsThreads;
+    if (spt == 1) return launch_lds<1>(c, g, a, iters, corr, post);
+    if (spt == 2) return launch_lds<2>(c, g, a, iters, corr, post);
+    return launch_lds<3>(c, g, a, iters, corr, post);
 }
 
 int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,

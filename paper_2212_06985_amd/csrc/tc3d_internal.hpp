@@ -110,6 +110,13 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 // post (may be null) = posterior floats.
 int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
                    float* post);
+// A whole decode (iters >= 1, scalar prior) with each shot's state in one
+// workgroup's LDS; bit-identical to the streaming kernels. Available when
+// bp_resident_ok: L^3 <= 3072 and no per-edge prior; the environment variable
+// TC3D_BP_RESIDENT=0 turns it off.
+bool bp_resident_ok(Geo g, const BpArgs& a);
+int launch_bp_resident(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr,
+                       float* post);
 
 // ------------------------------------------------ BP with meta-check factors
 // FP64 state [W][N][21][64] (e^msg: 12 check->qubit, 3 check->measurement,
