@@ -79,6 +79,16 @@ ALGO_BYTES = {
 # assembly + 4 layers); the class average launch carries the forward's FLOP
 # divided by its launches.
 CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
+# BP with each shot's state in LDS (lattices of at most 3072 sites, scalar
+# prior): FP32 operations of one site's three checks in one iteration, each
+# add, multiply, min, max or reciprocal counted once: per check 8 clamps,
+# 8 (a -+ 1), 14 products and 4 x (add, subtract, reciprocal, multiply) for
+# the outputs (46); per site 3 checks plus 30 products forming the incoming
+# e^mu. The posterior adds 12 products per site.
+RESIDENT_MAX_SITES = 3072
+RESIDENT_OPS_PER_SITE_ITER = 3 * 46 + 30
+RESIDENT_OPS_PER_SITE_POST = 12
+FP32_OPS_PEAK_TOPS = 157.3 / 2  # the 157.3 TFLOP/s FP32 vector peak counts an FMA as 2
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_long.npy")
 
@@ -92,6 +102,7 @@ def log(msg):
 KERNEL_SOURCES = {
     "bp_iter": ["tc3d_bp.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
     "bp_iter_prior": ["tc3d_bp.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
+    "bp_resident": ["tc3d_bp.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
     "cnn": ["tc3d_cnn.hip", "tc3d_device.hpp", "tc3d_internal.hpp"],
 }
 
@@ -315,7 +326,7 @@ def path_roofline(bp_iters, value, per_edge_prior=False):
 
 
 def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
-             per_edge_prior=False):
+             per_edge_prior=False, bp_iters=0):
     """Roofline of the dominant kernel class, from the HIP-event launch times.
     For the CNN class, `forwards` forward passes over `shots_padded` shots
     (whole 64-shot words) were timed. With a per-edge prior, the BP iterations
@@ -335,6 +346,22 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
                 "algo_flop_per_launch": flop, "algo_flop_per_unit": CNN_FLOP_PER_SITE,
                 "unit_of_work": "site-shot forward (passes of 5 launches)"}
+    shots = shots_padded if shots_padded else batch
+    n_batches = -(-shots // batch)
+    if (dom == "bp_iter" and not per_edge_prior and bp_iters >= 1
+            and n_sites <= RESIDENT_MAX_SITES):
+        # one launch decodes a batch with each shot's state in LDS: ALU-bound
+        per_site = RESIDENT_OPS_PER_SITE_ITER * (bp_iters - 1) + RESIDENT_OPS_PER_SITE_POST
+        ops = per_site * n_sites * shots / n_batches
+        achieved = ops / (avg_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_OPS_PEAK_TOPS,
+                "unit": "Tops/s (FP32, one per add/multiply/min/max/reciprocal)",
+                "frac": round(achieved / FP32_OPS_PEAK_TOPS, 4),
+                "traffic": stored_traffic("bp_resident", workload),
+                "kernel": "bp_resident (whole decode of a shot in one workgroup's LDS)",
+                "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
+                "algo_ops_per_launch": ops, "algo_ops_per_unit": per_site,
+                "unit_of_work": "site-shot decode"}
     per_unit, unit = ALGO_BYTES[dom]
     # counters are kept per kernel variant: the per-edge-prior BP iteration's
     # under the name bp_iter_prior
@@ -344,8 +371,6 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
         key = dom + "_prior"
     # a launch covers one batch of shots; with uneven batches (the last one of
     # a step may be smaller) the average launch carries shots / batches
-    shots = shots_padded if shots_padded else batch
-    n_batches = -(-shots // batch)
     units = n * shots / n_batches if unit == "edge-shot" else n * (shots // 64) / n_batches
     algo_bytes = per_unit * units
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
@@ -565,7 +590,8 @@ def main():
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
     roof = roofline(per_class, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
-                    shots_padded=64 * W, per_edge_prior=decoder == "cnn")
+                    shots_padded=64 * W, per_edge_prior=decoder == "cnn",
+                    bp_iters=main_cfg["bp"])
     # with the CNN prior, the conv launches' own (MFMA) roofline as well
     cnn_roof = None
     if decoder == "cnn" and per_class["cnn"]["launches"]:
@@ -585,7 +611,8 @@ def main():
                       "mean_residual_syndrome": resid2,
                       "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload,
                                            forwards=cycles * steps, shots_padded=64 * W,
-                                           per_edge_prior=other == "cnn"),
+                                           per_edge_prior=other == "cnn",
+                                           bp_iters=other_cfg["bp"]),
                       "kernel_ms": {k: round(v["ms"], 3) for k, v in pc2.items()}}
 
     cpu = None

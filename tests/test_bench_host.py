@@ -94,3 +94,20 @@ def test_path_roofline_model():
         36.0 * 6 + 6 / 8 + 4
     # without BP there is no HBM model
     assert bench.path_roofline(0, 1e10) is None
+
+
+def test_resident_bp_roofline_is_alu_bound():
+    # L = 12 (1728 sites, 5184 edges), 20 iterations, one launch of 2 ms per batch
+    pc = _cls(bp_iter={"ms": 2.0, "launches": 1})
+    r = bench.roofline(pc, 5184, 4096, 1728, "none", shots_padded=4096, bp_iters=20)
+    assert r["bound"] == "alu" and r["kernel"].startswith("bp_resident")
+    per_site = (3 * 46 + 30) * 19 + 12
+    assert r["algo_ops_per_unit"] == per_site
+    assert r["algo_ops_per_launch"] == per_site * 1728 * 4096
+    assert r["achieved"] == pytest.approx(per_site * 1728 * 4096 / 2e-3 / 1e12, abs=0.01)
+    assert r["peak"] == pytest.approx(157.3 / 2)
+    # larger lattices, or a per-edge prior, stream their messages through HBM
+    assert bench.roofline(pc, 3 * 4096, 4096, 4096, "none", shots_padded=4096,
+                          bp_iters=20)["bound"] == "hbm"
+    assert bench.roofline(pc, 5184, 4096, 1728, "none", shots_padded=4096, bp_iters=20,
+                          per_edge_prior=True)["bound"] == "hbm"
