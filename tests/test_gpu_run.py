@@ -130,7 +130,9 @@ def test_bp_pflip_run_matches_oracle(L, S, p, noisy):
     assert abs(f_g - f_o) <= 3 * sig + 1e-12
 
 
-def test_timed_run_counts_launches():
+@pytest.mark.parametrize("resident", ["0", "1"])
+def test_timed_run_counts_launches(resident, monkeypatch):
+    monkeypatch.setenv("TC3D_BP_RESIDENT", resident)
     L, S = 5, 128
     prm = tc.make_run_params(0.05, 0.05, 2, 7, 6, PFFPFF, n_shots=S, seed=3)
     m_a, _, e_a, t = gpu_run(L, prm, timed=True)
@@ -138,9 +140,13 @@ def test_timed_run_counts_launches():
     assert np.array_equal(e_a, e_b) and np.array_equal(m_a, m_b)
     d = t.as_dict()
     cycles = 3
-    assert d["bp_iter"]["launches"] == cycles * (7 - 2)
-    assert d["bp_first"]["launches"] == cycles
-    assert d["bp_post"]["launches"] == cycles
+    if resident == "1":  # one launch decodes each cycle's batch inside LDS
+        assert d["bp_iter"]["launches"] == cycles
+        assert d["bp_first"]["launches"] == 0 and d["bp_post"]["launches"] == 0
+    else:
+        assert d["bp_iter"]["launches"] == cycles * (7 - 2)
+        assert d["bp_first"]["launches"] == cycles
+        assert d["bp_post"]["launches"] == cycles
     assert d["sweep"]["launches"] == cycles * 6
     assert d["readout"]["launches"] == 1
     # class intervals are disjoint runs of launches inside the call's span
