@@ -111,3 +111,8 @@ def test_resident_bp_roofline_is_alu_bound():
                           bp_iters=20)["bound"] == "hbm"
     assert bench.roofline(pc, 5184, 4096, 1728, "none", shots_padded=4096, bp_iters=20,
                           per_edge_prior=True)["bound"] == "hbm"
+
+
+def test_path_roofline_is_none_for_a_resident_decode():
+    assert bench.path_roofline(20, 1e10, n_sites=1728) is None
+    assert bench.path_roofline(20, 1e10, n_sites=48 ** 3)["bytes_per_unit"] == 646.5
