@@ -753,6 +753,10 @@ int tc3d_run_jobs(const tc3d_job* jobs, int32_t n_jobs, void* ws, size_t ws_byte
     for (auto& e : js.ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return TC3D_EHIP;
     const hipStream_t head = graph ? js.s[0] : origin;
+    if (graph) {
+        const int prc = bp_resident_prepare();
+        if (prc) return prc;
+    }
     if (graph && hipStreamBeginCapture(head, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return TC3D_EHIP;
     int rc = TC3D_OK;

@@ -576,21 +576,31 @@ bool bp_resident_ok(Geo g, const BpArgs& a) {
     return !(e && e[0] == '0');
 }
 
+static std::atomic<int> g_lds_opted[64];  // 1: the kernels may use their LDS size there
+
+int bp_resident_prepare() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TC3D_EHIP;
+    if (g_lds_opted[dev].load(std::memory_order_relaxed)) return TC3D_OK;
+    const int bytes = (int)(12 * kLdsMaxSites * sizeof(float));
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bp_lds<1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bp_lds<2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bp_lds<3>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+        return TC3D_EHIP;
+    g_lds_opted[dev].store(1, std::memory_order_relaxed);
+    return TC3D_OK;
+}
+
 namespace {
 template <int SPT>
 int launch_lds(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr, float* post) {
     const size_t lds = (size_t)12 * g.N * sizeof(float);
-    static std::atomic<int> opted[64];  // 1: the LDS size is allowed on that device
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TC3D_EHIP;
-    if (opted[dev].load(std::memory_order_relaxed) == 0) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bp_lds<SPT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(12 * kLdsMaxSites * sizeof(float))) != hipSuccess)
-            return TC3D_EHIP;
-        opted[dev].store(1, std::memory_order_relaxed);
-    }
-    int rc = launch_clear(c, corr, 3 * (int64_t)g.N, a.nw);
+    int rc = bp_resident_prepare();
+    if (rc) return rc;
+    rc = launch_clear(c, corr, 3 * (int64_t)g.N, a.nw);
     if (rc) return rc;
     rc = before_launch(c, TC3D_K_BP_ITER);
     if (rc) return rc;

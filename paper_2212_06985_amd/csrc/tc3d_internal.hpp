@@ -115,6 +115,9 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 // bp_resident_ok: L^3 <= 3072 and no per-edge prior; the environment variable
 // TC3D_BP_RESIDENT=0 turns it off.
 bool bp_resident_ok(Geo g, const BpArgs& a);
+// Allows the resident kernels their LDS size on the current device (once per
+// device); called before a graph capture so that nothing of it runs inside one.
+int bp_resident_prepare();
 int launch_bp_resident(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr,
                        float* post);
 
