@@ -10,7 +10,10 @@ counters, so nothing but the seed is loaded.
 
 Prints one JSON line with the throughput in decoded qubit-cycles/s (one
 qubit-cycle = one edge x one cycle x one shot), the roofline of the dominant
-kernel, measured live with HIP events, and the oracle timed on the host.
+kernel, measured live with HIP events (HBM-bound for the streaming BP
+iteration; ALU-bound where a lattice of at most 3072 sites decodes each shot
+inside one workgroup's LDS), the whole path against the HBM peak, and the
+oracle timed on the host.
 
     python bench.py [--workload c5|c4|c3|c2|c1] [--decoder plain|cnn] [--steps K] [--warmup W]
 
