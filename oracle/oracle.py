@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("final_qubit_noise", ctypes.c_int32), ("bp_iters", ctypes.c_int32),
         ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
         ("seed", ctypes.c_uint64), ("subset_mask", ctypes.c_uint32),
-        ("bp_meta", ctypes.c_int32),
+        ("bp_meta", ctypes.c_int32), ("cycle0", ctypes.c_uint32),
     ]
 
 
@@ -328,12 +328,12 @@ _cnn_methods()
 
 def make_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, seed=1, p_dec=None,
                 q_dec=None, perfect_final=1, final_qubit_noise=1, subset_mask=0,
-                bp_meta=0) -> Params:
+                bp_meta=0, cycle0=0) -> Params:
     return Params(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                   q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                   perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                   bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
-                  subset_mask=subset_mask, bp_meta=bp_meta)
+                  subset_mask=subset_mask, bp_meta=bp_meta, cycle0=cycle0)
 
 
 def subset_class(j, m, cycle):

@@ -626,11 +626,13 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
         uint8_t* e = err + s * n;
         for (int32_t t = 0; t < cycles; ++t) {
             const int noisy = t < prm->noisy_cycles;
+            /* counters are keyed by the cycle of the whole experiment */
+            const uint32_t c = prm->cycle0 + (uint32_t)t;
             const double pt = (noisy || prm->final_qubit_noise) ? prm->p : 0.0;
             const double qt = noisy ? prm->q : 0.0;
-            tco_sample_noise(lat, e, 0, pt, prm->seed, (uint32_t)t, shot, 1);
+            tco_sample_noise(lat, e, 0, pt, prm->seed, c, shot, 1);
             tco_syndrome(lat, e, syn, 1, 0);
-            tco_sample_noise(lat, syn, 1, qt, prm->seed, (uint32_t)t, shot, 1);
+            tco_sample_noise(lat, syn, 1, qt, prm->seed, c, shot, 1);
             memset(corr, 0, n);
             if (prm->bp_iters > 0) {
                 if (prm->bp_meta)
@@ -646,11 +648,10 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
             for (int32_t k = 0; k < prm->n_sweeps; ++k) n_subset += (prm->subset_mask >> k) & 1u;
             for (int32_t k = 0, j = 0; k < prm->n_sweeps; ++k) {
                 if ((prm->subset_mask >> k) & 1u)
-                    tco_subset_pflip_sweep(lat, syn, corr, prm->seed, (uint32_t)t, (uint32_t)k,
-                                           shot, 1, tco_subset_class(j++, n_subset, (uint32_t)t));
+                    tco_subset_pflip_sweep(lat, syn, corr, prm->seed, c, (uint32_t)k, shot, 1,
+                                           tco_subset_class(j++, n_subset, c));
                 else if ((prm->pflip_mask >> k) & 1u)
-                    tco_pflip_sweep(lat, syn, corr, prm->seed, (uint32_t)t, (uint32_t)k, shot,
-                                    1);
+                    tco_pflip_sweep(lat, syn, corr, prm->seed, c, (uint32_t)k, shot, 1);
                 else
                     tco_flip_sweep(lat, syn, corr, 1);
             }

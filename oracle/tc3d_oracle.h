@@ -45,6 +45,11 @@ typedef struct {
     uint32_t subset_mask;     /* bit k set: sweep k is a subset p-flip sweep on
                                  the edge class tco_subset_class(j, m, t)        */
     int32_t bp_meta;          /* 1: BP with meta-check factors (tco_bp_meta_*)   */
+    uint32_t cycle0;          /* index of this call's first cycle: noise and
+                                 coins of its cycle t are those of cycle
+                                 cycle0 + t, so a run split at cycle k and
+                                 resumed from its residual with cycle0 = k
+                                 equals the unsplit run                         */
 } tco_params;
 
 tco_lattice* tco_lattice_new(int32_t L);
@@ -128,8 +133,9 @@ void tco_logical_check(const tco_lattice* lat, const uint8_t* err, int64_t n_sho
                        uint8_t* mask, int32_t* odd);
 
 /* Whole experiment for shots shot0 .. shot0+n_shots-1. err: [n_shots][n_edges]
- * residual error, in/out (zero for a fresh start). trace (NULL ok):
- * [cycles][n_shots][n_edges] residual after each cycle. */
+ * residual error, in/out (zero for a fresh start; the residual of an earlier
+ * call to resume it, with cycle0 set). trace (NULL ok):
+ * [cycles][n_shots][n_edges] residual after each cycle of this call. */
 void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot0,
                     int64_t n_shots, uint8_t* err, uint8_t* mask, int32_t* odd,
                     uint8_t* trace);

@@ -127,3 +127,145 @@ def test_logical_error_rate_grows_with_p():
         mask, _, _ = o.run_cycles(prm, 200)
         rates.append((mask != 0).mean())
     assert rates[0] < rates[1]
+
+
+# ----------------------------------------------------- checkpoint / resume
+@pytest.mark.parametrize("kind", ["flip", "pbp", "subset"])
+def test_resumed_run_equals_unsplit_run(kind):
+    """A run split after cycle k and resumed from its residual with cycle0 = k
+    equals the unsplit run: noise and coins are keyed by the experiment's cycle
+    index, so the residual and the next cycle index are the whole state."""
+    L, S = 4, 6
+    o = Oracle(L)
+    kw = dict(flip=dict(bp_iters=0, n_sweeps=5, pflip_mask=0b00100),
+              pbp=dict(bp_iters=5, n_sweeps=6, pflip_mask=0b001001),
+              subset=dict(bp_iters=0, n_sweeps=5, pflip_mask=0, subset_mask=0b00100))[kind]
+    full = make_params(0.06, 0.05, noisy_cycles=5, seed=9, **kw)
+    m_full, odd_full, e_full = o.run_cycles(full, S, shot0=64)
+    for k in (1, 3):
+        head = make_params(0.06, 0.05, noisy_cycles=k, perfect_final=0, seed=9, **kw)
+        _, _, e_k = o.run_cycles(head, S, shot0=64)
+        tail = make_params(0.06, 0.05, noisy_cycles=5 - k, seed=9, cycle0=k, **kw)
+        m, odd, e = o.run_cycles(tail, S, shot0=64, err=e_k.copy())
+        assert np.array_equal(e, e_full) and np.array_equal(m, m_full), k
+        assert np.array_equal(odd, odd_full)
+    # a resumed call that starts from the wrong cycle draws other noise
+    wrong = make_params(0.06, 0.05, noisy_cycles=4, seed=9, **kw)
+    _, _, e_1 = o.run_cycles(make_params(0.06, 0.05, noisy_cycles=1, perfect_final=0, seed=9,
+                                         **kw), S, shot0=64)
+    _, _, e_w = o.run_cycles(wrong, S, shot0=64, err=e_1.copy())
+    assert not np.array_equal(e_w, e_full)
+
+
+# ------------------------------------- planted errors through the whole cycle
+# With p = q = 0 a cycle adds no noise, so run_cycles decodes exactly the
+# planted error. The expected residuals below come from the paper's examples
+# and from the geometry of a vertex star, not from the oracle's stages.
+def star_edges(L, x, y, z):
+    """The six edges at vertex v as {(axis, sign): edge}: +a = e(v,a),
+    -a = e(v - unit(a), a)."""
+    from inputs import edge
+    out = {}
+    for a in range(3):
+        d = [0, 0, 0]
+        d[a] = -1
+        out[(a, +1)] = edge(L, x, y, z, a)
+        out[(a, -1)] = edge(L, x + d[0], y + d[1], z + d[2], a)
+    return out
+
+
+def star_automaton(L, v, A, schedule, coin):
+    """Parallel flip / p-flip sweeps on an error inside the star of v.
+
+    Each face at v holds exactly two star edges, one of each of two different
+    axes, and each pair of perpendicular star edges shares exactly one face;
+    every other edge touches at most one face at v. So for A inside the star,
+    the unsatisfied checks of a star edge e are the faces it shares with the
+    perpendicular star edges e' with [e' in A] != [e in A], other edges see at
+    most one unsatisfied check and never flip, and the sweeps stay inside the
+    star. schedule: 'P' or 'F' per sweep; coin(edge, sweep) -> 0/1."""
+    st = star_edges(L, *v)
+    A = set(A)
+    for k, kind in enumerate(schedule):
+        flips = set()
+        for (a, sg), e in st.items():
+            u = sum(1 for (b, _), f in st.items() if b != a and ((f in A) != (e in A)))
+            if u >= 3 or (kind == "P" and u == 2 and coin(e, k)):
+                flips.add(e)
+        A ^= flips
+    return A
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_planted_corner_half_star_through_one_pffpff_cycle(L):
+    """Section 3.2: the corner half-star (Fig. 3a) is stuck under flip (every
+    star edge has exactly 2 unsatisfied checks) and p-flip's coin flips decide
+    its fate. One P F F P F F cycle of run_cycles over 64 shots (64 coin
+    streams) ends on the residual the star automaton predicts for each shot;
+    some shots clear it (residual 0 or the whole star, a stabiliser) and some
+    keep a half-star."""
+    from oracle.oracle import coin
+    o = Oracle(L)
+    v = (1, 2, 1)
+    st = star_edges(L, *v)
+    A0 = {st[(0, 1)], st[(1, 1)], st[(2, 1)]}
+    S, shot0, seed = 64, 128, 5
+    err = np.zeros((S, o.n_edges), np.uint8)
+    err[:, sorted(A0)] = 1
+    prm = make_params(0.0, 0.0, noisy_cycles=1, bp_iters=0, n_sweeps=6, pflip_mask=0b001001,
+                      perfect_final=0, seed=seed)
+    _, _, res = o.run_cycles(prm, S, shot0=shot0, err=err)
+    outcomes = {"cleared": 0, "stuck": 0}
+    for s in range(S):
+        want = star_automaton(L, v, A0, "PFFPFF",
+                              lambda e, k: coin(seed, e, 0, k, shot0 + s))
+        assert set(np.flatnonzero(res[s])) == want, s
+        outcomes["cleared" if len(want) in (0, 6) else "stuck"] += 1
+    assert outcomes["cleared"] > 0 and outcomes["stuck"] > 0, outcomes
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_planted_errors_decoded_by_bp_inside_run_cycles(L):
+    """The BP family's cycle: BP (T = 20, p_dec = q_dec = 5%) then P F F P F F.
+    * the planar 2 x 2 error of Fig. 3b, which flip cannot correct, is
+      corrected by BP (Section 4.1), so the residual is zero;
+    * single qubit errors are corrected (the lowest-weight case);
+    * a logical X membrane has zero syndrome: nothing flips and the readout
+      reports its axis;
+    * the corner half-star: BP gives its six star edges one posterior (the
+      star's symmetry) and flips all or none, then the sweeps act as the star
+      automaton, so the residual is the automaton's, possibly times the star."""
+    from inputs import edge
+    from oracle.oracle import coin
+    o = Oracle(L)
+    cases = {
+        "planar": [edge(L, i, j, 0, 2) for i in (0, 1) for j in (0, 1)],
+        "single_x": [edge(L, 2, 1, 3, 0)],
+        "single_z": [edge(L, 0, 0, 0, 2)],
+        "membrane_y": geom.membrane(L, 1, 2),
+    }
+    S, seed = len(cases), 3
+    err = np.zeros((S, o.n_edges), np.uint8)
+    for s, sup in enumerate(cases.values()):
+        err[s, sup] = 1
+    prm = make_params(0.0, 0.0, noisy_cycles=1, bp_iters=20, n_sweeps=6, pflip_mask=0b001001,
+                      perfect_final=0, seed=seed, p_dec=0.05, q_dec=0.05)
+    mask, odd, res = o.run_cycles(prm, S, err=err)
+    for s, name in enumerate(cases):
+        if name == "membrane_y":
+            assert set(np.flatnonzero(res[s])) == set(cases[name])
+            assert mask[s] == 0b010 and odd[s, 1] == L * L
+        else:
+            assert res[s].sum() == 0 and mask[s] == 0, name
+    v = (2, 2, 2)
+    st = star_edges(L, *v)
+    A0 = {st[(0, 1)], st[(1, 1)], st[(2, 1)]}
+    S = 16
+    err = np.zeros((S, o.n_edges), np.uint8)
+    err[:, sorted(A0)] = 1
+    _, _, res = o.run_cycles(prm, S, err=err)
+    whole = set(st.values())
+    for s in range(S):
+        want = star_automaton(L, v, A0, "PFFPFF", lambda e, k: coin(seed, e, 0, k, s))
+        got = set(np.flatnonzero(res[s]))
+        assert got in (want, want ^ whole), s

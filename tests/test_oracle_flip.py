@@ -298,3 +298,92 @@ def test_L3_corners_and_u_shapes_defeat_iterated_parallel_flip():
             for _ in range(8):
                 o.flip_sweep(syn, corr)
             assert syn.sum() > 0
+
+
+def test_L3_weight_three_brute_force():
+    """All 85,320 weight-3 errors on L = 3 (81 qubits).
+    * Minimum weight: no error of weight 1 or 2 has the syndrome of a weight-3
+      error, so each is a minimum-weight error for its syndrome.
+    * Iterated parallel flip (Section 3.2) clears all of them but exactly 594,
+      and those are the stuck shapes the paper draws, plus the one family that
+      needs the torus to be 3 wide:
+        - 27 x 8 corner half-stars (three mutually perpendicular edges at a
+          vertex, Fig. 3a), every star edge tied at 2 of 4;
+        - 27 x 12 U-shapes (two opposite star edges and a third, Fig. 5),
+          which parallel flip swaps with their complement in the star;
+        - 54 strips of three parallel edges that close around the torus (3
+          axes x 2 directions x 9 positions), every edge tied like the planar
+          2 x 2 of Fig. 3b.
+      Every other error ends with zero syndrome and no logical error."""
+    L = 3
+    o = Oracle(L)
+    n = o.n_edges
+    combs = np.array(list(itertools.combinations(range(n), 3)), dtype=np.int64)
+    S = len(combs)
+    assert S == 85_320
+    err = np.zeros((S, n), np.uint8)
+    err[np.arange(S)[:, None], combs] = 1
+    syn = o.syndrome(err)
+    low = [bits([i], n) for i in range(n)]
+    low += [bits([i, j], n) for i, j in itertools.combinations(range(n), 2)]
+    low_keys = {s.tobytes() for s in o.syndrome(np.array(low))}
+    assert not any(s.tobytes() in low_keys for s in syn)
+    corr = np.zeros_like(err)
+    for _ in range(12):
+        o.flip_sweep(syn, corr)
+    stuck = syn.sum(axis=1) > 0
+    assert int(stuck.sum()) == 594
+    mask, _ = o.logical_check(err ^ corr)
+    assert not mask[~stuck].any()
+    # the stuck set, built from the shapes
+    expect = set()
+    for x, y, z in itertools.product(range(L), repeat=3):
+        st = geom.star(L, x, y, z)  # +x,-x,+y,-y,+z,-z
+        for c in itertools.combinations(range(6), 3):
+            expect.add(tuple(sorted(st[k] for k in c)))  # 8 corners + 12 U-shapes
+    assert len(expect) == 27 * 20
+    from inputs import edge
+    for a in range(3):
+        for b in range(3):
+            if b == a:
+                continue
+            c = 3 - a - b
+            for i, j in itertools.product(range(L), repeat=2):
+                strip = []
+                for t in range(L):
+                    p = [0, 0, 0]
+                    p[b], p[c] = t, i
+                    p[a] = j
+                    strip.append(edge(L, p[0], p[1], p[2], a))
+                expect.add(tuple(sorted(strip)))
+    assert len(expect) == 594
+    assert set(map(tuple, combs[stuck])) == expect
+
+
+def test_parallel_flip_can_raise_a_noisy_syndrome():
+    """The strict decrease of the syndrome weight holds for sequential flip
+    (one qubit at a time, change 4 - 2u <= -2) but not for the parallel sweep:
+    on syndromes with check-outcome errors (not closed loops) a sweep can
+    raise the weight, because qubits that share a check undo each other's
+    improvement there. Searched over seeded random syndromes of density 0.4
+    (sparser ones showed no rise); the largest rise found is reported. On
+    valid syndromes (closed loops, perfect measurements) no rise is asserted
+    either way: none is known, none is proved."""
+    L = 4
+    o = Oracle(L)
+    rises = []
+    for seed in range(40):
+        syn = random_bits(900 + seed, 64, o.n_faces, 0.4)
+        before = syn.sum(axis=1).astype(int)
+        corr = np.zeros((64, o.n_edges), np.uint8)
+        o.flip_sweep(syn, corr)
+        rises.append((syn.sum(axis=1).astype(int) - before).max())
+    print(f"largest rise of the syndrome weight in one parallel sweep: {max(rises)}")
+    assert max(rises) > 0
+    # closed-loop syndromes of random errors: report only
+    err = random_bits(77, 256, o.n_edges, 0.06)
+    syn = o.syndrome(err)
+    before = syn.sum(axis=1).astype(int)
+    corr = np.zeros_like(err)
+    o.flip_sweep(syn, corr)
+    print(f"valid syndromes: largest change {(syn.sum(axis=1).astype(int) - before).max()}")
