@@ -44,6 +44,7 @@ class Params(ctypes.Structure):
         ("n_sweeps", ctypes.c_int32), ("pflip_mask", ctypes.c_uint32),
         ("seed", ctypes.c_uint64), ("subset_mask", ctypes.c_uint32),
         ("bp_meta", ctypes.c_int32), ("cycle0", ctypes.c_uint32),
+        ("bp_warm", ctypes.c_int32), ("bp_damp", ctypes.c_double),
     ]
 
 
@@ -78,6 +79,7 @@ def lib():
             "tco_pflip_sweep_coins": (None, [vp, vp, vp, vp]),
             "tco_sequential_flip": (i64, [vp, vp, vp, i64]),
             "tco_bp_step": (None, [vp, vp, vp, f64, f64, vp, vp, vp]),
+            "tco_bp_step_damped": (None, [vp, vp, vp, f64, f64, f64, vp, vp, vp]),
             "tco_bp_decode": (None, [vp, vp, i64, vp, f64, f64, i32, vp, vp]),
             "tco_logical_check": (None, [vp, vp, i64, vp, vp]),
             "tco_run_cycles": (None, [vp, ctypes.POINTER(Params), u64, i64, vp, vp, vp, vp]),
@@ -214,6 +216,16 @@ class Oracle:
                           _p(post))
         return nu_out, post
 
+    def bp_step_damped(self, syn, p_dec, q_dec, damp, nu_in=None):
+        _chk(syn, np.uint8, (self.n_faces,))
+        if nu_in is not None:
+            _chk(nu_in, np.float64, (self.n_faces, 4))
+        nu_out = np.zeros((self.n_faces, 4), np.float64)
+        post = np.zeros(self.n_edges, np.float64)
+        lib().tco_bp_step_damped(self._h, _p(syn), None, p_dec, q_dec, damp, _p(nu_in),
+                                 _p(nu_out), _p(post))
+        return nu_out, post
+
     def bp_decode(self, syn, p_dec, q_dec, iters, llr0=None):
         _chk(syn, np.uint8)
         S = syn.size // self.n_faces
@@ -328,12 +340,13 @@ _cnn_methods()
 
 def make_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, seed=1, p_dec=None,
                 q_dec=None, perfect_final=1, final_qubit_noise=1, subset_mask=0,
-                bp_meta=0, cycle0=0) -> Params:
+                bp_meta=0, cycle0=0, bp_warm=0, bp_damp=0.0) -> Params:
     return Params(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                   q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                   perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                   bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
-                  subset_mask=subset_mask, bp_meta=bp_meta, cycle0=cycle0)
+                  subset_mask=subset_mask, bp_meta=bp_meta, cycle0=cycle0, bp_warm=bp_warm,
+                  bp_damp=bp_damp)
 
 
 def subset_class(j, m, cycle):

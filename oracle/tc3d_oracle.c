@@ -389,6 +389,28 @@ void tco_bp_step(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
     free(mu);
 }
 
+/* Damped flooding BP: the new factor-to-variable messages are mixed with the
+ * previous ones in the log domain, nu = (1 - g) nu_new + g nu_old. Section
+ * 4.1 runs BP undamped; damping is one of the things its implementation
+ * leaves open, tried here as a reading. */
+void tco_bp_step_damped(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
+                        double p_dec, double q_dec, double damp, const double* nu_in,
+                        double* nu_out, double* post) {
+    const int64_t n = lat->n_edges, m = lat->n_faces;
+    tco_bp_step(lat, syn, llr0, p_dec, q_dec, nu_in, nu_out, NULL);
+    for (int64_t j = 0; j < 4 * m; ++j)
+        nu_out[j] = (1.0 - damp) * nu_out[j] + damp * (nu_in ? nu_in[j] : 0.0);
+    if (post) {
+        const double l0s = log((1.0 - p_dec) / p_dec);
+        for (int64_t i = 0; i < n; ++i) {
+            double l = llr0 ? llr0[i] : l0s;
+            for (int j = 0; j < 4; ++j)
+                l += nu_out[4 * lat->edge_face[4 * i + j] + lat->edge_slot[4 * i + j]];
+            post[i] = l;
+        }
+    }
+}
+
 /* ------------------------------------------------- BP with meta-checks */
 
 /* Face slot j (0..5) of cube c (the unit cube at corner site c): the lower
@@ -621,6 +643,12 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
     uint8_t* syn = (uint8_t*)malloc(m);
     uint8_t* corr = (uint8_t*)malloc(n);
     uint8_t* cbp = (uint8_t*)malloc(n);
+    /* BP read as damped or warm-started: messages kept between iterations
+       and, warm, between cycles */
+    const int bp_ext = prm->bp_iters > 0 && !prm->bp_meta && (prm->bp_warm || prm->bp_damp > 0.0);
+    double* nu_a = bp_ext ? (double*)malloc(sizeof(double) * 4 * m) : NULL;
+    double* nu_b = bp_ext ? (double*)malloc(sizeof(double) * 4 * m) : NULL;
+    double* post = bp_ext ? (double*)malloc(sizeof(double) * n) : NULL;
     for (int64_t s = 0; s < n_shots; ++s) {
         const uint64_t shot = shot0 + (uint64_t)s;
         uint8_t* e = err + s * n;
@@ -634,7 +662,22 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
             tco_syndrome(lat, e, syn, 1, 0);
             tco_sample_noise(lat, syn, 1, qt, prm->seed, c, shot, 1);
             memset(corr, 0, n);
-            if (prm->bp_iters > 0) {
+            if (bp_ext) {
+                /* start: the previous cycle's final messages (warm), else the
+                   priors (nu_in NULL) */
+                const int warm = prm->bp_warm && t > 0;
+                for (int32_t it = 0; it < prm->bp_iters; ++it) {
+                    const double* in = (it == 0 && !warm) ? NULL : nu_a;
+                    tco_bp_step_damped(lat, syn, NULL, prm->p_dec, prm->q_dec, prm->bp_damp,
+                                       in, nu_b, it == prm->bp_iters - 1 ? post : NULL);
+                    double* tmp = nu_a;
+                    nu_a = nu_b;
+                    nu_b = tmp;
+                }
+                for (int64_t i = 0; i < n; ++i) cbp[i] = post[i] < 0.0;
+                for (int64_t i = 0; i < n; ++i) corr[i] = cbp[i];
+                tco_syndrome(lat, cbp, syn, 1, 1);
+            } else if (prm->bp_iters > 0) {
                 if (prm->bp_meta)
                     tco_bp_meta_decode(lat, syn, 1, prm->p_dec, prm->q_dec, prm->bp_iters, cbp,
                                        NULL);
@@ -663,6 +706,9 @@ void tco_run_cycles(const tco_lattice* lat, const tco_params* prm, uint64_t shot
     free(syn);
     free(corr);
     free(cbp);
+    free(nu_a);
+    free(nu_b);
+    free(post);
 }
 
 /* ---------------------------------------------------------------- CNN prior */

@@ -50,6 +50,14 @@ typedef struct {
                                  cycle0 + t, so a run split at cycle k and
                                  resumed from its residual with cycle0 = k
                                  equals the unsplit run                         */
+    int32_t bp_warm;          /* 1: BP of every cycle but a call's first starts
+                                 from the factor-to-variable messages the
+                                 previous cycle's BP ended with (0: from the
+                                 priors, the paper's BP)                       */
+    double bp_damp;           /* damping g in [0, 1): each iteration's new
+                                 messages become (1 - g) nu_new + g nu_old,
+                                 nu_old = 0 before a cold start's first
+                                 iteration (0: the paper's BP)                 */
 } tco_params;
 
 tco_lattice* tco_lattice_new(int32_t L);
@@ -106,6 +114,11 @@ int64_t tco_sequential_flip(const tco_lattice* lat, uint8_t* syn, uint8_t* corr,
 void tco_bp_step(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
                  double p_dec, double q_dec, const double* nu_in, double* nu_out,
                  double* post);
+/* tco_bp_step followed by damping: nu_out = (1 - damp) nu_out + damp nu_in
+ * (nu_in NULL counts as 0), and post from the damped messages. */
+void tco_bp_step_damped(const tco_lattice* lat, const uint8_t* syn, const double* llr0,
+                        double p_dec, double q_dec, double damp, const double* nu_in,
+                        double* nu_out, double* post);
 /* iters >= 1 BP iterations per shot; corr[s][i] = [posterior < 0]. post is
  * [n_shots][n_edges] or NULL; llr0 is [n_shots][n_edges] or NULL. */
 void tco_bp_decode(const tco_lattice* lat, const uint8_t* syn, int64_t n_shots,

@@ -277,3 +277,65 @@ def test_bp_commutes_with_reflections(axis):
         _, post = o.bp_decode(syn[None], 0.05, 0.05, T)
         _, post_r = o.bp_decode(syn_r[None], 0.05, 0.05, T)
         np.testing.assert_allclose(post_r[0][emap], post[0], rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------- readings: damped and warm BP
+def test_damped_step_reduces_to_the_plain_step():
+    L = 4
+    o = Oracle(L)
+    syn = random_bits(61, 1, o.n_faces, 0.2)[0]
+    nu = random_messages(62, 1, o.n_faces)[0]
+    a, pa = o.bp_step(syn, 0.05, 0.05, nu_in=nu)
+    b, pb = o.bp_step_damped(syn, 0.05, 0.05, 0.0, nu_in=nu)
+    assert np.array_equal(a, b) and np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("damp", [0.3, 0.7])
+def test_damped_zero_syndrome_scalar_recursion(damp):
+    """On the zero syndrome every message is one scalar, and damping mixes it
+    with the previous one: nu_t = (1 - g) F(nu_{t-1}) + g nu_{t-1}, nu_0 = 0,
+    F(nu) = 2 atanh(K tanh((l0 + 3 nu)/2)^3); posterior l0 + 4 nu_T."""
+    L, p, q, T = 4, 0.05, 0.05, 9
+    o = Oracle(L)
+    syn = np.zeros(o.n_faces, np.uint8)
+    l0 = math.log((1 - p) / p)
+    K = 1 - 2 * q
+    nu, post = None, None
+    s = 0.0
+    for _ in range(T):
+        nu, post = o.bp_step_damped(syn, p, q, damp, nu_in=nu)
+        s = (1 - damp) * 2 * math.atanh(K * math.tanh((l0 + 3 * s) / 2) ** 3) + damp * s
+        np.testing.assert_allclose(nu, s, rtol=1e-13)
+    np.testing.assert_allclose(post, l0 + 4 * s, rtol=1e-13)
+
+
+def test_warm_and_damped_runs():
+    """run_cycles with the readings: damping 0 and a cold start are the
+    paper's BP bit for bit; a warm start's first cycle is the cold one; its
+    later cycles start from the previous cycle's final messages (checked by
+    composing the damped step, the only BP in these runs)."""
+    from oracle.oracle import make_params
+    L, S = 4, 6
+    o = Oracle(L)
+    base = make_params(0.05, 0.05, 3, 6, 6, 0b001001, seed=13)
+    m0, _, e0 = o.run_cycles(base, S)
+    m1, _, e1 = o.run_cycles(make_params(0.05, 0.05, 3, 6, 6, 0b001001, seed=13, bp_damp=0.0),
+                             S)
+    assert np.array_equal(e0, e1) and np.array_equal(m0, m1)
+    warm = make_params(0.05, 0.05, 1, 6, 6, 0b001001, seed=13, bp_warm=1, perfect_final=0)
+    cold = make_params(0.05, 0.05, 1, 6, 6, 0b001001, seed=13, perfect_final=0)
+    assert np.array_equal(o.run_cycles(warm, S)[2], o.run_cycles(cold, S)[2])
+    # two warm cycles with damping by hand, one shot
+    prm = make_params(0.06, 0.05, 2, 5, 0, 0, seed=21, bp_warm=1, bp_damp=0.4,
+                      perfect_final=0)
+    _, _, e_run = o.run_cycles(prm, 1, shot0=3)
+    e = np.zeros((1, o.n_edges), np.uint8)
+    nu = None
+    for t in range(2):
+        o.sample_noise(e, 0, 0.06, 21, t, 3)
+        syn = o.syndrome(e)
+        o.sample_noise(syn, 1, 0.05, 21, t, 3)
+        for it in range(5):
+            nu, post = o.bp_step_damped(syn[0], 0.06, 0.05, 0.4, nu_in=nu)
+        e ^= (post < 0).astype(np.uint8)[None]
+    assert np.array_equal(e, e_run)
