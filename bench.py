@@ -38,9 +38,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # name -> workload. Shots per step x steps covers the configuration's shots.
 WORKLOADS = {
     # L = 48 (331,776 qubits), p = q = 0.05, 48 noisy cycles + 1 perfect,
-    # BP 20 iterations + P F F P F F, 2x10^4 shots (10 steps of 2048)
-    "c5": dict(L=48, ps=[0.05], noisy=48, bp=20, sweeps=6, mask=0b001001,
-               sched="PFFPFF", shots=2048, steps=10, warmup=1),
+    # BP 20 iterations + P F F P F F, 2x10^4 shots (10 steps of 2048), with and
+    # without the CNN prior: the comparison decodes the shots of the first
+    # compare_steps steps again with the CNN prior at its matched-throughput
+    # point (6 BP iterations, prior blended at 0.5)
+    "c5": dict(L=48, ps=[0.05], noisy=48, bp=20, cnn_bp=6, beta=0.5, sweeps=6, mask=0b001001,
+               sched="PFFPFF", shots=2048, steps=10, warmup=1, compare=True, compare_steps=5),
     # L = 12 (5,184 qubits), p = q in {0.04, 0.05, 0.055, 0.06}, 12 + 1 cycles,
     # BP 20 + P F F P F F, 10^5 shots per p (one step per p value)
     "c2": dict(L=12, ps=[0.04, 0.05, 0.055, 0.06], noisy=12, bp=20, sweeps=6, mask=0b001001,
@@ -59,7 +62,7 @@ WORKLOADS = {
     # L = 6 (648 qubits), p = q = 0.02, 6 + 1 cycles, flip + p-flip F F P F F,
     # no BP, 10^4 shots
     "c1": dict(L=6, ps=[0.02], noisy=6, bp=0, sweeps=5, mask=0b00100, sched="FFPFF",
-               shots=10_048, steps=10, warmup=2),
+               shots=10_048, steps=10, warmup=2, graph=True),
 }
 
 # algorithmic HBM bytes per launch unit of each kernel class:
@@ -83,15 +86,19 @@ ALGO_BYTES = {
 # divided by its launches.
 CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
 # BP with each shot's state in LDS (lattices of at most 3072 sites, scalar
-# prior): FP32 operations of one site's three checks in one iteration, each
-# add, multiply, min, max or reciprocal counted once: per check 8 clamps,
-# 8 (a -+ 1), 14 products and 4 x (add, subtract, reciprocal, multiply) for
-# the outputs (46); per site 3 checks plus 30 products forming the incoming
-# e^mu. The posterior adds 12 products per site.
+# prior) is bound by the vector ALU. Its algorithmic FP32 work per site and
+# iteration, in VALU issue slots of one lane: per check 8 clamps (min, max),
+# 8 (a -+ 1), 14 products and, for each of the 4 outputs, an add, a subtract,
+# a multiply (1 slot each) and a reciprocal (4 slots: transcendental ops run
+# at a quarter of the rate), 58 slots; per site 3 checks plus 30 products
+# forming the incoming e^mu. The posterior adds 12 products per site.
 RESIDENT_MAX_SITES = 3072
-RESIDENT_OPS_PER_SITE_ITER = 3 * 46 + 30
-RESIDENT_OPS_PER_SITE_POST = 12
-FP32_OPS_PEAK_TOPS = 157.3 / 2  # the 157.3 TFLOP/s FP32 vector peak counts an FMA as 2
+RESIDENT_SLOTS_PER_SITE_ITER = 3 * (8 + 8 + 14 + 4 * (3 + 4)) + 30
+RESIDENT_SLOTS_PER_SITE_POST = 12
+# one non-packed FP32 operation per lane per clock: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (the 157.3 TFLOP/s vector peak counts packed FMAs, 4 FLOP
+# per lane per clock, which this build does not use)
+VALU_SLOTS_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_long.npy")
 
@@ -155,22 +162,52 @@ def stored_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(cfg, target_s: float):
+def host_cpu():
+    """The host's CPU model, core count and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, allowed
+
+
+# worker threads of the oracle: the host cores this process may use, at most
+# 16 (a one-GPU share of the GPU hosts)
+CPU_SHARE = 16
+
+
+def cpu_baseline(cfg, target_s: float, tc=None):
     """The oracle, as it is, on a bounded sample of the same workload: a few
-    shots for the first cycle(s), one shot per thread."""
+    shots for the first cycle(s), one shot per thread. With the library given,
+    the GPU decodes the same sample and the shots that came out differently
+    are counted (FP32 against FP64 BP near a tie)."""
     import concurrent.futures as cf
+
+    import numpy as np
 
     from oracle.oracle import Oracle, make_params
 
-    cores = min(os.cpu_count() or 1, 16)
+    model, nproc, allowed = host_cpu()
+    cores = min(allowed, CPU_SHARE)
     o = Oracle(cfg["L"])
     n = 3 * cfg["L"] ** 3
     p = cfg["ps"][0]
 
+    def prm_of(cycles):
+        return make_params(p, p, cycles, cfg["bp"], cfg["sweeps"], cfg["mask"], seed=1,
+                           perfect_final=0)
+
     def one(shot, cycles):
-        prm = make_params(p, p, cycles, cfg["bp"], cfg["sweeps"], cfg["mask"], seed=1,
-                          perfect_final=0)
-        o.run_cycles(prm, 1, shot0=shot)
+        return o.run_cycles(prm_of(cycles), 1, shot0=shot)
 
     # calibrate on one shot-cycle, then size the sample to ~target_s of wall
     t0 = time.perf_counter()
@@ -180,17 +217,35 @@ def cpu_baseline(cfg, target_s: float):
     shots = cores
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(cores) as ex:
-        list(ex.map(lambda s: one(s, cycles), range(shots)))
+        res = list(ex.map(lambda s: one(s, cycles), range(shots)))
     wall = time.perf_counter() - t0
     qc = n * cycles * shots
-    return {
+    out = {
         "value": qc / wall,
         "unit": "qubit-cycles/s",
         "cores": cores,
         "kind": "oracle",
         "sample": f"{shots} shots x first {cycles} noisy cycle(s) of the workload, one shot "
                   f"per thread, {wall:.1f} s wall",
+        "host": {"cpu_model": model, "nproc": nproc, "cores_allowed": allowed,
+                 "threads_used": cores},
     }
+    if tc is not None:
+        import torch
+        lat = tc.make_lattice(cfg["L"])
+        prm = tc.make_run_params(p, p, cycles, cfg["bp"], cfg["sweeps"], cfg["mask"],
+                                 n_shots=shots, seed=1, perfect_final=0)
+        err = torch.zeros((lat.n_edges, tc.n_words(shots)), dtype=torch.int64, device="cuda")
+        mask = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+        ws = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
+        tc.run_cycles(lat, prm, err, mask, None, ws)
+        torch.cuda.synchronize()
+        w = err.cpu().numpy().view(np.uint64)
+        g = np.unpackbits(w.view(np.uint8).reshape(w.shape[0], -1), axis=1,
+                          bitorder="little")[:, :shots].T
+        same = sum(int(np.array_equal(g[s], r[2][0])) for s, r in enumerate(res))
+        out["parity_vs_gpu"] = {"shots": shots, "identical": same, "diverged": shots - same}
+    return out
 
 
 def copy_calibration(nbytes: int, reps: int):
@@ -225,19 +280,18 @@ def cnn_packed(p: float, beta: float, weights: str):
     import numpy as np
     import torch
 
-    import paper_2212_06985_amd as tc
-    from paper_2212_06985_amd.train_cnn import blend_prior
-    w = np.load(weights, allow_pickle=False)
-    d = torch.from_numpy(blend_prior(w, beta, p)).cuda()
-    packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
-    tc.cnn_pack(d, packed)
+    from paper_2212_06985_amd.train_cnn import packed_prior
+    packed = packed_prior(np.load(weights, allow_pickle=False), beta, p)
     torch.cuda.synchronize()
     return packed
 
 
-def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, weights, tag):
+def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, weights, tag,
+                graph=False):
     """Warm up, then time `steps` complete experiments of one decoder. Returns
-    the wall time of the timed steps, per-class kernel times and statistics."""
+    the wall time of the timed steps, per-class kernel times and statistics.
+    graph: every step is one HIP graph of all its launches (plain decoder);
+    the per-class kernel times then come from one more step run eagerly."""
     import torch
     W = tc.n_words(S)
     L = cfg["L"]
@@ -247,7 +301,7 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
         p = cfg["ps"][step % len(cfg["ps"])]
         return tc.make_run_params(p, p, cfg["noisy"], cfg["bp"], cfg["sweeps"], cfg["mask"],
                                   n_shots=S, seed=1, shot0=64 * W * step, batch_shots=batch,
-                                  bp_tile=bp_tile)
+                                  bp_tile=bp_tile, flags=tc.RUN_GRAPH if graph else 0)
 
     nps = len(cfg["ps"])
     packs = [cnn_packed(p, beta, weights) for p in cfg["ps"]] if cnn else [None] * nps
@@ -266,6 +320,13 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
         if cnn:
             f = tc.run_cycles_cnn_timed if timed else tc.run_cycles_cnn
             return f(lat, params(k), pk, err, mask, odd, ws)
+        if graph and timed:  # the graph's launches, without per-class events
+            tc.run_cycles(lat, params(k), err, mask, odd, ws)
+            return None
+        if graph:
+            prm = params(k)
+            prm.flags = 0
+            return tc.run_cycles_timed(lat, prm, err, mask, odd, ws)
         f = tc.run_cycles_timed if timed else tc.run_cycles
         return f(lat, params(k), err, mask, odd, ws)
 
@@ -275,31 +336,46 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
         log(f"[bench] {tag} warmup step {k} done")
 
     per_class = {k: {"ms": 0.0, "launches": 0} for k in tc.KERNEL_CLASSES}
+    decisions = near_ties = 0
     fails_x = fails_any = 0
     hist = [0] * 8  # mask histogram: bit d = logical X error on qubit d
     ties = 0        # majority-vote ties (an axis with exactly L^2/2 odd strings)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
+        t0k = time.perf_counter()
         t = one(k, True)
-        for name, v in t.as_dict().items():
-            per_class[name]["ms"] += v["ms"]
-            per_class[name]["launches"] += v["launches"]
+        if t is not None:
+            for name, v in t.as_dict().items():
+                per_class[name]["ms"] += v["ms"]
+                per_class[name]["launches"] += v["launches"]
+            decisions += t.bp_decisions
+            near_ties += t.bp_near_ties
         m = mask.cpu()
         fails_x += int((m & 1).ne(0).sum())
         fails_any += int(m.ne(0).sum())
         hb = torch.bincount(m.long(), minlength=8)
         hist = [h + int(v) for h, v in zip(hist, hb.tolist())]
         ties += int((2 * odd == L * L).any(dim=1).sum())
-        log(f"[bench] {tag} step {k}: {t.total_ms:.1f} ms")
+        log(f"[bench] {tag} step {k}: "
+            f"{t.total_ms if t is not None else (time.perf_counter() - t0k) * 1e3:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if graph:  # kernel times of one eager step (the same work)
+        t = one(0, False)
+        for name, v in t.as_dict().items():
+            per_class[name]["ms"] += v["ms"] * steps
+            per_class[name]["launches"] += v["launches"] * steps
     N = S * steps
     ler = {"axis_x": fails_x / N, "axis_x_sigma": (fails_x / N * (1 - fails_x / N) / N) ** 0.5,
            "any_axis": fails_any / N,
            "any_axis_sigma": (fails_any / N * (1 - fails_any / N) / N) ** 0.5, "shots": N,
            "mask_histogram": {format(k, "03b")[::-1]: hist[k] for k in range(8)},
-           "majority_ties": ties}
+           "majority_ties": ties,
+           # BP decisions whose posterior was within 1e-3 nats of 0, where FP32
+           # and the FP64 oracle may decide apart
+           "bp_near_ties": {"count": near_ties, "decisions": decisions,
+                            "fraction": near_ties / decisions if decisions else None}}
     # residual syndrome weight of the last step's final state (what the
     # decoder left behind; stabiliser-equivalent residue is invisible to it)
     syn = torch.zeros_like(err)
@@ -358,12 +434,12 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
     if (dom == "bp_iter" and not per_edge_prior and bp_iters >= 1
             and n_sites <= RESIDENT_MAX_SITES):
         # one launch decodes a batch with each shot's state in LDS: ALU-bound
-        per_site = RESIDENT_OPS_PER_SITE_ITER * (bp_iters - 1) + RESIDENT_OPS_PER_SITE_POST
+        per_site = RESIDENT_SLOTS_PER_SITE_ITER * (bp_iters - 1) + RESIDENT_SLOTS_PER_SITE_POST
         ops = per_site * n_sites * shots / n_batches
         achieved = ops / (avg_ms * 1e-3) / 1e12
-        return {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_OPS_PEAK_TOPS,
-                "unit": "Tops/s (FP32, one per add/multiply/min/max/reciprocal)",
-                "frac": round(achieved / FP32_OPS_PEAK_TOPS, 4),
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_SLOTS_PEAK_T, 2),
+                "unit": "T VALU slots/s (FP32 lane-ops; a reciprocal takes 4 slots)",
+                "frac": round(achieved / VALU_SLOTS_PEAK_T, 4),
                 "traffic": stored_traffic("bp_resident", workload),
                 "kernel": "bp_resident (whole decode of a shot in one workgroup's LDS)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
@@ -528,6 +604,8 @@ def main():
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=None,
+                    help="run each step as one HIP graph (default: the workload's)")
     ap.add_argument("--copy-calibrate", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter scaling)")
     args = ap.parse_args()
@@ -546,8 +624,9 @@ def main():
 
     import paper_2212_06985_amd as tc
 
-    if not os.path.exists(tc.LIB_PATH):
-        from paper_2212_06985_amd import build as hip_build
+    from paper_2212_06985_amd import build as hip_build
+    if tc.built_id() != hip_build.source_id():  # missing, or older than its sources
+        log("[bench] building libtc3d.so")
         hip_build.build()
 
     cfg = dict(WORKLOADS[args.workload])
@@ -558,7 +637,7 @@ def main():
         if not args.no_cpu_baseline:
             log("[bench] timing the oracle on the host")
             out["cpu_baseline"] = cpu_baseline(dict(cfg, L=12, ps=[0.055], noisy=12),
-                                               args.cpu_seconds)
+                                               args.cpu_seconds, tc)
         print(json.dumps(out), flush=True)
         return
     if args.L:
@@ -593,9 +672,11 @@ def main():
         return dict(cfg, bp=bp)
 
     main_cfg = cfg_for(decoder, True)
+    graph = cfg.get("graph", False) if args.graph is None else args.graph
+    graph = graph and decoder == "plain"
     wall, per_class, ler, resid = run_decoder(tc, lat, main_cfg, decoder, steps, warmup, S,
                                               batch, args.bp_tile, beta, args.weights,
-                                              "main")
+                                              "main", graph=graph)
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
     roof = roofline(per_class, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
@@ -612,14 +693,19 @@ def main():
     if compare:
         other = "plain" if decoder == "cnn" else "cnn"
         other_cfg = cfg_for(other, False)
-        w2, pc2, ler2, resid2 = run_decoder(tc, lat, other_cfg, other, steps, warmup, S, batch,
+        c_steps = min(steps, cfg.get("compare_steps", steps))
+        c_warm = min(warmup, 1)
+        w2, pc2, ler2, resid2 = run_decoder(tc, lat, other_cfg, other, c_steps, c_warm, S, batch,
                                             args.bp_tile, beta, args.weights, "compare")
-        comparison = {"decoder": other, "bp_iters": other_cfg["bp"],
-                      "value": qubit_cycles / w2, "unit": "qubit-cycles/s",
-                      "ms_per_step": w2 / steps * 1e3, "ler": ler2,
+        dec2 = "plain p-BP" if other == "plain" else f"CNN prior (beta={beta}) + p-BP"
+        comparison = {"decoder": dec2, "bp_iters": other_cfg["bp"], "steps": c_steps,
+                      "shots": S * c_steps, "same_shots_as_main": "the first "
+                      f"{S * c_steps} of the main run's {S * steps}",
+                      "value": n * cycles * S * c_steps / w2, "unit": "qubit-cycles/s",
+                      "ms_per_step": w2 / c_steps * 1e3, "ler": ler2,
                       "mean_residual_syndrome": resid2,
                       "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload,
-                                           forwards=cycles * steps, shots_padded=64 * W,
+                                           forwards=cycles * c_steps, shots_padded=64 * W,
                                            per_edge_prior=other == "cnn",
                                            bp_iters=other_cfg["bp"]),
                       "kernel_ms": {k: round(v["ms"], 3) for k, v in pc2.items()}}
@@ -627,7 +713,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
-        cpu = cpu_baseline(cfg, args.cpu_seconds)
+        cpu = cpu_baseline(cfg, args.cpu_seconds, tc)
 
     dec_name = "plain p-BP" if decoder == "plain" else f"CNN prior (beta={beta}) + p-BP"
     out = {
@@ -651,7 +737,7 @@ def main():
                                f"{' with the CNN prior' if decoder == 'cnn' else ''}",
                    "L": L, "shots_per_step": S, "batch_shots": batch, "shots_total": S * steps,
                    "cycles": cycles, "bp_iters": main_cfg["bp"], "schedule": cfg["sched"],
-                   "decoder": dec_name,
+                   "decoder": dec_name, "graph": graph,
                    "parallelism": "shots (bit-sliced 64 per word; one lane per shot in BP)"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -39,11 +39,15 @@
  * 256-byte aligned.
  *
  * Execution: every call is asynchronous on `stream` (a hipStream_t; NULL is
- * the default stream) except tc3d_run_cycles_timed, which blocks. Calls
- * return TC3D_OK, or a negative TC3D_E* code for invalid arguments or a failed
- * launch; faults during execution surface at the caller's next
- * synchronisation. No exception crosses the ABI. The library keeps no mutable
- * global state, so concurrent calls on different buffers are safe.
+ * the default stream) except tc3d_run_cycles_timed, tc3d_run_jobs and
+ * tc3d_autotune, which block. Calls return TC3D_OK, or a negative TC3D_E*
+ * code for invalid arguments or a failed launch; faults during execution
+ * surface at the caller's next synchronisation. No exception crosses the ABI.
+ *
+ * State: results depend only on the arguments. The library caches, per
+ * device, two facts it queries once (the LDS size of a compute unit, and
+ * that the LDS-resident BP kernels were granted their LDS size); neither
+ * changes a result. Concurrent calls on different buffers are safe.
  */
 #ifndef TC3D_H
 #define TC3D_H
@@ -92,6 +96,12 @@ int tc3d_sample_noise(const tc3d_lattice* lat, uint64_t* plane, int32_t kind, do
 int tc3d_syndrome(const tc3d_lattice* lat, const uint64_t* err, uint64_t* syn,
                   int64_t n_words, int32_t xor_into, void* stream);
 
+/* Apply a correction and carry the residual (Section 3.2: the accumulated
+ * correction is applied at the end of the cycle; Section 1: residual errors
+ * carry over): err ^= corr over two edge planes [3L^3][n_words]. */
+int tc3d_apply_correction(const tc3d_lattice* lat, uint64_t* err, const uint64_t* corr,
+                          int64_t n_words, void* stream);
+
 /* Scratch needed by one flip, p-flip or subset p-flip sweep: one edge plane. */
 size_t tc3d_sweep_workspace_bytes(const tc3d_lattice* lat, int64_t n_words);
 
@@ -137,14 +147,18 @@ size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
  *   post_out  posterior LLRs [W][3L^3][64], or NULL
  * 0 <= meas_factor < 1; |llr0_scalar| <= 40 (per-edge priors are clamped to
  * +-40 nats).
- * With the scalar prior on lattices of at most 3072 sites (L <= 14) the whole
- * decode of each shot runs inside one workgroup, its messages in LDS; the
- * result is bit-identical to the streaming kernels used otherwise, and the
- * environment variable TC3D_BP_RESIDENT=0 selects those. tc3d_run_cycles
- * decodes the same way. */
+ * bp_path picks the kernels; it never changes a result:
+ *   TC3D_BP_AUTO       the resident kernel where it applies, else streaming;
+ *   TC3D_BP_STREAMING  one launch per iteration over messages in HBM;
+ *   TC3D_BP_RESIDENT   the whole decode of each shot inside one workgroup,
+ *                      its messages in LDS: scalar prior and at most 3072
+ *                      sites (L <= 14), else EINVAL. Bit-identical to the
+ *                      streaming kernels. */
+enum { TC3D_BP_AUTO = 0, TC3D_BP_STREAMING = 1, TC3D_BP_RESIDENT = 2 };
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                    const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
-                   uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes, void* stream);
+                   int32_t bp_path, uint64_t* corr_out, float* post_out, void* ws,
+                   size_t ws_bytes, void* stream);
 
 /* One flooding BP iteration, for inspection and parity checks. The state is
  * the factor-to-variable messages in multiplicative form, e^nu (the form the
@@ -154,17 +168,13 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
  * member edge k for the 64 shots of word w. nu_in == NULL means the first
  * iteration (every variable-to-check message equals its prior). post_out
  * (NULL ok) receives the posterior LLR (nats) computed from nu_out,
- * [W][3L^3][64]. */
+ * [W][3L^3][64]. damp (0 <= damp < 1; scalar prior only) damps the new
+ * messages: nu = (1 - damp) nu_new + damp nu_in, nu_in NULL counting as 0
+ * (a reading of BP the paper leaves open; 0 is the paper's BP). */
 int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
-                 const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
-                 float* nu_out, float* post_out, void* stream);
+                 const float* llr0, float llr0_scalar, float meas_factor, float damp,
+                 const float* nu_in, float* nu_out, float* post_out, void* stream);
 
-/* Majority-vote readout (Section 3.1 and Fig. 2 caption): for each axis d,
- * count the L^2 disjoint logical Z strings along d (the L d-edges through
- * fixed other coordinates) whose error parity is odd; the shot has a logical
- * X error on qubit d when that count is at least L^2/2 (a tie counts as a
- * failure). mask_out[s] bit d records it; odd_out (NULL ok) is
- * [n_shots][3] int32 counts. err is an edge plane [3L^3][ceil(n_shots/64)]. */
 /* BP with meta-check factors: the extension of the factor graph that Section
  * 4.1 describes and leaves out, and that the closing discussion names as a
  * likely improvement. Each check has a measurement-error variable (prior
@@ -191,8 +201,17 @@ int tc3d_bp_meta_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_sh
                       double p_dec, double q_dec, const double* state_in, double* state_out,
                       double* post_out, void* stream);
 
+/* Majority-vote readout (Section 3.1 and Fig. 2 caption): for each axis d,
+ * count the L^2 disjoint logical Z strings along d (the L d-edges through
+ * fixed other coordinates) whose error parity is odd; the shot has a logical
+ * X error on qubit d when that count is at least L^2/2 (a tie counts as a
+ * failure). mask_out[s] bit d records it; odd_out (NULL ok) is
+ * [n_shots][3] int32 counts. err is an edge plane [3L^3][ceil(n_shots/64)].
+ * Scratch: the string parities, tc3d_logical_check_workspace_bytes. */
+size_t tc3d_logical_check_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
 int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_shots,
-                       uint8_t* mask_out, int32_t* odd_out, void* stream);
+                       uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
+                       void* stream);
 
 /* One Monte Carlo experiment. */
 typedef struct {
@@ -222,8 +241,31 @@ typedef struct {
                                   (j + t m) mod 12. Needs L even; 0 = none      */
     int32_t bp_meta;           /* 1: BP with meta-check factors
                                   (tc3d_bp_meta_decode) instead of the paper's */
+    uint32_t cycle0;           /* index of this call's first cycle (0 for a
+                                  fresh run): its cycle t draws the noise and
+                                  coins of cycle cycle0 + t, so a run split
+                                  after cycle k and resumed from its residual
+                                  err_state with cycle0 = k equals the unsplit
+                                  run bit for bit                             */
+    int32_t bp_path;           /* TC3D_BP_AUTO / _STREAMING / _RESIDENT (see
+                                  tc3d_bp_decode); never changes a result     */
+    int32_t bp_warm;           /* 1: BP of every cycle but the call's first
+                                  starts from the messages the previous
+                                  cycle's BP ended with, 0: from the priors
+                                  (the paper's BP); a reading the paper leaves
+                                  open. A resumed call starts cold.            */
+    double bp_damp;            /* damping 0 <= g < 1 of the BP messages:
+                                  nu = (1 - g) nu_new + g nu_old, nu_old = 0
+                                  before a cold start (0: the paper's BP);
+                                  streaming kernels, scalar prior            */
+    uint32_t flags;            /* TC3D_RUN_GRAPH: tc3d_run_cycles captures all
+                                  its launches into one HIP graph, launches it
+                                  and waits for it (for runs of many short
+                                  launches); never changes a result          */
     int32_t reserved;          /* zero                                           */
 } tc3d_run_params;
+
+enum { TC3D_RUN_GRAPH = 1 };
 
 size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);
 
@@ -235,7 +277,9 @@ size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* 
  * updates the working syndrome, then the flip / p-flip sweeps on the working
  * syndrome, then the accumulated correction is applied and the residual error
  * carries over. Finally the majority-vote readout of the residual.
- *   err_state  edge plane [3L^3][ceil(n_shots/64)], in/out (zero to start)
+ *   err_state  edge plane [3L^3][ceil(n_shots/64)], in/out (zero to start, or
+ *              the residual of an earlier call to continue it: checkpoint =
+ *              err_state + the next cycle index, passed as cycle0)
  *   mask_out   [n_shots] uint8, odd_out [n_shots][3] int32 or NULL
  * bp_iters > 0 needs 0 < p_dec < 0.5 and 0 < q_dec < 0.5. */
 int tc3d_run_cycles(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err_state,
@@ -260,12 +304,17 @@ typedef struct {
     double ms[TC3D_K_COUNT];        /* summed HIP-event durations per class */
     int64_t launches[TC3D_K_COUNT]; /* launches per class                   */
     double total_ms;                /* first to last event of the call      */
+    int64_t bp_decisions;           /* BP hard decisions made (edges x
+                                       padded shots x decoded cycles)      */
+    int64_t bp_near_ties;           /* of those, posteriors |l| < 1e-3 nats:
+                                       where FP32 and FP64 may decide apart */
 } tc3d_timing;
 
 /* tc3d_run_cycles with HIP events recorded on `stream` around every run of
  * consecutive launches of one kernel class (ms[k] then includes the short
- * gaps between the launches of a run; launches[k] counts every launch);
- * blocks until the work is done and fills *timing. */
+ * gaps between the launches of a run; launches[k] counts every launch) and
+ * with the near-tie count of the paper's BP (FP32 kernels; 0 for BP with
+ * meta-checks); blocks until the work is done and fills *timing. */
 int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
                           uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
                           size_t ws_bytes, void* stream, tc3d_timing* timing);
@@ -286,7 +335,12 @@ int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
  * (tc3d_cnn_packed_bytes(), made by tc3d_cnn_pack). */
 int64_t tc3d_cnn_param_count(void);
 size_t tc3d_cnn_packed_bytes(void);
-int tc3d_cnn_pack(const float* params, void* packed, void* stream);
+/* Packs params for the kernels with the prior blended with the channel prior
+ * l0 = ln((1-p)/p) at strength 0 <= beta <= 1: the packed network's prior is
+ * llr0 = l0 + beta (llr_cnn - l0) (its last layer's weights scale by beta,
+ * its biases become beta b - (1 - beta) l0). beta = 1 packs the network as
+ * it is (training uses that); beta = 0 gives the paper's prior. |l0| <= 40. */
+int tc3d_cnn_pack(const float* params, float beta, float l0, void* packed, void* stream);
 /* Scratch of one pass over n_shots shots (training != 0: forward + backward). */
 size_t tc3d_cnn_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots, int32_t training);
 /* llr_out [W][3L^3][64] = -z for the shots of the face planes syn and prev
@@ -375,6 +429,10 @@ int tc3d_stream_copy(void* dst, const void* src, int64_t n_bytes, int32_t nontem
 
 /* Human-readable text of a return code. */
 const char* tc3d_strerror(int code);
+
+/* SHA-256 (hex) of the sources the library was built from, so that a caller
+ * can refuse a library older than its sources. */
+const char* tc3d_build_id(void);
 
 #ifdef __cplusplus
 }

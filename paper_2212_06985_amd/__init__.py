@@ -21,6 +21,8 @@ __all__ = [
     "bp_meta_workspace_bytes", "bp_meta_decode", "bp_meta_step", "bp_workspace_bytes",
     "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
     "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
+    "logical_check_workspace_bytes", "built_id", "BP_AUTO", "BP_STREAMING", "BP_RESIDENT",
+    "apply_correction", "RUN_GRAPH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtc3d.so")
@@ -49,13 +51,16 @@ class RunParams(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("shot0", ctypes.c_uint64),
         ("n_shots", ctypes.c_int64), ("batch_shots", ctypes.c_int64),
         ("bp_tile", ctypes.c_int32), ("subset_mask", ctypes.c_uint32),
-        ("bp_meta", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bp_meta", ctypes.c_int32), ("cycle0", ctypes.c_uint32),
+        ("bp_path", ctypes.c_int32), ("bp_warm", ctypes.c_int32),
+        ("bp_damp", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
     ]
 
 
 class Timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("bp_decisions", ctypes.c_int64),
+                ("bp_near_ties", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: {"ms": self.ms[i], "launches": int(self.launches[i])}
@@ -70,23 +75,48 @@ class Job(ctypes.Structure):
 
 
 class TuneChoice(ctypes.Structure):
-    _fields_ = [("bp_tile", ctypes.c_int32), ("subset_mask", ctypes.c_uint32),
+    _fields_ = [("bp_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("batch_shots", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 JOBS_CONCURRENT = 1
 JOBS_GRAPH = 2
 
+# run flags: capture a run's launches into one HIP graph (tc3d_run_cycles blocks)
+RUN_GRAPH = 1
+
+# kernels of a BP decode (tc3d_bp_decode's bp_path; never changes a result)
+BP_AUTO = 0
+BP_STREAMING = 1
+BP_RESIDENT = 2
+
 _lib = None
 
 
+def built_id():
+    """The source hash libtc3d.so was built with, or None when it is missing."""
+    if not os.path.exists(LIB_PATH):
+        return None
+    L = ctypes.CDLL(LIB_PATH)
+    L.tc3d_build_id.restype = ctypes.c_char_p
+    L.tc3d_build_id.argtypes = []
+    return L.tc3d_build_id().decode()
+
+
 def lib():
-    """Load libtc3d.so; fail loudly when it has not been built."""
+    """Load libtc3d.so; fail loudly when it has not been built, or was built
+    from other sources than the ones in the tree."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2212_06985_amd.build`")
+    from . import build as _build
+    have, want = built_id(), _build.source_id()
+    if have != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources ({have[:12]}, the tree "
+                          f"is {want[:12]}): rebuild it with "
                           "`python -m paper_2212_06985_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, u32, i64, u64, f32, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
@@ -103,9 +133,11 @@ def lib():
         "tc3d_subset_pflip_sweep": (ctypes.c_int, [lat, vp, vp, i64, u64, u32, u32, u64, i32,
                                                    vp, sz, vp]),
         "tc3d_bp_workspace_bytes": (sz, [lat, i64]),
-        "tc3d_bp_decode": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, i32, vp, vp, vp, sz, vp]),
-        "tc3d_bp_step": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, vp, vp, vp, vp]),
-        "tc3d_logical_check": (ctypes.c_int, [lat, vp, i64, vp, vp, vp]),
+        "tc3d_bp_decode": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp, sz,
+                                          vp]),
+        "tc3d_bp_step": (ctypes.c_int, [lat, vp, i64, vp, f32, f32, f32, vp, vp, vp, vp]),
+        "tc3d_logical_check_workspace_bytes": (sz, [lat, i64]),
+        "tc3d_logical_check": (ctypes.c_int, [lat, vp, i64, vp, vp, vp, sz, vp]),
         "tc3d_bp_meta_workspace_bytes": (sz, [lat, i64]),
         "tc3d_bp_meta_decode": (ctypes.c_int, [lat, vp, i64, f64, f64, i32, vp, vp, vp, sz, vp]),
         "tc3d_bp_meta_step": (ctypes.c_int, [lat, vp, i64, f64, f64, vp, vp, vp, vp]),
@@ -114,9 +146,11 @@ def lib():
         "tc3d_run_cycles_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp,
                                                  ctypes.POINTER(Timing)]),
         "tc3d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "tc3d_build_id": (ctypes.c_char_p, []),
         "tc3d_cnn_param_count": (i64, []),
         "tc3d_cnn_packed_bytes": (sz, []),
-        "tc3d_cnn_pack": (ctypes.c_int, [vp, vp, vp]),
+        "tc3d_cnn_pack": (ctypes.c_int, [vp, f32, f32, vp, vp]),
+        "tc3d_apply_correction": (ctypes.c_int, [lat, vp, vp, i64, vp]),
         "tc3d_cnn_workspace_bytes": (sz, [lat, i64, i32]),
         "tc3d_cnn_forward": (ctypes.c_int, [lat, vp, vp, i64, vp, vp, vp, sz, vp]),
         "tc3d_cnn_loss_grad": (ctypes.c_int, [lat, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]),
@@ -193,6 +227,12 @@ def syndrome(lat, err, syn, nw, xor_into=False, stream=None):
                                1 if xor_into else 0, _stream(stream)), "syndrome")
 
 
+def apply_correction(lat, err, corr, nw, stream=None):
+    """err ^= corr (apply a cycle's correction, carry the residual)."""
+    _check(lib().tc3d_apply_correction(ctypes.byref(lat), _ptr(err), _ptr(corr), int(nw),
+                                       _stream(stream)), "apply_correction")
+
+
 def sweep_workspace_bytes(lat, nw) -> int:
     return int(lib().tc3d_sweep_workspace_bytes(ctypes.byref(lat), int(nw)))
 
@@ -223,18 +263,18 @@ def bp_workspace_bytes(lat, n_shots) -> int:
 
 
 def bp_decode(lat, syn, n_shots, llr0, llr0_scalar, meas_factor, iters, corr_out, post_out, ws,
-              stream=None):
+              stream=None, path=BP_AUTO):
     _check(lib().tc3d_bp_decode(ctypes.byref(lat), _ptr(syn), int(n_shots), _ptr(llr0),
-                                float(llr0_scalar), float(meas_factor), int(iters),
+                                float(llr0_scalar), float(meas_factor), int(iters), int(path),
                                 _ptr(corr_out), _ptr(post_out), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream)), "bp_decode")
 
 
 def bp_step(lat, syn, n_shots, llr0, llr0_scalar, meas_factor, nu_in, nu_out, post_out=None,
-            stream=None):
+            stream=None, damp=0.0):
     _check(lib().tc3d_bp_step(ctypes.byref(lat), _ptr(syn), int(n_shots), _ptr(llr0),
-                              float(llr0_scalar), float(meas_factor), _ptr(nu_in), _ptr(nu_out),
-                              _ptr(post_out), _stream(stream)), "bp_step")
+                              float(llr0_scalar), float(meas_factor), float(damp), _ptr(nu_in),
+                              _ptr(nu_out), _ptr(post_out), _stream(stream)), "bp_step")
 
 
 def bp_meta_workspace_bytes(lat, n_shots) -> int:
@@ -254,9 +294,16 @@ def bp_meta_step(lat, syn, n_shots, p_dec, q_dec, state_in, state_out, post_out,
                                    _ptr(post_out), _stream(stream)), "bp_meta_step")
 
 
-def logical_check(lat, err, n_shots, mask_out, odd_out=None, stream=None):
+def logical_check_workspace_bytes(lat, n_shots) -> int:
+    return int(lib().tc3d_logical_check_workspace_bytes(ctypes.byref(lat), int(n_shots)))
+
+
+def logical_check(lat, err, n_shots, mask_out, odd_out=None, ws=None, stream=None):
+    if ws is None:
+        ws = alloc_workspace(logical_check_workspace_bytes(lat, n_shots))
     _check(lib().tc3d_logical_check(ctypes.byref(lat), _ptr(err), int(n_shots), _ptr(mask_out),
-                                    _ptr(odd_out), _stream(stream)), "logical_check")
+                                    _ptr(odd_out), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _stream(stream)), "logical_check")
 
 
 def run_workspace_bytes(lat, prm: RunParams) -> int:
@@ -291,8 +338,15 @@ def cnn_packed_bytes() -> int:
     return int(lib().tc3d_cnn_packed_bytes())
 
 
-def cnn_pack(params, packed, stream=None):
-    _check(lib().tc3d_cnn_pack(_ptr(params), _ptr(packed), _stream(stream)), "cnn_pack")
+def cnn_pack(params, packed, beta=1.0, p=None, stream=None):
+    """Packs the network; with beta < 1 its prior is blended with the channel
+    prior of error rate p: llr0 = l0 + beta (llr_cnn - l0)."""
+    import math
+    l0 = 0.0 if p is None else math.log((1 - p) / p)
+    if beta != 1.0 and p is None:
+        raise ValueError("cnn_pack: blending needs the channel error rate p")
+    _check(lib().tc3d_cnn_pack(_ptr(params), float(beta), float(l0), _ptr(packed),
+                               _stream(stream)), "cnn_pack")
 
 
 def cnn_workspace_bytes(lat, n_shots, training=False) -> int:
@@ -354,13 +408,16 @@ __all__ += ["cnn_param_count", "cnn_packed_bytes", "cnn_pack", "cnn_workspace_by
 
 def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,
                     shot0=0, p_dec=None, q_dec=None, perfect_final=1, final_qubit_noise=1,
-                    batch_shots=0, bp_tile=0, subset_mask=0, bp_meta=0) -> RunParams:
+                    batch_shots=0, bp_tile=0, subset_mask=0, bp_meta=0, cycle0=0,
+                    bp_path=BP_AUTO, bp_warm=0, bp_damp=0.0, flags=0) -> RunParams:
     return RunParams(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                      q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                      perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
                      bp_iters=bp_iters, n_sweeps=n_sweeps, pflip_mask=pflip_mask, seed=seed,
                      shot0=shot0, n_shots=n_shots, batch_shots=batch_shots, bp_tile=bp_tile,
-                     subset_mask=subset_mask, bp_meta=int(bp_meta))
+                     subset_mask=subset_mask, bp_meta=int(bp_meta), cycle0=int(cycle0),
+                     bp_path=int(bp_path), bp_warm=int(bp_warm), bp_damp=float(bp_damp),
+                     flags=int(flags))
 
 
 __all__.append("make_run_params")

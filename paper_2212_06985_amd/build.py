@@ -5,6 +5,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -34,11 +35,31 @@ def hipcc() -> str:
     return exe
 
 
+def source_files() -> list:
+    """Every file the library is built from, in a fixed order."""
+    return (sorted(glob.glob(os.path.join(CSRC, "*.hip"))) +
+            sorted(glob.glob(os.path.join(CSRC, "*.hpp"))) +
+            [os.path.join(ROOT, "include", "tc3d.h")])
+
+
+def source_id() -> str:
+    """SHA-256 over the sources' names and contents; the library returns the
+    value it was built with from tc3d_build_id()."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.relpath(f, ROOT).encode())
+        h.update(b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o",
-           tmp]
+    cmd = [hipcc(), *HIP_FLAGS, f'-DTC3D_BUILD_ID="{source_id()}"', "-I",
+           os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -140,19 +140,36 @@ size_t nu_bytes(const tc3d_lattice* lat, int64_t n_shots) {
 // (-1)^s * nu1 for every check, so they are not stored: the second iteration
 // reads them straight from the syndrome.
 int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, float* buf1,
-           Plane corr, float* post) {
+           Plane corr, float* post, const float* warm = nullptr,
+           const float** final_state = nullptr) {
     int rc;
     // a whole decode keeps its state to itself, so per-edge priors can be
     // folded into it (the one-step entry point keeps the plain state)
     BpArgs a = args;
     a.fold = a.llr0 != nullptr;
+    if (c.stats) {
+        a.ties = c.stats->d_ties;
+        c.stats->decisions += 3 * (int64_t)g.N * a.s_pad;
+    }
+    if (final_state) *final_state = nullptr;
     // small lattices: the whole decode of a shot inside one workgroup's LDS
-    if (iters >= 1 && bp_resident_ok(g, a)) return launch_bp_resident(c, g, a, iters, corr, post);
+    if (a.path == TC3D_BP_RESIDENT && (!bp_resident_fits(g, a.llr0, a.nw) || warm || final_state))
+        return TC3D_EINVAL;
+    if (iters >= 1 && !warm && !final_state && bp_resident_used(g, a))
+        return launch_bp_resident(c, g, a, iters, corr, post);
     int mode;
     const float* cur = nullptr;
     float* bufs[2] = {buf0, buf1};
     int nb = 0;
-    if (!a.llr0) {
+    int32_t first = 2;  // the first iteration launched
+    if (warm) {
+        // every iteration reads stored messages, the first those the previous
+        // cycle ended with
+        cur = warm;
+        nb = warm == buf0 ? 1 : 0;
+        mode = NU_LOAD;
+        first = 1;
+    } else if (!a.llr0) {
         mode = NU_SIGMA;
     } else {
         rc = launch_bp_iter(c, g, a, NU_ZERO, nullptr, bufs[nb], TC3D_K_BP_FIRST);
@@ -161,7 +178,7 @@ int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, 
         nb ^= 1;
         mode = NU_LOAD;
     }
-    for (int32_t it = 2; it <= iters; ++it) {
+    for (int32_t it = first; it <= iters; ++it) {
         rc = launch_bp_iter(c, g, a, mode, cur, bufs[nb],
                             mode == NU_SIGMA ? TC3D_K_BP_FIRST : TC3D_K_BP_ITER);
         if (rc) return rc;
@@ -169,6 +186,7 @@ int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, 
         nb ^= 1;
         mode = NU_LOAD;
     }
+    if (final_state) *final_state = mode == NU_LOAD ? cur : nullptr;
     return launch_bp_post(c, g, a, mode, cur, corr, post);
 }
 
@@ -176,14 +194,16 @@ bool prob_ok(double p) { return p >= 0.0 && p <= 1.0; }
 
 }  // namespace
 
-BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw, int tile) {
+BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw, int tile,
+                    int path, float damp) {
     BpArgs a;
     a.syn = syn;
     a.llr0 = llr0;
     a.l0 = l0;
     a.K = K;
     const double t = tanh(0.5 * (double)l0);
-    const double nu1 = 2.0 * atanh((double)K * t * t * t);
+    // the first iteration's messages (from the priors), damped towards 0
+    const double nu1 = (1.0 - (double)damp) * 2.0 * atanh((double)K * t * t * t);
     a.a0 = (float)exp((double)l0);
     a.b1 = (float)exp(nu1);
     a.b1_inv = (float)exp(-nu1);
@@ -191,6 +211,9 @@ BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw
     a.s_pad = 64 * nw;
     a.tile = tile;
     a.fold = false;
+    a.path = path;
+    a.ties = nullptr;
+    a.damp = damp;
     return a;
 }
 
@@ -205,7 +228,17 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
         return TC3D_EINVAL;
     if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
     if (prm->bp_meta != 0 && prm->bp_meta != 1) return TC3D_EINVAL;
-    if (prm->reserved != 0) return TC3D_EINVAL;
+    if (prm->bp_path < TC3D_BP_AUTO || prm->bp_path > TC3D_BP_RESIDENT) return TC3D_EINVAL;
+    if (prm->bp_warm != 0 && prm->bp_warm != 1) return TC3D_EINVAL;
+    if (!(prm->bp_damp >= 0.0 && prm->bp_damp < 1.0)) return TC3D_EINVAL;
+    // the readings of BP as damped or warm-started apply to the paper's BP
+    if ((prm->bp_warm || prm->bp_damp > 0.0) && prm->bp_meta) return TC3D_EINVAL;
+    // a warm start continues from stored messages, which one iteration never writes
+    if (prm->bp_warm && prm->bp_iters == 1) return TC3D_EINVAL;
+    if ((prm->flags & ~(uint32_t)TC3D_RUN_GRAPH) != 0 || prm->reserved != 0) return TC3D_EINVAL;
+    // cycle indices of this call stay below 2^32
+    if ((uint64_t)prm->cycle0 + (uint64_t)prm->noisy_cycles + 1 > 0xffffffffull)
+        return TC3D_EINVAL;
     // subset sweeps: within the schedule, and an edge colouring needs L even
     if (prm->subset_mask != 0 &&
         ((prm->n_sweeps < 32 && (prm->subset_mask >> prm->n_sweeps) != 0) || lat->L % 2 != 0))
@@ -229,6 +262,19 @@ size_t llr_bytes(const tc3d_lattice* lat, int64_t nw) {
     return round_up((size_t)nw * 64 * (size_t)lat->n_edges * 4, 256);
 }
 
+// The paper's BP decoded by the resident kernel keeps its messages in LDS
+// and needs no BP state in the workspace.
+bool run_bp_resident(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cnn) {
+    return prm->bp_iters > 0 && !prm->bp_meta && !cnn && prm->bp_path != TC3D_BP_STREAMING &&
+           !prm->bp_warm && prm->bp_damp == 0.0 && bp_resident_fits(geo_of(lat), nullptr, 1);
+}
+
+// BP state buffers of a batch of nw words (two, or none).
+size_t run_bp_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t nw, bool cnn) {
+    if (prm->bp_iters <= 0 || run_bp_resident(lat, prm, cnn)) return 0;
+    return 2 * bp_state_bytes(lat, prm, nw);
+}
+
 // Words decoded together. With the CNN prior a batch also holds the CNN's
 // activations and its rows (64 words N) must stay below 2^31.
 int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cnn) {
@@ -238,8 +284,7 @@ int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cn
     if (prm->batch_shots > 0) {
         nb = std::min<int64_t>(W, prm->batch_shots / 64);
     } else {
-        size_t per_word = (cnn ? 4 : 3) * plane_bytes(lat, 1) +
-                          (prm->bp_iters > 0 ? 2 * bp_state_bytes(lat, prm, 1) : 0);
+        size_t per_word = (cnn ? 4 : 3) * plane_bytes(lat, 1) + run_bp_bytes(lat, prm, 1, cnn);
         if (cnn) per_word += llr_bytes(lat, 1) + cnn_workspace_bytes(64 * lat->n_sites, 0);
         const size_t budget = (size_t)24 << 30;
         nb = std::max<int64_t>(1, std::min<int64_t>(W, (int64_t)(budget / per_word)));
@@ -248,17 +293,20 @@ int64_t batch_words(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cn
     return nb;
 }
 
+// The last 256 bytes of a run's workspace hold its counters (timed runs).
+constexpr size_t kCounterBytes = 256;
+
 size_t run_ws_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm, int64_t* nb_out,
                     bool cnn) {
     const int64_t nb = batch_words(lat, prm, cnn);
     if (nb_out) *nb_out = nb;
-    if (nb == 0) return 256;
-    size_t b = 3 * plane_bytes(lat, nb);  // syn, corr, flips
-    if (prm->bp_iters > 0) b += 2 * bp_state_bytes(lat, prm, nb);
+    if (nb == 0) return kCounterBytes;
+    size_t b = 3 * plane_bytes(lat, nb);  // syn, corr, flips (also the readout's scratch)
+    b += run_bp_bytes(lat, prm, nb, cnn);
     if (cnn)  // previous working syndrome, priors, CNN activations
         b += plane_bytes(lat, nb) + llr_bytes(lat, nb) +
              round_up(cnn_workspace_bytes(64 * nb * lat->n_sites, 0), 256);
-    return b;
+    return b + kCounterBytes;
 }
 
 // packed == nullptr: the paper's BP prior; else the CNN prior every cycle.
@@ -269,7 +317,12 @@ int run_validate(const tc3d_lattice* lat, const tc3d_run_params* prm, const void
     int rc = check_run(lat, prm);
     if (rc) return rc;
     const bool cnn = packed != nullptr;
-    if (cnn && (prm->bp_iters <= 0 || prm->bp_meta)) return TC3D_EINVAL;
+    // the CNN prior changes every cycle (and is folded into the messages), so
+    // it takes neither reading
+    if (cnn && (prm->bp_iters <= 0 || prm->bp_meta || prm->bp_damp > 0.0 || prm->bp_warm))
+        return TC3D_EINVAL;
+    if (prm->bp_path == TC3D_BP_RESIDENT && prm->bp_iters > 0 && !run_bp_resident(lat, prm, cnn))
+        return TC3D_EINVAL;
     if (prm->n_shots == 0) return TC3D_OK;
     if (!err || !mask) return TC3D_EINVAL;
     if (!aligned(err, 8) || (odd && !aligned(odd, 4)) || (cnn && !aligned(packed, 256)))
@@ -288,7 +341,7 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
     if (prm->n_shots == 0) return TC3D_OK;
     const bool cnn = packed != nullptr;
     int64_t nb = 0;
-    (void)run_ws_bytes(lat, prm, &nb, cnn);
+    const size_t ws_need = run_ws_bytes(lat, prm, &nb, cnn);
     const Geo g = geo_of(lat);
     const int64_t W = words_of(prm->n_shots);
     const int64_t rows = lat->n_edges;
@@ -299,10 +352,14 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
     float* nu0 = nullptr;
     float* nu1 = nullptr;
     char* next = base + 3 * plane_bytes(lat, nb);
-    if (prm->bp_iters > 0) {
+    if (run_bp_bytes(lat, prm, nb, cnn) > 0) {
         nu0 = (float*)next;
         nu1 = (float*)(next + bp_state_bytes(lat, prm, nb));
         next += 2 * bp_state_bytes(lat, prm, nb);
+    }
+    if (c.stats) {  // a timed run counts BP near-ties on the device
+        c.stats->d_ties = (unsigned long long*)(base + ws_need - kCounterBytes);
+        if ((rc = launch_clear(c, Plane{(uint64_t*)c.stats->d_ties, 1}, 1, 1))) return rc;
     }
     uint64_t* prev = nullptr;
     float* llr = nullptr;
@@ -318,43 +375,55 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
     const uint32_t th_p = threshold_of(prm->p), th_q = threshold_of(prm->q);
     const float l0 = (float)log((1.0 - prm->p_dec) / prm->p_dec);
     const float K = (float)(1.0 - 2.0 * prm->q_dec);
+    const int n_subset = __builtin_popcount(prm->subset_mask);
     for (int64_t w0 = 0; w0 < W; w0 += nb) {
         const int64_t bw = std::min(nb, W - w0);
         const uint64_t gword0 = prm->shot0 / 64 + (uint64_t)w0;
         const Plane E{err + w0, W}, S{syn, bw}, C{corr, bw}, F{flips, bw};
         const CPlane cE{err + w0, W}, cS{syn, bw}, cC{corr, bw}, cF{flips, bw};
+        const float* warm = nullptr;  // the messages the previous cycle's BP ended with
+        // a resumed run's CNN input needs the working syndrome the previous
+        // cycle ended with: H e of the residual plus that cycle's check-outcome
+        // noise (the sweeps' corrections cancel in H e), a noisy cycle
+        if (cnn && prm->cycle0 > 0 &&
+            (rc = launch_syndrome(c, g, cE, Plane{prev, bw}, bw, 0, th_q, gword0,
+                                  prm->cycle0 - 1, prm->seed)))
+            return rc;
         for (int32_t t = 0; t < cycles; ++t) {
             const bool noisy = t < prm->noisy_cycles;
             const uint32_t tp = (noisy || prm->final_qubit_noise) ? th_p : 0u;
             const uint32_t tq = noisy ? th_q : 0u;
-            if ((rc = launch_noise(c, g, E, bw, gword0, 0u, (uint32_t)t, tp, prm->seed))) return rc;
-            if ((rc = launch_syndrome(c, g, cE, S, bw, 0, tq, gword0, (uint32_t)t, prm->seed)))
+            const uint32_t cyc = prm->cycle0 + (uint32_t)t;  // cycle of the whole experiment
+            if ((rc = launch_noise(c, g, E, bw, gword0, 0u, cyc, tp, prm->seed))) return rc;
+            if ((rc = launch_syndrome(c, g, cE, S, bw, 0, tq, gword0, cyc, prm->seed)))
                 return rc;
             if (prm->bp_iters > 0) {
                 if (cnn &&
-                    (rc = cnn_forward(c, g, syn, t == 0 ? nullptr : prev, bw, 64 * bw * g.N,
-                                      packed, llr, cnn_ws)))
+                    (rc = cnn_forward(c, g, syn, (t == 0 && prm->cycle0 == 0) ? nullptr : prev,
+                                      bw, 64 * bw * g.N, packed, llr, cnn_ws)))
                     return rc;
                 if (prm->bp_meta) {
                     if ((rc = bp_meta_run(c, g, cS, bw, prm->p_dec, prm->q_dec, prm->bp_iters,
                                           (double*)nu0, (double*)nu1, C, nullptr)))
                         return rc;
                 } else {
-                    const BpArgs a =
-                        make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw, prm->bp_tile);
-                    if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr))) return rc;
+                    const BpArgs a = make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw,
+                                                  prm->bp_tile, prm->bp_path,
+                                                  (float)prm->bp_damp);
+                    if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr, warm,
+                                     prm->bp_warm ? &warm : nullptr)))
+                        return rc;
                 }
                 if ((rc = launch_syndrome(c, g, cC, S, bw, 1, 0u, 0, 0, 0))) return rc;
             } else {
                 if ((rc = launch_clear(c, C, rows, bw))) return rc;
             }
-            const int n_subset = __builtin_popcount(prm->subset_mask);
             for (int32_t k = 0, j = 0; k < prm->n_sweeps; ++k) {
                 const bool sub = (prm->subset_mask >> k) & 1u;
                 const int pf = sub ? 1 : (int)((prm->pflip_mask >> k) & 1u);
-                const int cls = sub ? (int)(((uint64_t)j++ + (uint64_t)t * n_subset) % 12u) : -1;
-                if ((rc = launch_sweep_decide(c, g, cS, C, F, bw, pf, gword0, (uint32_t)t,
-                                              (uint32_t)k, prm->seed, cls)))
+                const int cls = sub ? (int)(((uint64_t)j++ + (uint64_t)cyc * n_subset) % 12u) : -1;
+                if ((rc = launch_sweep_decide(c, g, cS, C, F, bw, pf, gword0, cyc, (uint32_t)k,
+                                              prm->seed, cls)))
                     return rc;
                 if ((rc = launch_syndrome(c, g, cF, S, bw, 1, 0u, 0, 0, 0))) return rc;
             }
@@ -362,13 +431,73 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
             if ((rc = launch_xor(c, E, cC, rows, bw))) return rc;
         }
         const int64_t shots_b = std::min<int64_t>(64 * bw, prm->n_shots - 64 * w0);
-        if ((rc = launch_readout(c, g, cE, shots_b, mask + 64 * w0, odd ? odd + 3 * 64 * w0 : nullptr)))
+        // the flip plane (3 L^3 rows) holds the 3 L^2 string parities
+        if ((rc = launch_readout(c, g, cE, shots_b, mask + 64 * w0,
+                                 odd ? odd + 3 * 64 * w0 : nullptr, flips)))
             return rc;
     }
     return TC3D_OK;
 }
 
+// run_impl captured into one HIP graph on a library stream (a capture cannot
+// start on the legacy default stream), launched on `stream` and waited for.
+// Every argument is checked first, so nothing half-captured is left behind.
+int run_graph(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err,
+              uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc = run_validate(lat, prm, nullptr, err, mask, odd, ws, ws_bytes);
+    if (rc || prm->n_shots == 0) return rc;
+    if ((rc = bp_resident_prepare())) return rc;
+    hipStream_t cap = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return TC3D_EHIP;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return TC3D_EHIP;
+    }
+    // the captured work starts after what is already on `stream`
+    if (hipEventRecord(ev, stream) != hipSuccess || hipStreamWaitEvent(cap, ev, 0) != hipSuccess)
+        rc = TC3D_EHIP;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    if (!rc && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        rc = TC3D_EHIP;
+    if (!rc) {
+        const Ctx c{cap, nullptr};
+        rc = run_impl(lat, prm, nullptr, err, mask, odd, ws, ws_bytes, c);
+        if (hipStreamEndCapture(cap, &g) != hipSuccess && !rc) rc = TC3D_EHIP;
+    }
+    if (!rc && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) rc = TC3D_EHIP;
+    if (!rc && hipGraphLaunch(ex, stream) != hipSuccess) rc = TC3D_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess && !rc) rc = TC3D_EHIP;
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cap);
+    return rc;
+}
+
+// run_impl with HIP-event timing and the BP near-tie counter; blocks.
+int run_timed(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* packed,
+              uint64_t* err, uint8_t* mask, int32_t* odd, void* ws, size_t ws_bytes,
+              hipStream_t stream, tc3d_timing* timing) {
+    Timer tm(stream);
+    RunStats st;
+    const Ctx c{stream, &tm, &st};
+    int rc = run_impl(lat, prm, packed, err, mask, odd, ws, ws_bytes, c);
+    unsigned long long ties = 0;
+    if (!rc && st.d_ties &&
+        hipMemcpyAsync(&ties, st.d_ties, sizeof(ties), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess)
+        rc = TC3D_EHIP;
+    const int rc2 = tm.finish(timing);
+    if (hipStreamSynchronize(stream) != hipSuccess && !rc) rc = TC3D_EHIP;
+    timing->bp_decisions = st.decisions;
+    timing->bp_near_ties = (int64_t)ties;
+    return rc ? rc : rc2;
+}
+
 }  // namespace
+
 }  // namespace tc3d
 
 using namespace tc3d;
@@ -410,6 +539,16 @@ int tc3d_syndrome(const tc3d_lattice* lat, const uint64_t* err, uint64_t* syn,
     const Ctx c{(hipStream_t)stream, nullptr};
     return launch_syndrome(c, geo_of(lat), CPlane{err, n_words}, Plane{syn, n_words}, n_words,
                            xor_into ? 1 : 0, 0u, 0, 0, 0);
+}
+
+int tc3d_apply_correction(const tc3d_lattice* lat, uint64_t* err, const uint64_t* corr,
+                          int64_t n_words, void* stream) {
+    if (!lattice_ok(lat) || n_words < 0) return TC3D_EINVAL;
+    if (n_words == 0) return TC3D_OK;
+    if (!err || !corr) return TC3D_EINVAL;
+    if (!aligned(err, 8) || !aligned(corr, 8)) return TC3D_EALIGN;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return launch_xor(c, Plane{err, n_words}, CPlane{corr, n_words}, lat->n_edges, n_words);
 }
 
 size_t tc3d_sweep_workspace_bytes(const tc3d_lattice* lat, int64_t n_words) {
@@ -469,10 +608,12 @@ static bool bp_scalars_ok(float l0, float K) {
 
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                    const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
-                   uint64_t* corr_out, float* post_out, void* ws, size_t ws_bytes,
-                   void* stream) {
-    if (!lattice_ok(lat) || n_shots < 0 || iters < 1 || !bp_scalars_ok(llr0_scalar, meas_factor))
+                   int32_t bp_path, uint64_t* corr_out, float* post_out, void* ws,
+                   size_t ws_bytes, void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0 || iters < 1 || !bp_scalars_ok(llr0_scalar, meas_factor) ||
+        bp_path < TC3D_BP_AUTO || bp_path > TC3D_BP_RESIDENT)
         return TC3D_EINVAL;
+    if (bp_path == TC3D_BP_RESIDENT && !bp_resident_fits(geo_of(lat), llr0, 1)) return TC3D_EINVAL;
     if (n_shots == 0) return TC3D_OK;
     if (!syn || !corr_out) return TC3D_EINVAL;
     if (!aligned(syn, 8) || !aligned(corr_out, 8) || (llr0 && !aligned(llr0, 4)) ||
@@ -483,16 +624,18 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
     if (!aligned(ws, 256)) return TC3D_EALIGN;
     const int64_t nw = words_of(n_shots);
     const Ctx c{(hipStream_t)stream, nullptr};
-    const BpArgs a = make_bp_args(CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, nw, 0);
+    const BpArgs a =
+        make_bp_args(CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, nw, 0, bp_path);
     float* b0 = (float*)ws;
     float* b1 = (float*)((char*)ws + half);
     return bp_run(c, geo_of(lat), a, iters, b0, b1, Plane{corr_out, nw}, post_out);
 }
 
 int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
-                 const float* llr0, float llr0_scalar, float meas_factor, const float* nu_in,
-                 float* nu_out, float* post_out, void* stream) {
-    if (!lattice_ok(lat) || n_shots < 0 || !bp_scalars_ok(llr0_scalar, meas_factor))
+                 const float* llr0, float llr0_scalar, float meas_factor, float damp,
+                 const float* nu_in, float* nu_out, float* post_out, void* stream) {
+    if (!lattice_ok(lat) || n_shots < 0 || !bp_scalars_ok(llr0_scalar, meas_factor) ||
+        !(damp >= 0.0f && damp < 1.0f) || (damp > 0.0f && llr0))
         return TC3D_EINVAL;
     if (n_shots == 0) return TC3D_OK;
     if (!syn || !nu_out || nu_in == nu_out) return TC3D_EINVAL;
@@ -502,7 +645,8 @@ int tc3d_bp_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
     const int64_t nw = words_of(n_shots);
     const Ctx c{(hipStream_t)stream, nullptr};
     const Geo g = geo_of(lat);
-    const BpArgs a = make_bp_args(CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, nw, 0);
+    const BpArgs a = make_bp_args(CPlane{syn, nw}, llr0, llr0_scalar, meas_factor, nw, 0,
+                                  TC3D_BP_STREAMING, damp);
     int rc = launch_bp_iter(c, g, a, nu_in ? NU_LOAD : NU_ZERO, nu_in, nu_out,
                             nu_in ? TC3D_K_BP_ITER : TC3D_K_BP_FIRST);
     if (rc || !post_out) return rc;
@@ -556,15 +700,24 @@ int tc3d_bp_meta_step(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_sh
                                Plane{nullptr, nw}, post_out);
 }
 
+size_t tc3d_logical_check_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots) {
+    if (!lattice_ok(lat) || n_shots < 0) return 0;
+    return round_up((size_t)readout_scratch_words(geo_of(lat), words_of(n_shots)) * 8 + 8, 256);
+}
+
 int tc3d_logical_check(const tc3d_lattice* lat, const uint64_t* err, int64_t n_shots,
-                       uint8_t* mask_out, int32_t* odd_out, void* stream) {
+                       uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
+                       void* stream) {
     if (!lattice_ok(lat) || n_shots < 0) return TC3D_EINVAL;
     if (n_shots == 0) return TC3D_OK;
     if (!err || !mask_out) return TC3D_EINVAL;
     if (!aligned(err, 8) || (odd_out && !aligned(odd_out, 4))) return TC3D_EALIGN;
+    if (!ws || ws_bytes < tc3d_logical_check_workspace_bytes(lat, n_shots))
+        return TC3D_EWORKSPACE;
+    if (!aligned(ws, 256)) return TC3D_EALIGN;
     const Ctx c{(hipStream_t)stream, nullptr};
     return launch_readout(c, geo_of(lat), CPlane{err, words_of(n_shots)}, n_shots, mask_out,
-                          odd_out);
+                          odd_out, (uint64_t*)ws);
 }
 
 size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm) {
@@ -575,6 +728,9 @@ size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* 
 int tc3d_run_cycles(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err_state,
                     uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
                     void* stream) {
+    if (prm && (prm->flags & TC3D_RUN_GRAPH))
+        return run_graph(lat, prm, err_state, mask_out, odd_out, ws, ws_bytes,
+                         (hipStream_t)stream);
     const Ctx c{(hipStream_t)stream, nullptr};
     return run_impl(lat, prm, nullptr, err_state, mask_out, odd_out, ws, ws_bytes, c);
 }
@@ -583,11 +739,8 @@ int tc3d_run_cycles_timed(const tc3d_lattice* lat, const tc3d_run_params* prm,
                           uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out, void* ws,
                           size_t ws_bytes, void* stream, tc3d_timing* timing) {
     if (!timing) return TC3D_EINVAL;
-    Timer tm((hipStream_t)stream);
-    const Ctx c{(hipStream_t)stream, &tm};
-    int rc = run_impl(lat, prm, nullptr, err_state, mask_out, odd_out, ws, ws_bytes, c);
-    int rc2 = tm.finish(timing);
-    return rc ? rc : rc2;
+    return run_timed(lat, prm, nullptr, err_state, mask_out, odd_out, ws, ws_bytes,
+                     (hipStream_t)stream, timing);
 }
 
 // ------------------------------------------------------------------ CNN prior
@@ -595,11 +748,13 @@ int64_t tc3d_cnn_param_count(void) { return cnn_param_count(); }
 
 size_t tc3d_cnn_packed_bytes(void) { return cnn_packed_bytes(); }
 
-int tc3d_cnn_pack(const float* params, void* packed, void* stream) {
-    if (!params || !packed) return TC3D_EINVAL;
+int tc3d_cnn_pack(const float* params, float beta, float l0, void* packed, void* stream) {
+    if (!params || !packed || !(beta >= 0.0f && beta <= 1.0f) || !isfinite(l0) ||
+        fabsf(l0) > 40.0f)
+        return TC3D_EINVAL;
     if (!aligned(params, 4) || !aligned(packed, 256)) return TC3D_EALIGN;
     const Ctx c{(hipStream_t)stream, nullptr};
-    return cnn_pack(c, params, packed);
+    return cnn_pack(c, params, beta, l0, packed);
 }
 
 static int64_t cnn_rows(const tc3d_lattice* lat, int64_t n_shots) {
@@ -681,11 +836,8 @@ int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* pr
                               int32_t* odd_out, void* ws, size_t ws_bytes, void* stream,
                               tc3d_timing* timing) {
     if (!packed || !timing) return TC3D_EINVAL;
-    Timer tm((hipStream_t)stream);
-    const Ctx c{(hipStream_t)stream, &tm};
-    int rc = run_impl(lat, prm, packed, err_state, mask_out, odd_out, ws, ws_bytes, c);
-    int rc2 = tm.finish(timing);
-    return rc ? rc : rc2;
+    return run_timed(lat, prm, packed, err_state, mask_out, odd_out, ws, ws_bytes,
+                     (hipStream_t)stream, timing);
 }
 
 // ------------------------------------------------------------ batched jobs
@@ -879,6 +1031,12 @@ int tc3d_stream_copy(void* dst, const void* src, int64_t n_bytes, int32_t nontem
     const Ctx c{(hipStream_t)stream, nullptr};
     return launch_stream_copy(c, dst, src, n_bytes / 16, nontemporal);
 }
+
+#ifndef TC3D_BUILD_ID
+#define TC3D_BUILD_ID "unknown"
+#endif
+
+const char* tc3d_build_id(void) { return TC3D_BUILD_ID; }
 
 const char* tc3d_strerror(int code) {
     switch (code) {

@@ -119,35 +119,58 @@ __global__ __launch_bounds__(kBlock) void k_clear(uint64_t* __restrict__ dst, in
     dst[r * ld + w] = 0;
 }
 
-// One workgroup per word, 12 wavefronts: wavefront 4a + q walks every fourth
-// logical Z string of axis a (strings q, q+4, ...), XORs the L words of a
-// string (a wave-uniform load) and each lane counts the odd strings of its
-// shot. The 12 partial counts meet in LDS; wavefront 0 writes the mask byte
-// and the counts of its 64 shots.
+// Majority-vote readout in two passes.
+// Pass 1, one work item per (axis d, logical Z string s, word w), w fastest so
+// that a wavefront's loads of one edge row are contiguous: the parity word of
+// the string (XOR of its L edge words) goes to par[(w 3 + d) L^2 + s]. String
+// s = i L + j holds the edges e(v + t unit(d), d), t = 0 .. L-1, where v has
+// coordinate i on axis (d+1) mod 3, j on axis (d+2) mod 3 and 0 on axis d.
+__global__ __launch_bounds__(kBlock) void k_string_parity(const uint64_t* __restrict__ err,
+                                                          int64_t ld, int L, int N, int64_t nw,
+                                                          uint64_t* __restrict__ par) {
+    const int64_t LL = (int64_t)L * L;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 3 * LL * nw) return;
+    const int64_t w = idx % nw, rest = idx / nw;
+    const int64_t s = rest % LL;
+    const int d = (int)(rest / LL);
+    const int64_t i = s / L, j = s - (s / L) * L;
+    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    const int64_t st = d == 0 ? 1 : (d == 1 ? L : LL);
+    const int64_t s1 = d1 == 0 ? 1 : (d1 == 1 ? L : LL);
+    const int64_t s2 = d2 == 0 ? 1 : (d2 == 1 ? L : LL);
+    const uint64_t* row = err + ((int64_t)d * N + i * s1 + j * s2) * ld + w;
+    uint64_t p = 0;
+    for (int t = 0; t < L; ++t) p ^= row[t * st * ld];
+    par[(w * 3 + d) * LL + s] = p;
+}
+
+// Pass 2, one workgroup per word, wavefront 4 d + q for axis d: each lane
+// loads the parity word of one string (64 consecutive strings per step, every
+// fourth step for wavefront q) and 64 ballots count, for each shot of the word,
+// its odd strings among them; lane k keeps the count of shot 64 w + k. The 12
+// partial counts meet in LDS; wavefront 0 applies the majority rule.
 constexpr int kReadoutParts = 4;
 
-__global__ __launch_bounds__(64 * 3 * kReadoutParts) void k_readout(
-    const uint64_t* __restrict__ err, int64_t ld, int L, int N, int64_t n_shots,
-    uint8_t* __restrict__ mask, int32_t* __restrict__ odd) {
+__global__ __launch_bounds__(64 * 3 * kReadoutParts) void k_string_count(
+    const uint64_t* __restrict__ par, int L, int64_t n_shots, uint8_t* __restrict__ mask,
+    int32_t* __restrict__ odd) {
     __shared__ int part_count[3 * kReadoutParts][64];
     const int64_t w = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int d = wave / kReadoutParts, q = wave % kReadoutParts;
     const int64_t LL = (int64_t)L * L;
-    // stride between consecutive edges of a string, and of the two other axes
-    const int64_t step = d == 0 ? 1 : (d == 1 ? L : LL);
-    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-    const int64_t s1 = d1 == 0 ? 1 : (d1 == 1 ? L : LL);
-    const int64_t s2 = d2 == 0 ? 1 : (d2 == 1 ? L : LL);
-    const uint64_t* base = err + (int64_t)d * N * ld + w;
+    const uint64_t* col = par + (w * 3 + d) * LL;
     int cnt = 0;
-    for (int64_t str = q; str < LL; str += kReadoutParts) {
-        const int64_t i = str / L, j = str - i * L;
-        const uint64_t* row = base + (i * s1 + j * s2) * ld;
-        uint64_t par = 0;
-        for (int t = 0; t < L; ++t) par ^= row[t * step * ld];
-        cnt += (int)((par >> lane) & 1u);
+    for (int64_t c0 = 64 * (int64_t)q; c0 < LL; c0 += 64 * kReadoutParts) {
+        const int64_t s = c0 + lane;
+        const uint64_t p = s < LL ? col[s] : 0ull;
+#pragma unroll 8
+        for (int k = 0; k < 64; ++k) {
+            const int n = __popcll(__ballot((p >> k) & 1ull));
+            cnt += lane == k ? n : 0;
+        }
     }
     part_count[wave][lane] = cnt;
     __syncthreads();
@@ -234,14 +257,22 @@ int launch_clear(const Ctx& c, Plane dst, int64_t rows, int64_t nw) {
     return after_launch(c);
 }
 
+int64_t readout_scratch_words(Geo g, int64_t nw) { return 3 * (int64_t)g.L * g.L * nw; }
+
 int launch_readout(const Ctx& c, Geo g, CPlane err, int64_t n_shots, uint8_t* mask,
-                   int32_t* odd) {
+                   int32_t* odd, uint64_t* par) {
     if (n_shots == 0) return TC3D_OK;
     const int64_t nw = (n_shots + 63) / 64;
     int rc = before_launch(c, TC3D_K_READOUT);
     if (rc) return rc;
-    k_readout<<<dim3((unsigned)nw), dim3(64 * 3 * kReadoutParts), 0, c.stream>>>(
-        err.p, err.ld, g.L, g.N, n_shots, mask, odd);
+    k_string_parity<<<dim3((unsigned)blocks_for(readout_scratch_words(g, nw))), dim3(kBlock), 0,
+                      c.stream>>>(err.p, err.ld, g.L, g.N, nw, par);
+    rc = after_launch(c);
+    if (rc) return rc;
+    rc = before_launch(c, TC3D_K_READOUT);
+    if (rc) return rc;
+    k_string_count<<<dim3((unsigned)nw), dim3(64 * 3 * kReadoutParts), 0, c.stream>>>(
+        par, g.L, n_shots, mask, odd);
     return after_launch(c);
 }
 

@@ -39,8 +39,6 @@
 // running slowest inside the column; T = L by default, i.e. plain memory
 // order), with the message stores streaming past L2 so that the rows loaded
 // for neighbours stay resident.
-#include <stdlib.h>
-
 #include <atomic>
 
 #include "tc3d_device.hpp"
@@ -240,12 +238,26 @@ __device__ __forceinline__ void check_rule(const float a_in[4], float sK, float 
     for (int k = 0; k < 4; ++k) out[k] = (Dk[k] + Nk[k]) * __builtin_amdgcn_rcpf(Dk[k] - Nk[k]);
 }
 
+// |l| < 1e-3 for the posterior e^l: e^-0.001 < e^l < e^0.001.
+__device__ __forceinline__ bool near_tie(float el) {
+    return el > 0.99900050f && el < 1.00100050f;
+}
+
+// Damping (DAMP): nu = (1 - g) nu_new + g nu_old, i.e. e^nu =
+// (e^nu_new)^(1 - g) (e^nu_old)^g, formed with the hardware's base-2 log and
+// exp. Only with the scalar prior.
+__device__ __forceinline__ float damped(float b_new, float b_old, float g) {
+    return __builtin_amdgcn_exp2f((1.0f - g) * __builtin_amdgcn_logf(b_new) +
+                                  g * __builtin_amdgcn_logf(b_old));
+}
+
 // FOLD: 0 plain state in and out; 1 plain in, folded out (the first
 // iteration of a decode with per-edge priors); 2 folded in and out.
-template <int MODE, bool EP, int FOLD>
-__global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
+template <int MODE, bool EP, int FOLD, bool DAMP = false>
+__global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K, float g,
                                                     float* __restrict__ b_out) {
     static_assert(FOLD == 0 || EP, "only per-edge priors are folded");
+    static_assert(!DAMP || (!EP && FOLD == 0), "damping goes with the scalar prior");
     const Item it = item_of(tl);
     if (!it.ok) return;
     const Reader<MODE> R = reader_of<MODE>(S, it);
@@ -302,6 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
         const float sK = sbit[n] ? -K : K;
         float out[4];
         check_rule(a, sK, out);
+        if constexpr (DAMP) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[k] = damped(out[k], R(4 * n + k, v), g);
+        }
         if constexpr (FOLD != 0) {  // slots 8, 10, 6 carry the priors of e(v,x), e(v,y), e(v,z)
             if (n == 2) {
                 out[0] *= ex;
@@ -321,7 +337,8 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K,
 template <int MODE, bool EP, bool FOLDED>
 __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
                                                     uint64_t* __restrict__ corr, int64_t ld_c,
-                                                    float* __restrict__ post) {
+                                                    float* __restrict__ post,
+                                                    unsigned long long* __restrict__ ties) {
     const Item it = item_of(tl);
     if (!it.ok) return;
     const Reader<MODE> R = reader_of<MODE>(S, it);
@@ -346,6 +363,12 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
         const uint64_t flips = __ballot(el[c] < 1.0f);
         if (corr && it.lane == 0) corr[e * ld_c + it.w] = flips;
     }
+    if (ties) {  // posteriors within 1e-3 nats of the decision boundary
+        int n = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) n += __popcll(__ballot(near_tie(el[c])));
+        if (n && it.lane == 0) atomicAdd(ties, (unsigned long long)n);
+    }
 }
 
 // ---------------------------------------------- one shot per workgroup in LDS
@@ -364,7 +387,8 @@ constexpr int kLdsMaxSites = 3 * kLdsThreads;  // L <= 14
 template <int SPT>
 __global__ __launch_bounds__(kLdsThreads) void k_bp_lds(
     const uint64_t* __restrict__ syn, int64_t ld_syn, int L, float a0, float b1, float b1_inv,
-    float K, int more_iters, uint64_t* __restrict__ corr, int64_t ld_c, float* __restrict__ post) {
+    float K, int more_iters, uint64_t* __restrict__ corr, int64_t ld_c, float* __restrict__ post,
+    unsigned long long* __restrict__ ties) {
     extern __shared__ float m[];  // [12][N]
     const int N = L * L * L;
     const int64_t w = blockIdx.x >> 6;
@@ -458,6 +482,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_bp_lds(
                 post[(w * 3 * (int64_t)N + e) * 64 + bit] =
                     0.69314718055994531f * __builtin_amdgcn_logf(el[c]);
             if (el[c] < 1.0f) atomicOr((unsigned long long*)(corr + e * ld_c + w), 1ull << bit);
+            if (ties && near_tie(el[c])) atomicAdd(ties, 1ull);
         }
     }
 }
@@ -548,32 +573,46 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     const Src S = make_src(g, a, nu_in);
     const dim3 grid((unsigned)blocks), block(kBlock);
     const size_t lds = mode == NU_LOAD ? residency_lds(kLoadIterBlocksPerCu) : 0;
+    const float damp = a.damp;
     if (a.llr0) {
+        if (damp != 0.0f) return TC3D_EINVAL;  // damping goes with the scalar prior
         if (mode == NU_ZERO && a.fold)
-            k_bp_iter<NU_ZERO, true, 1><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_ZERO, true, 1><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
         else if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, true, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_ZERO, true, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
         else if (mode == NU_LOAD && a.fold)
-            k_bp_iter<NU_LOAD, true, 2><<<grid, block, lds, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_LOAD, true, 2><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp, nu_out);
         else if (mode == NU_LOAD)
-            k_bp_iter<NU_LOAD, true, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_LOAD, true, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp, nu_out);
         else
             return TC3D_EINVAL;  // the syndrome-implied first state needs a scalar prior
+    } else if (damp != 0.0f) {
+        if (mode == NU_ZERO)
+            k_bp_iter<NU_ZERO, false, 0, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp,
+                                                                            nu_out);
+        else if (mode == NU_SIGMA)
+            k_bp_iter<NU_SIGMA, false, 0, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp,
+                                                                             nu_out);
+        else
+            k_bp_iter<NU_LOAD, false, 0, true><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp,
+                                                                              nu_out);
     } else {
         if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_ZERO, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
         else if (mode == NU_SIGMA)
-            k_bp_iter<NU_SIGMA, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_SIGMA, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
         else
-            k_bp_iter<NU_LOAD, false, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, nu_out);
+            k_bp_iter<NU_LOAD, false, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp, nu_out);
     }
     return after_launch(c);
 }
 
-bool bp_resident_ok(Geo g, const BpArgs& a) {
-    if (a.llr0 || g.N > kLdsMaxSites || a.nw <= 0 || a.nw > (int64_t)1 << 24) return false;
-    const char* e = getenv("TC3D_BP_RESIDENT");
-    return !(e && e[0] == '0');
+bool bp_resident_fits(Geo g, const float* llr0, int64_t nw) {
+    return !llr0 && g.N <= kLdsMaxSites && nw > 0 && nw <= (int64_t)1 << 24;
+}
+
+bool bp_resident_used(Geo g, const BpArgs& a) {
+    return a.path != TC3D_BP_STREAMING && a.damp == 0.0f && bp_resident_fits(g, a.llr0, a.nw);
 }
 
 static std::atomic<int> g_lds_opted[64];  // 1: the kernels may use their LDS size there
@@ -605,14 +644,15 @@ int launch_lds(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr, 
     rc = before_launch(c, TC3D_K_BP_ITER);
     if (rc) return rc;
     k_bp_lds<SPT><<<dim3((unsigned)(64 * a.nw)), dim3(kLdsThreads), lds, c.stream>>>(
-        a.syn.p, a.syn.ld, g.L, a.a0, a.b1, a.b1_inv, a.K, iters - 1, corr.p, corr.ld, post);
+        a.syn.p, a.syn.ld, g.L, a.a0, a.b1, a.b1_inv, a.K, iters - 1, corr.p, corr.ld, post,
+        a.ties);
     return after_launch(c);
 }
 }  // namespace
 
 int launch_bp_resident(const Ctx& c, Geo g, const BpArgs& a, int32_t iters, Plane corr,
                        float* post) {
-    if (!bp_resident_ok(g, a) || iters < 1) return TC3D_EINVAL;
+    if (!bp_resident_fits(g, a.llr0, a.nw) || iters < 1) return TC3D_EINVAL;
     const int spt = (g.N + kLdsThreads - 1) / kLdsThreads;
     if (spt == 1) return launch_lds<1>(c, g, a, iters, corr, post);
     if (spt == 2) return launch_lds<2>(c, g, a, iters, corr, post);
@@ -630,21 +670,22 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     const Src S = make_src(g, a, nu);
     const dim3 grid((unsigned)blocks), block(kBlock);
     const size_t lds = mode == NU_LOAD ? residency_lds(kLoadPostBlocksPerCu) : 0;
+    unsigned long long* ties = a.ties;
     if (a.llr0) {
         if (mode != NU_LOAD) return TC3D_EINVAL;  // a posterior follows a stored iteration
         if (a.fold)
-            k_bp_post<NU_LOAD, true, true><<<grid, block, lds, c.stream>>>(S, tl, corr.p, corr.ld,
-                                                                          post);
+            k_bp_post<NU_LOAD, true, true>
+                <<<grid, block, lds, c.stream>>>(S, tl, corr.p, corr.ld, post, ties);
         else
-            k_bp_post<NU_LOAD, true, false><<<grid, block, lds, c.stream>>>(S, tl, corr.p,
-                                                                           corr.ld, post);
+            k_bp_post<NU_LOAD, true, false>
+                <<<grid, block, lds, c.stream>>>(S, tl, corr.p, corr.ld, post, ties);
     } else {
         if (mode == NU_SIGMA)
-            k_bp_post<NU_SIGMA, false, false><<<grid, block, 0, c.stream>>>(S, tl, corr.p,
-                                                                           corr.ld, post);
+            k_bp_post<NU_SIGMA, false, false>
+                <<<grid, block, 0, c.stream>>>(S, tl, corr.p, corr.ld, post, ties);
         else if (mode == NU_LOAD)
-            k_bp_post<NU_LOAD, false, false><<<grid, block, lds, c.stream>>>(S, tl, corr.p,
-                                                                            corr.ld, post);
+            k_bp_post<NU_LOAD, false, false>
+                <<<grid, block, lds, c.stream>>>(S, tl, corr.p, corr.ld, post, ties);
         else
             return TC3D_EINVAL;
     }

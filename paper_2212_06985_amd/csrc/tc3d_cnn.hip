@@ -105,12 +105,17 @@ constexpr int64_t kPackedBytes = kBiasOffsetBytes + 4 * 32 * 4;
 __device__ __forceinline__ int wrap(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
 // ----------------------------------------------------------- packing
-__global__ void k_pack(const float* __restrict__ params, bf16* __restrict__ packed,
-                       float* __restrict__ bias) {
+// The last layer is packed blended with the channel prior l0 at strength
+// beta: its weights scale by beta and its biases become beta b - (1 - beta)
+// l0, so that the prior -z of the packed network is l0 + beta (llr - l0).
+__global__ void k_pack(const float* __restrict__ params, float beta, float l0,
+                       bf16* __restrict__ packed, float* __restrict__ bias) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 4 * 32) {
         const int l = (int)(i / 32), c = (int)(i % 32);
-        bias[i] = c < kCh[l + 1] ? params[param_offset(l) + 27 * kCh[l] * kCh[l + 1] + c] : 0.f;
+        const float b =
+            c < kCh[l + 1] ? params[param_offset(l) + 27 * kCh[l] * kCh[l + 1] + c] : 0.f;
+        bias[i] = l == 3 && c < kCh[l + 1] ? beta * b - (1.0f - beta) * l0 : b;
     }
     if (i >= kPackedElems) return;
     int b = 0;
@@ -136,6 +141,7 @@ __global__ void k_pack(const float* __restrict__ params, bf16* __restrict__ pack
         else  // reversed tap, transposed: input channel c is the layer's output
             v = W[((int64_t)(26 - d) * lin + o) * lout + c];
     }
+    if (B.layer == 3) v *= beta;
     packed[i] = (bf16)v;
 }
 
@@ -1094,11 +1100,11 @@ int64_t cnn_param_count() { return kParams; }
 size_t cnn_packed_bytes() { return (size_t)kPackedBytes; }
 size_t cnn_workspace_bytes(int64_t R, int training) { return cnn_ws_bytes(R, training); }
 
-int cnn_pack(const Ctx& c, const float* params, void* packed) {
+int cnn_pack(const Ctx& c, const float* params, float beta, float l0, void* packed) {
     int rc = before_launch(c, TC3D_K_CNN);
     if (rc) return rc;
     k_pack<<<dim3((unsigned)cdiv(kPackedElems, 256)), dim3(256), 0, c.stream>>>(
-        params, (bf16*)packed, (float*)((char*)packed + kBiasOffsetBytes));
+        params, beta, l0, (bf16*)packed, (float*)((char*)packed + kBiasOffsetBytes));
     return after_launch(c);
 }
 
@@ -1153,7 +1159,7 @@ int cnn_adam(const Ctx& c, float* params, const float* grad, float* m, float* v,
     k_adam<<<dim3((unsigned)cdiv(kParams, 256)), dim3(256), 0, c.stream>>>(
         params, grad, m, v, kParams, lr, b1, b2, (float)c1, (float)c2, eps);
     if ((rc = after_launch(c))) return rc;
-    return cnn_pack(c, params, packed);
+    return cnn_pack(c, params, 1.0f, 0.0f, packed);
 }
 
 int copy_plane(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw) {

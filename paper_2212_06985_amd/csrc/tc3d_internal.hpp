@@ -40,9 +40,16 @@ class Timer {
     int64_t launches_[TC3D_K_COUNT] = {};
 };
 
+// Counters a timed run reports besides kernel times.
+struct RunStats {
+    unsigned long long* d_ties = nullptr;  // device counter of BP near-ties
+    int64_t decisions = 0;                 // BP hard decisions enqueued
+};
+
 struct Ctx {
     hipStream_t stream;
-    Timer* timer;  // nullptr: no timing
+    Timer* timer;              // nullptr: no timing
+    RunStats* stats = nullptr;  // nullptr: no counters
 };
 
 // A bit plane view: rows x nw words, row stride ld words.
@@ -79,9 +86,11 @@ int launch_xor(const Ctx& c, Plane dst, CPlane src, int64_t rows, int64_t nw);
 int launch_clear(const Ctx& c, Plane dst, int64_t rows, int64_t nw);
 // dst[i] = src[i] for n16 16-byte elements (non-temporal stores if asked).
 int launch_stream_copy(const Ctx& c, void* dst, const void* src, int64_t n16, int nontemporal);
-// Majority-vote readout of n_shots shots of an edge plane.
+// Majority-vote readout of n_shots shots of an edge plane; par is scratch of
+// readout_scratch_words(g, nw) words (the parities of the logical strings).
+int64_t readout_scratch_words(Geo g, int64_t nw);
 int launch_readout(const Ctx& c, Geo g, CPlane err, int64_t n_shots, uint8_t* mask,
-                   int32_t* odd);
+                   int32_t* odd, uint64_t* par);
 
 // ----------------------------------------------------------------------- BP
 enum NuMode { NU_ZERO = 0, NU_SIGMA = 1, NU_LOAD = 2 };
@@ -97,10 +106,14 @@ struct BpArgs {
     int64_t s_pad;       // 64 * nw
     int tile;            // site-tile edge of the traversal order (0: automatic)
     bool fold;           // per-edge priors folded into the stored state (see tc3d_bp.hip)
+    int path;            // TC3D_BP_AUTO / _STREAMING / _RESIDENT
+    unsigned long long* ties;  // device counter of posteriors |l| < 1e-3, or nullptr
+    float damp;          // damping g: nu = (1 - g) nu_new + g nu_old (0: none)
 };
 
 // Fills the derived fields of BpArgs (in double precision, then rounded).
-BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw, int tile);
+BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw, int tile,
+                    int path = TC3D_BP_AUTO, float damp = 0.0f);
 
 // One iteration: b_out = BP(b_in) (messages in the form e^nu) where the
 // incoming state is given by mode.
@@ -111,10 +124,11 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
                    float* post);
 // A whole decode (iters >= 1, scalar prior) with each shot's state in one
-// workgroup's LDS; bit-identical to the streaming kernels. Available when
-// bp_resident_ok: L^3 <= 3072 and no per-edge prior; the environment variable
-// TC3D_BP_RESIDENT=0 turns it off.
-bool bp_resident_ok(Geo g, const BpArgs& a);
+// workgroup's LDS; bit-identical to the streaming kernels. Possible when
+// bp_resident_fits: L^3 <= 3072 and no per-edge prior; bp_resident_used adds
+// the caller's choice of kernels (a.path).
+bool bp_resident_fits(Geo g, const float* llr0, int64_t nw);
+bool bp_resident_used(Geo g, const BpArgs& a);
 // Allows the resident kernels their LDS size on the current device (once per
 // device); called before a graph capture so that nothing of it runs inside one.
 int bp_resident_prepare();
@@ -136,7 +150,7 @@ int bp_meta_run(const Ctx& c, Geo g, CPlane syn, int64_t nw, double p_dec, doubl
 int64_t cnn_param_count();
 size_t cnn_packed_bytes();
 size_t cnn_workspace_bytes(int64_t rows, int training);
-int cnn_pack(const Ctx& c, const float* params, void* packed);
+int cnn_pack(const Ctx& c, const float* params, float beta, float l0, void* packed);
 // llr [W][3N][64] = -CNN(syn, prev) for R = 64 W N rows; prev may be null.
 int cnn_forward(const Ctx& c, Geo g, const uint64_t* syn, const uint64_t* prev, int64_t ld,
                 int64_t rows, const void* packed, float* llr, void* ws);

@@ -17,11 +17,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 import paper_2212_06985_amd as tc  # noqa: E402
-from paper_2212_06985_amd.train_cnn import blend_prior  # noqa: E402
+from paper_2212_06985_amd.train_cnn import packed_prior  # noqa: E402
 
 
-def run(L, shots, p, cycles, params=None, seed=777, bp_iters=20, batch_shots=0):
-    """One experiment; params None: the paper's prior. Returns a dict."""
+def run(L, shots, p, cycles, params=None, seed=777, bp_iters=20, batch_shots=0, beta=1.0):
+    """One experiment; params None: the paper's prior, else the network's
+    prior blended at strength beta. Returns a dict."""
     import torch
     lat = tc.make_lattice(L)
     prm = tc.make_run_params(p, p, cycles, bp_iters, 6, 0b001001, n_shots=shots, seed=seed,
@@ -33,9 +34,7 @@ def run(L, shots, p, cycles, params=None, seed=777, bp_iters=20, batch_shots=0):
         ws = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
         t = tc.run_cycles_timed(lat, prm, err, mask, odd, ws)
     else:
-        d = torch.from_numpy(np.asarray(params, np.float32)).cuda()
-        packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
-        tc.cnn_pack(d, packed)
+        packed = packed_prior(params, beta, p)
         ws = tc.alloc_workspace(tc.run_cnn_workspace_bytes(lat, prm))
         t = tc.run_cycles_cnn_timed(lat, prm, packed, err, mask, odd, ws)
     m = mask.cpu().numpy()
@@ -73,8 +72,7 @@ def main():
         print(json.dumps(base), flush=True)
         for it in args.bp_iters:
             for beta in args.betas:
-                r = run(L, args.shots, args.p, cycles, blend_prior(w, beta, args.p), args.seed,
-                        bp_iters=it)
+                r = run(L, args.shots, args.p, cycles, w, args.seed, bp_iters=it, beta=beta)
                 r["decoder"] = f"CNN prior beta={beta}"
                 print(json.dumps(r), flush=True)
 

@@ -82,11 +82,8 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
     if cnn_weights is not None:
         if it == 0:
             raise ValueError("the CNN prior feeds BP: pick a decoder with BP iterations")
-        from paper_2212_06985_amd.train_cnn import blend_prior
-        w = np.load(cnn_weights, allow_pickle=False)
-        d = torch.from_numpy(blend_prior(w, beta, p).astype(np.float32)).cuda()
-        packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
-        tc.cnn_pack(d, packed)
+        from paper_2212_06985_amd.train_cnn import packed_prior
+        packed = packed_prior(np.load(cnn_weights, allow_pickle=False), beta, p)
     sub_bits = 0
     if schedule:
         ns, mask_bits, sub_bits = parse_schedule(schedule)

@@ -46,17 +46,16 @@ def init_params(seed: int, p: float) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-def blend_prior(params: np.ndarray, beta: float, p: float) -> np.ndarray:
-    """Parameters whose prior is llr0 = l0 + beta (llr_cnn - l0), with l0 the
-    channel prior ln((1-p)/p): the last layer's weights scale by beta and its
-    bias by beta plus (1 - beta) times the channel logit. beta = 0 gives the
-    paper's decoder, beta = 1 the network as trained."""
-    out = np.asarray(params, np.float32).copy()
-    n4w = 27 * CHANNELS[3] * CHANNELS[4]
-    off = len(out) - (n4w + CHANNELS[4])
-    out[off:off + n4w] *= beta
-    out[off + n4w:] = beta * out[off + n4w:] + (1 - beta) * math.log(p / (1 - p))
-    return out
+def packed_prior(params: np.ndarray, beta: float, p: float):
+    """Device copy of a network in the kernels' packed layout, its prior
+    blended with the channel prior of error rate p at strength beta (by the
+    library's packing kernel): llr0 = l0 + beta (llr_cnn - l0). beta = 0 gives
+    the paper's decoder, beta = 1 the network as trained."""
+    import torch
+    d = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
+    packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
+    tc.cnn_pack(d, packed, beta=beta, p=p)
+    return packed
 
 
 class Trainer:
@@ -75,6 +74,7 @@ class Trainer:
         self.grad = torch.zeros_like(self.params)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device=dev)
+        self.packed_dec = torch.zeros_like(self.packed)  # blended, for on-policy decoding
         tc.cnn_pack(self.params, self.packed)
         self.err = torch.zeros((n, self.W), dtype=torch.int64, device=dev)
         self.syn = torch.zeros_like(self.err)
@@ -113,10 +113,8 @@ class Trainer:
         tc.cnn_adam(self.params, self.grad, self.m, self.v, self.step, lr, self.packed)
         # decode this cycle and carry the residual
         if on_policy:  # priors of the updated network, blended as when decoding
-            tc.cnn_forward(lat, self.syn, prev, S, self.packed, self.llr, self.ws_train)
-            if beta != 1.0:
-                l0p = math.log((1 - self.p) / self.p)
-                self.llr.mul_(beta).add_((1.0 - beta) * l0p)
+            tc.cnn_pack(self.params, self.packed_dec, beta=beta, p=self.p)
+            tc.cnn_forward(lat, self.syn, prev, S, self.packed_dec, self.llr, self.ws_train)
             llr = self.llr
         else:
             llr = None
@@ -130,7 +128,7 @@ class Trainer:
             else:
                 tc.flip_sweep(lat, self.syn, self.corr, W, self.ws_sw)
         self.prev.copy_(self.syn)
-        self.err ^= self.corr
+        tc.apply_correction(lat, self.err, self.corr, W)
         self.t += 1
 
     def params_numpy(self):
@@ -179,7 +177,7 @@ def main():
     ap.add_argument("--on-policy-iters", type=int, default=20,
                     help="BP iterations of that decoder")
     ap.add_argument("--on-policy-beta", type=float, default=1.0,
-                    help="prior strength of that decoder (see blend_prior)")
+                    help="prior strength of that decoder (see packed_prior)")
     args = ap.parse_args()
     tr, hist, secs = train(args.L, args.shots, args.p, args.cycles, args.snapshots,
                            args.on_policy_frac, seed=args.seed,

@@ -65,8 +65,101 @@ def oracle_run_parallel(o, params, n_shots, shot0=0, chunk=None):
     return mask, odd, err
 
 
+def post_bound_from_messages(edge_face, edge_slot, o_nu):
+    """Tolerance of a posterior LLR (E4: l = l0 + the sum of its 4 incoming
+    messages) implied by the per-message tolerance: the sum of the 4 messages'
+    bounds, BP_REL max(|nu|, BP_FLOOR) each."""
+    return (BP_REL * np.maximum(np.abs(o_nu[edge_face, edge_slot]), BP_FLOOR)).sum(axis=1)
+
+
 def within_bp_tol(g: np.ndarray, o: np.ndarray):
     bound = BP_REL * np.maximum(np.abs(o), BP_FLOOR)
     dev = np.abs(g - o)
     return bool((dev <= bound).all()), float((dev / np.maximum(np.abs(o), 1e-30)).max()), \
         float(dev.max())
+
+
+# ------------------------------------------------ divergence of p-BP shots
+def gpu_word_residual(L, kw, shot, cycles_done):
+    """Residual of `shot` after the first `cycles_done` cycles of the run with
+    run-parameter keywords kw (make_run_params), from a GPU run of the one
+    64-shot word that holds the shot. A run's trajectory depends only on
+    (seed, shot, cycle), so its prefix is a shorter run."""
+    import torch
+    import paper_2212_06985_amd as tc
+    noisy = kw["noisy_cycles"]
+    k = dict(kw)
+    if cycles_done <= noisy:
+        k.update(noisy_cycles=cycles_done, perfect_final=0)
+    k.update(n_shots=64, shot0=64 * (shot // 64), batch_shots=0)
+    prm = tc.make_run_params(**k)
+    lat = tc.make_lattice(L)
+    err = torch.zeros((lat.n_edges, 1), dtype=torch.int64, device="cuda")
+    mask = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    ws = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
+    tc.run_cycles(lat, prm, err, mask, None, ws)
+    torch.cuda.synchronize()
+    return bits_of_dev(err, 64)[shot % 64]
+
+
+def explain_divergence(o, L, kw, shot, e_gpu_final):
+    """Why shot `shot` ended differently on the GPU (FP32 BP) and in the
+    oracle (FP64 BP). Finds the first cycle whose residual differs (from the
+    oracle's trace and GPU runs of the shot's word), recomputes that cycle's
+    syndrome from the common residual before it, and decodes it with both BPs.
+    Returns (cycle, differing BP decisions, the oracle's |l| there): the
+    divergence is explained when BP decided apart only where |l| < LLR_TIE."""
+    import math
+    import torch
+    import paper_2212_06985_amd as tc
+    from oracle.oracle import make_params
+    prm_o = make_params(kw["p"], kw["q"], kw["noisy_cycles"], kw["bp_iters"], kw["n_sweeps"],
+                        kw["pflip_mask"], seed=kw.get("seed", 1),
+                        perfect_final=kw.get("perfect_final", 1))
+    _, _, e_o, tr = o.run_cycles(prm_o, 1, shot0=shot, trace=True)
+    cycles = tr.shape[0]
+    # first differing cycle (1-based count of cycles done), by bisection over
+    # GPU prefix runs; the final states differ, so cycle `cycles` differs
+    assert not np.array_equal(tr[-1][0], e_gpu_final)
+    lo, hi = 0, cycles  # residual after lo cycles agrees, after hi differs
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if np.array_equal(gpu_word_residual(L, kw, shot, mid), tr[mid - 1][0]):
+            lo = mid
+        else:
+            hi = mid
+    c = hi - 1  # index of the first cycle that ends apart
+    e = np.zeros((1, o.n_edges), np.uint8) if c == 0 else tr[c - 1].copy()
+    noisy = c < kw["noisy_cycles"]
+    o.sample_noise(e, 0, kw["p"], kw.get("seed", 1), c, shot)
+    syn = o.syndrome(e)
+    o.sample_noise(syn, 1, kw["q"] if noisy else 0.0, kw.get("seed", 1), c, shot)
+    p_dec, q_dec = kw.get("p_dec") or kw["p"], kw.get("q_dec") or kw["q"]
+    c_o, post_o = o.bp_decode(syn, p_dec, q_dec, kw["bp_iters"])
+    lat = tc.make_lattice(L)
+    d_syn = dev_plane_of_bits(syn)
+    corr = torch.zeros_like(d_syn)
+    ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, 1))
+    tc.bp_decode(lat, d_syn, 1, None, math.log((1 - p_dec) / p_dec), 1 - 2 * q_dec,
+                 kw["bp_iters"], corr, None, ws)
+    torch.cuda.synchronize()
+    c_g = bits_of_dev(corr, 1)
+    where = np.flatnonzero(c_g[0] != c_o[0])
+    return c, where, np.abs(post_o[0][where])
+
+
+def compare_runs(o, L, kw, m_g, e_g, m_o, e_o, shots):
+    """Per-shot comparison of GPU and oracle runs over the given shot indices
+    (rows of m_g/e_g and m_o/e_o in that order). Every shot that differs must
+    be explained by a BP near-tie (explain_divergence). Returns the number of
+    diverged shots."""
+    same = (e_g == e_o).all(axis=1) & (m_g == m_o)
+    diverged = [int(s) for s, ok in zip(shots, same) if not ok]
+    for s in diverged:
+        row = list(shots).index(s)
+        cyc, where, absl = explain_divergence(o, L, kw, s, e_g[row])
+        announce(f"  shot {s} diverged in cycle {cyc}: BP decisions differ on "
+                 f"{len(where)} edges, oracle |l| there {absl.tolist()}")
+        assert len(where) > 0, f"shot {s}: BP agreed, the divergence is not BP's"
+        assert (absl < LLR_TIE).all(), f"shot {s}: BP decided apart away from a near-tie"
+    return len(diverged)

@@ -53,9 +53,19 @@ def test_workspace_sizes(lib):
     assert tc.sweep_workspace_bytes(lat, 3) == ((5184 * 3 * 8 + 255) // 256) * 256
     # two FP32 message buffers of 12 L^3 S_pad
     assert tc.bp_workspace_bytes(lat, 100) == 2 * 12 * 1728 * 128 * 4
-    prm = tc.make_run_params(0.05, 0.05, 12, 20, 6, 0b001001, n_shots=1000, batch_shots=512)
-    need = tc.run_workspace_bytes(lat, prm)
-    assert need == 3 * ((5184 * 8 * 8 + 255) // 256) * 256 + 2 * 12 * 1728 * 512 * 4
+    # a run: syndrome, correction and flip planes of one batch, two message
+    # buffers when BP streams them through HBM, 256 bytes of counters
+    planes = 3 * ((5184 * 8 * 8 + 255) // 256) * 256
+    prm = tc.make_run_params(0.05, 0.05, 12, 20, 6, 0b001001, n_shots=1000, batch_shots=512,
+                             bp_path=tc.BP_STREAMING)
+    assert tc.run_workspace_bytes(lat, prm) == planes + 2 * 12 * 1728 * 512 * 4 + 256
+    # the resident decode (L <= 14) keeps its messages in LDS
+    prm.bp_path = tc.BP_AUTO
+    assert tc.run_workspace_bytes(lat, prm) == planes + 256
+    prm.bp_path = tc.BP_RESIDENT
+    assert tc.run_workspace_bytes(lat, prm) == planes + 256
+    # a readout: the parities of the 3 L^2 strings of each word
+    assert tc.logical_check_workspace_bytes(lat, 100) == ((3 * 144 * 2 * 8 + 8 + 255) // 256) * 256
     corrupt = tc.make_lattice(12)
     corrupt.n_edges = 7
     assert lib.tc3d_sweep_workspace_bytes(ctypes.byref(corrupt), 3) == 0
@@ -71,6 +81,13 @@ def test_invalid_parameters_are_rejected_before_any_launch(lib):
         dict(p_dec=0.0),                   # BP prior must be in (0, 0.5)
         dict(q_dec=0.5),
         dict(perfect_final=2),
+        dict(bp_path=3),                   # no such kernel choice
+        dict(cycle0=0xFFFFFFFF),           # cycle indices past 2^32
+        dict(bp_damp=1.0),                 # damping in [0, 1)
+        dict(bp_damp=-0.1),
+        dict(bp_warm=2),
+        dict(bp_warm=1, bp_iters=1),       # one iteration stores no messages
+        dict(bp_warm=1, bp_meta=1),        # the readings are of the paper's BP
     ]
     for over in cases:
         kw = dict(p=0.02, q=0.02, noisy_cycles=6, bp_iters=20, n_sweeps=5, pflip_mask=4,
@@ -87,13 +104,21 @@ def test_invalid_parameters_are_rejected_before_any_launch(lib):
     assert lib.tc3d_sample_noise(ctypes.byref(lat), None, 2, 0.1, 1, 0, 0, 64, None) == -1
     assert lib.tc3d_sample_noise(ctypes.byref(lat), None, 0, 1.5, 1, 0, 0, 64, None) == -1
     assert lib.tc3d_sample_noise(ctypes.byref(lat), None, 0, 0.1, 1, 0, 32, 64, None) == -1
-    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 1.0, 20, None, None, None,
-                              0, None) == -1  # meas_factor must be < 1
-    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 0, None, None, None,
-                              0, None) == -1  # iters >= 1
+    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 1.0, 20, 0, None, None,
+                              None, 0, None) == -1  # meas_factor must be < 1
+    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 0, 0, None, None,
+                              None, 0, None) == -1  # iters >= 1
+    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 20, 3, None, None,
+                              None, 0, None) == -1  # no such kernel choice
+    big = tc.make_lattice(16)  # the resident kernel holds at most 3072 sites
+    assert lib.tc3d_bp_decode(ctypes.byref(big), None, 64, None, 2.9, 0.9, 20, 2, None, None,
+                              None, 0, None) == -1
     # empty calls are no-ops
     assert lib.tc3d_syndrome(ctypes.byref(lat), None, None, 0, 0, None) == 0
-    assert lib.tc3d_logical_check(ctypes.byref(lat), None, 0, None, None, None) == 0
+    assert lib.tc3d_logical_check(ctypes.byref(lat), None, 0, None, None, None, 0, None) == 0
+    # a readout needs the string-parity scratch
+    assert lib.tc3d_logical_check(ctypes.byref(lat), ctypes.c_void_p(256), 64,
+                                  ctypes.c_void_p(512), None, None, 0, None) == -4
 
 
 def test_misaligned_and_missing_buffers(lib):

@@ -101,11 +101,14 @@ def test_resident_bp_roofline_is_alu_bound():
     pc = _cls(bp_iter={"ms": 2.0, "launches": 1})
     r = bench.roofline(pc, 5184, 4096, 1728, "none", shots_padded=4096, bp_iters=20)
     assert r["bound"] == "alu" and r["kernel"].startswith("bp_resident")
-    per_site = (3 * 46 + 30) * 19 + 12
+    # VALU issue slots per site and iteration: 3 checks of 30 one-slot ops and
+    # 4 outputs of 3 one-slot ops and a quarter-rate reciprocal, 30 products
+    per_site = (3 * (30 + 4 * (3 + 4)) + 30) * 19 + 12
     assert r["algo_ops_per_unit"] == per_site
     assert r["algo_ops_per_launch"] == per_site * 1728 * 4096
     assert r["achieved"] == pytest.approx(per_site * 1728 * 4096 / 2e-3 / 1e12, abs=0.01)
-    assert r["peak"] == pytest.approx(157.3 / 2)
+    # one FP32 op per lane per clock: 256 CUs x 64 lanes x 2.4 GHz
+    assert r["peak"] == pytest.approx(39.32, abs=0.01)
     # larger lattices, or a per-edge prior, stream their messages through HBM
     assert bench.roofline(pc, 3 * 4096, 4096, 4096, "none", shots_padded=4096,
                           bp_iters=20)["bound"] == "hbm"

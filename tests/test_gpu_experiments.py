@@ -64,14 +64,12 @@ def test_memory_run_with_the_cnn_prior_is_run_cycles_cnn():
     import torch
 
     import paper_2212_06985_amd as tc
-    from paper_2212_06985_amd.train_cnn import blend_prior
+    from paper_2212_06985_amd.train_cnn import packed_prior
     L, p, cycles, shots, beta, it = 6, 0.06, 20, 512, 0.5, 8
     w = os.path.join(os.path.dirname(tc.__file__), "weights", "cnn_L12_long.npy")
     r = ex.memory_run(L, p, cycles, "pbp", shots, seed=5, bp_iters=it, cnn_weights=w,
                       beta=beta)
-    d = torch.from_numpy(blend_prior(np.load(w), beta, p).astype(np.float32)).cuda()
-    packed = torch.zeros(tc.cnn_packed_bytes(), dtype=torch.uint8, device="cuda")
-    tc.cnn_pack(d, packed)
+    packed = packed_prior(np.load(w), beta, p)
     lat = tc.make_lattice(L)
     prm = tc.make_run_params(p, p, cycles, it, 6, 0b001001, n_shots=shots, seed=5,
                              perfect_final=0)

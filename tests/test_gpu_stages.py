@@ -394,7 +394,7 @@ def test_bp_decode_per_edge_prior(L, n_shots):
 
 @pytest.mark.parametrize("L,n_shots,iters", [(3, 130, 20), (5, 100, 1), (6, 200, 2),
                                               (8, 150, 20), (12, 128, 20), (14, 64, 20)])
-def test_bp_decode_resident_equals_streaming(L, n_shots, iters, monkeypatch):
+def test_bp_decode_resident_equals_streaming(L, n_shots, iters):
     """The whole-decode-in-LDS path (L <= 14, scalar prior) against the
     streaming kernels on the same syndromes: corrections and posteriors bit for
     bit, padding shots of the last word included."""
@@ -407,16 +407,17 @@ def test_bp_decode_resident_equals_streaming(L, n_shots, iters, monkeypatch):
     d_syn = dev_plane_of_bits(syn)
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     out = {}
-    for mode in ("1", "0"):
-        monkeypatch.setenv("TC3D_BP_RESIDENT", mode)
+    for mode in (tc.BP_RESIDENT, tc.BP_STREAMING):
         corr = torch.full((3 * L ** 3, W), -1, dtype=torch.int64, device="cuda")
         post = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
-        tc.bp_decode(lat, d_syn, n_shots, None, math.log(19.0), 0.9, iters, corr, post, ws)
+        tc.bp_decode(lat, d_syn, n_shots, None, math.log(19.0), 0.9, iters, corr, post, ws,
+                     path=mode)
         sync()
         out[mode] = (corr.cpu().numpy(), post.cpu().numpy().view(np.int32))
-    assert np.array_equal(out["1"][0], out["0"][0])
-    assert np.array_equal(out["1"][1], out["0"][1])
-    assert out["1"][0].any()
+    res, stream = out[tc.BP_RESIDENT], out[tc.BP_STREAMING]
+    assert np.array_equal(res[0], stream[0])
+    assert np.array_equal(res[1], stream[1])
+    assert res[0].any()
 
 
 def test_zero_syndrome_scalar_recursion_on_gpu():
