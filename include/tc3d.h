@@ -46,8 +46,11 @@
  *
  * State: results depend only on the arguments. The library caches, per
  * device, two facts it queries once (the LDS size of a compute unit, and
- * that the LDS-resident BP kernels were granted their LDS size); neither
- * changes a result. Concurrent calls on different buffers are safe.
+ * that the LDS-resident BP kernels were granted their LDS size) and the
+ * address of its scratch array for tc3d_run_cycles_noalloc; none of them
+ * changes a result. Concurrent calls on different buffers are safe, except
+ * tc3d_run_cycles_noalloc calls that overlap on one device (they share its
+ * scratch array).
  */
 #ifndef TC3D_H
 #define TC3D_H
@@ -285,6 +288,22 @@ size_t tc3d_run_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* 
 int tc3d_run_cycles(const tc3d_lattice* lat, const tc3d_run_params* prm, uint64_t* err_state,
                     uint8_t* mask_out, int32_t* odd_out, void* ws, size_t ws_bytes,
                     void* stream);
+
+/* tc3d_run_cycles for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the scratch comes from a fixed array of 128 MiB that the library keeps on
+ * each device it runs on until the process ends, and the call allocates
+ * nothing. The caller passes only the inputs and outputs of tc3d_run_cycles.
+ * With batch_shots = 0 the largest batch whose scratch fits is chosen (one
+ * 64-shot word of the streaming BP state fits up to L = 24); a run whose
+ * smallest batch, or whose given batch_shots, needs more than 128 MiB is
+ * refused with TC3D_EWORKSPACE. Every call on a device shares that device's
+ * array, which keeps the last call's contents (nothing in it has to start at
+ * zero): calls that overlap on one device race, so order them on one stream
+ * or synchronise between them. Results equal tc3d_run_cycles bit for bit. */
+int tc3d_run_cycles_noalloc(const tc3d_lattice* lat, const tc3d_run_params* prm,
+                            uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out,
+                            void* stream);
 
 /* Kernel classes reported by tc3d_run_cycles_timed. */
 enum {

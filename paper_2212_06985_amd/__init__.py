@@ -22,7 +22,7 @@ __all__ = [
     "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
     "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
     "logical_check_workspace_bytes", "built_id", "BP_AUTO", "BP_STREAMING", "BP_RESIDENT",
-    "apply_correction", "RUN_GRAPH",
+    "run_cycles_noalloc", "apply_correction", "RUN_GRAPH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtc3d.so")
@@ -143,6 +143,7 @@ def lib():
         "tc3d_bp_meta_step": (ctypes.c_int, [lat, vp, i64, f64, f64, vp, vp, vp, vp]),
         "tc3d_run_workspace_bytes": (sz, [lat, prm]),
         "tc3d_run_cycles": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp]),
+        "tc3d_run_cycles_noalloc": (ctypes.c_int, [lat, prm, vp, vp, vp, vp]),
         "tc3d_run_cycles_timed": (ctypes.c_int, [lat, prm, vp, vp, vp, vp, sz, vp,
                                                  ctypes.POINTER(Timing)]),
         "tc3d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -317,6 +318,13 @@ def run_cycles(lat, prm: RunParams, err_state, mask_out, odd_out, ws, stream=Non
     _check(lib().tc3d_run_cycles(ctypes.byref(lat), ctypes.byref(prm), _ptr(err_state),
                                  _ptr(mask_out), _ptr(odd_out), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream(stream)), "run_cycles")
+
+
+def run_cycles_noalloc(lat, prm: RunParams, err_state, mask_out, odd_out=None, stream=None):
+    """run_cycles with the library's fixed per-device scratch (no workspace)."""
+    _check(lib().tc3d_run_cycles_noalloc(ctypes.byref(lat), ctypes.byref(prm), _ptr(err_state),
+                                         _ptr(mask_out), _ptr(odd_out), _stream(stream)),
+           "run_cycles_noalloc")
 
 
 def run_cycles_timed(lat, prm: RunParams, err_state, mask_out, odd_out, ws,

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "tc3d_internal.hpp"
@@ -498,6 +499,33 @@ int run_timed(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* p
 
 }  // namespace
 
+// Scratch of tc3d_run_cycles_noalloc: a fixed array in device memory, one
+// copy per device, held until the process ends. 128 MiB holds one 64-shot
+// word of the streaming BP state up to L = 24 and whole batches at smaller L.
+// Every step of run_impl writes its scratch before reading it, so nothing
+// in it needs clearing between calls.
+constexpr size_t kNoallocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch[kMaxDevices];
+
+// Device address of the current device's copy of the array, looked up once
+// per device on the first call there (in host code the array's name only
+// stands in for it).
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return TC3D_EHIP;
+    void* p = g_scratch[dev].load(std::memory_order_acquire);
+    if (!p) {
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TC3D_EHIP;
+        g_scratch[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return TC3D_OK;
+}
+}  // namespace
 }  // namespace tc3d
 
 using namespace tc3d;
@@ -838,6 +866,35 @@ int tc3d_run_cycles_cnn_timed(const tc3d_lattice* lat, const tc3d_run_params* pr
     if (!packed || !timing) return TC3D_EINVAL;
     return run_timed(lat, prm, packed, err_state, mask_out, odd_out, ws, ws_bytes,
                      (hipStream_t)stream, timing);
+}
+
+// A run that allocates nothing: its scratch is the array above.
+int tc3d_run_cycles_noalloc(const tc3d_lattice* lat, const tc3d_run_params* prm,
+                            uint64_t* err_state, uint8_t* mask_out, int32_t* odd_out,
+                            void* stream) {
+    int rc = check_run(lat, prm);
+    if (rc) return rc;
+    tc3d_run_params p = *prm;
+    if (p.batch_shots == 0 && p.n_shots > 0) {
+        // the largest batch whose workspace fits the array (results do not
+        // depend on the batch)
+        int64_t lo = 0, hi = words_of(p.n_shots);
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            p.batch_shots = 64 * mid;
+            if (run_ws_bytes(lat, &p, nullptr, false) <= kNoallocScratchBytes)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        if (lo == 0) return TC3D_EWORKSPACE;  // one word does not fit: L too large
+        p.batch_shots = 64 * lo;
+    }
+    if (run_ws_bytes(lat, &p, nullptr, false) > kNoallocScratchBytes) return TC3D_EWORKSPACE;
+    void* ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws))) return rc;
+    const Ctx c{(hipStream_t)stream, nullptr};
+    return run_impl(lat, &p, nullptr, err_state, mask_out, odd_out, ws, kNoallocScratchBytes, c);
 }
 
 // ------------------------------------------------------------ batched jobs
