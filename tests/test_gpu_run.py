@@ -261,3 +261,25 @@ def test_failing_regime_ler_parity():
     assert f_o > 0.02
     assert abs(f_g - f_o) <= 3 * sig
     assert n_div <= 1024 // 20
+
+
+def test_graph_run_equals_eager_run():
+    """TC3D_RUN_GRAPH: the whole run captured into one HIP graph equals the
+    eager run bit for bit, on three calls in a row with eager work of the
+    program between them (flip family at L = 6, and p-BP streaming and
+    resident)."""
+    import torch
+    for L, kw in ((6, dict(bp_iters=0, n_sweeps=5, pflip_mask=FFPFF)),
+                  (6, dict(bp_iters=20, n_sweeps=6, pflip_mask=PFFPFF,
+                           bp_path=tc.BP_STREAMING)),
+                  (8, dict(bp_iters=20, n_sweeps=6, pflip_mask=PFFPFF))):
+        for call in range(3):
+            S = (700, 130, 1000)[call]
+            prm = tc.make_run_params(0.04, 0.04, 4, n_shots=S, seed=30 + call, **kw)
+            m_e, odd_e, e_e, _ = gpu_run(L, prm)
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work in between
+            prm.flags = tc.RUN_GRAPH
+            m_g, odd_g, e_g, _ = gpu_run(L, prm)
+            assert float(junk) == float(junk)
+            assert np.array_equal(e_g, e_e) and np.array_equal(m_g, m_e), (L, call)
+            assert np.array_equal(odd_g, odd_e)
