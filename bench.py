@@ -337,9 +337,9 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
 
     per_class = {k: {"ms": 0.0, "launches": 0} for k in tc.KERNEL_CLASSES}
     decisions = near_ties = 0
-    fails_x = fails_any = 0
-    hist = [0] * 8  # mask histogram: bit d = logical X error on qubit d
-    ties = 0        # majority-vote ties (an axis with exactly L^2/2 odd strings)
+    # statistics stay on the device during the timed steps (no copy, no sync)
+    hist_d = torch.zeros(8, dtype=torch.int64, device="cuda")  # mask histogram
+    ties_d = torch.zeros((), dtype=torch.int64, device="cuda")  # majority-vote ties
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -351,16 +351,17 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
                 per_class[name]["launches"] += v["launches"]
             decisions += t.bp_decisions
             near_ties += t.bp_near_ties
-        m = mask.cpu()
-        fails_x += int((m & 1).ne(0).sum())
-        fails_any += int(m.ne(0).sum())
-        hb = torch.bincount(m.long(), minlength=8)
-        hist = [h + int(v) for h, v in zip(hist, hb.tolist())]
-        ties += int((2 * odd == L * L).any(dim=1).sum())
-        log(f"[bench] {tag} step {k}: "
-            f"{t.total_ms if t is not None else (time.perf_counter() - t0k) * 1e3:.1f} ms")
+        hist_d += torch.bincount(mask.long(), minlength=8)
+        ties_d += (2 * odd == L * L).any(dim=1).sum()
+        if k < 3 or k == steps - 1:
+            log(f"[bench] {tag} step {k}: "
+                f"{t.total_ms if t is not None else (time.perf_counter() - t0k) * 1e3:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    hist = hist_d.tolist()  # bit d of the index: logical X error on qubit d
+    ties = int(ties_d)
+    fails_x = sum(hist[i] for i in range(8) if i & 1)
+    fails_any = sum(hist[1:])
     if graph:  # kernel times of one eager step (the same work)
         t = one(0, False)
         for name, v in t.as_dict().items():
@@ -485,10 +486,11 @@ def run_c3(args, cfg, tc):
                                  n_shots=S, seed=1, batch_shots=min(64 * W, 32768))
         ws = tc.alloc_workspace(tc.autotune_workspace_bytes(lat, prm))
         tried = tc.autotune(lat, prm, ws, probe_cycles=1)
-        tuned[L] = (prm.bp_tile, prm.batch_shots, tried)
+        tuned[L] = dict(bp_tile=prm.bp_tile, batch_shots=prm.batch_shots, bp_path=prm.bp_path,
+                        bp_occupancy=prm.bp_occupancy, candidates=len(tried))
         del ws
-        log(f"[bench] c3 autotune L={L}: tile {prm.bp_tile} batch {prm.batch_shots} "
-            f"({len(tried)} candidates)")
+        log(f"[bench] c3 autotune L={L}: path {prm.bp_path} tile {prm.bp_tile} occupancy "
+            f"{prm.bp_occupancy} batch {prm.batch_shots} ({len(tried)} candidates)")
     specs = [(L, p) for L in cfg["Ls"] for p in cfg["ps"]]
     bufs = []
     for L, p in specs:
@@ -501,8 +503,8 @@ def run_c3(args, cfg, tc):
         out = []
         for (L, p), (e, m, o) in zip(specs, bufs):
             prm = tc.make_run_params(p, p, L, cfg["bp"], cfg["sweeps"], cfg["mask"], n_shots=S,
-                                     seed=1, shot0=64 * W * step, batch_shots=tuned[L][1],
-                                     bp_tile=tuned[L][0])
+                                     seed=1, shot0=64 * W * step,
+                                     **{k: v for k, v in tuned[L].items() if k != "candidates"})
             out.append(tc.make_job(L, prm, e, m, o))
         return out
 
@@ -537,13 +539,13 @@ def run_c3(args, cfg, tc):
     L = max(cfg["Ls"])
     lat = tc.make_lattice(L)
     prm = tc.make_run_params(0.055, 0.055, L, cfg["bp"], cfg["sweeps"], cfg["mask"], n_shots=S,
-                             seed=1, batch_shots=tuned[L][1], bp_tile=tuned[L][0])
+                             seed=1, **{k: v for k, v in tuned[L].items() if k != "candidates"})
     w1 = tc.alloc_workspace(tc.run_workspace_bytes(lat, prm))
     e, m, o = bufs[-1]
     e.zero_()
     t = tc.run_cycles_timed(lat, prm, e, m, o, w1)
     per_class = t.as_dict()
-    batch = tuned[L][1] if tuned[L][1] else 64 * W
+    batch = tuned[L]["batch_shots"] if tuned[L]["batch_shots"] else 64 * W
     roof = roofline(per_class, lat.n_edges, min(batch, 64 * W), lat.n_sites, "c3",
                     shots_padded=64 * W)
     roof["measured_on"] = f"L={L} job, p=0.055, {S} shots, timed separately"
@@ -563,7 +565,7 @@ def run_c3(args, cfg, tc):
                                f"BP{cfg['bp']} + {cfg['sched']}, one graph per step",
                    "jobs": len(specs), "shots_per_job_per_step": S, "shots_per_job": N,
                    "decoder": "plain p-BP",
-                   "autotuned": {str(L): {"bp_tile": v[0], "batch_shots": v[1]}
+                   "autotuned": {str(L): v
                                  for L, v in tuned.items()},
                    "parallelism": "jobs on 8 concurrent streams inside one HIP graph; shots "
                                   "bit-sliced 64 per word"},

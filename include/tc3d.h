@@ -265,7 +265,11 @@ typedef struct {
                                   its launches into one HIP graph, launches it
                                   and waits for it (for runs of many short
                                   launches); never changes a result          */
-    int32_t reserved;          /* zero                                           */
+    int32_t bp_occupancy;      /* workgroups per compute unit of the streaming
+                                  BP iterations that read stored messages:
+                                  0 = the library's choice (4), 1..8 = that
+                                  many (8: no cap); a tuning knob that never
+                                  changes a result                            */
 } tc3d_run_params;
 
 enum { TC3D_RUN_GRAPH = 1 };
@@ -418,19 +422,28 @@ size_t tc3d_run_jobs_workspace_bytes(const tc3d_job* jobs, int32_t n_jobs);
 int tc3d_run_jobs(const tc3d_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
                   int32_t flags, void* stream);
 
-/* Autotuning of the knobs that never change results: the BP traversal
- * (bp_tile: planes, square columns or x-row bands) and the shots decoded
- * together (batch_shots). Each candidate
- * decodes the first probe_cycles noisy cycles of *prm's shots (timed with
- * HIP events, after one untimed warm-up run) and the fastest is written back
- * into prm->bp_tile and prm->batch_shots. The candidates tried (at most
- * max_out are reported; *n_out = their number) are returned with their time.
- * Workspace: tc3d_autotune_workspace_bytes. Blocks until done. */
+/* Autotuning of the knobs that never change results, one after the other
+ * (each stage keeps the best of the previous ones):
+ *   1. the BP iteration schedule, bp_path: one launch per iteration over
+ *      messages in HBM, or (L <= 14) the whole decode in one launch per batch
+ *      with the messages in LDS;
+ *   2. the streaming traversal, bp_tile: planes, square columns or x-row
+ *      bands;
+ *   3. the streaming iterations' occupancy, bp_occupancy: 3 to 8 workgroups
+ *      per compute unit (how many sites' loads are in flight per CU);
+ *   4. the shots decoded together, batch_shots: the automatic size, 1/2, 1/4.
+ * Each candidate decodes the first probe_cycles noisy cycles of *prm's shots
+ * (timed with HIP events, after one untimed warm-up run) and the fastest is
+ * written back into *prm. The candidates tried (at most max_out are
+ * reported; *n_out = their number) are returned with their time. Workspace:
+ * tc3d_autotune_workspace_bytes. Blocks until done. */
 typedef struct {
     int32_t bp_tile;
-    int32_t reserved;
+    int32_t bp_path;
     int64_t batch_shots;
     double ms;
+    int32_t bp_occupancy;
+    int32_t reserved;
 } tc3d_tune_choice;
 size_t tc3d_autotune_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_params* prm);
 int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_cycles,

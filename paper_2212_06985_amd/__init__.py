@@ -53,7 +53,8 @@ class RunParams(ctypes.Structure):
         ("bp_tile", ctypes.c_int32), ("subset_mask", ctypes.c_uint32),
         ("bp_meta", ctypes.c_int32), ("cycle0", ctypes.c_uint32),
         ("bp_path", ctypes.c_int32), ("bp_warm", ctypes.c_int32),
-        ("bp_damp", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+        ("bp_damp", ctypes.c_double), ("flags", ctypes.c_uint32),
+        ("bp_occupancy", ctypes.c_int32),
     ]
 
 
@@ -75,8 +76,9 @@ class Job(ctypes.Structure):
 
 
 class TuneChoice(ctypes.Structure):
-    _fields_ = [("bp_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("batch_shots", ctypes.c_int64), ("ms", ctypes.c_double)]
+    _fields_ = [("bp_tile", ctypes.c_int32), ("bp_path", ctypes.c_int32),
+                ("batch_shots", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bp_occupancy", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 JOBS_CONCURRENT = 1
@@ -417,7 +419,8 @@ __all__ += ["cnn_param_count", "cnn_packed_bytes", "cnn_pack", "cnn_workspace_by
 def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots, seed=1,
                     shot0=0, p_dec=None, q_dec=None, perfect_final=1, final_qubit_noise=1,
                     batch_shots=0, bp_tile=0, subset_mask=0, bp_meta=0, cycle0=0,
-                    bp_path=BP_AUTO, bp_warm=0, bp_damp=0.0, flags=0) -> RunParams:
+                    bp_path=BP_AUTO, bp_warm=0, bp_damp=0.0, flags=0,
+                    bp_occupancy=0) -> RunParams:
     return RunParams(p=p, q=q, p_dec=p if p_dec is None else p_dec,
                      q_dec=q if q_dec is None else q_dec, noisy_cycles=noisy_cycles,
                      perfect_final=perfect_final, final_qubit_noise=final_qubit_noise,
@@ -425,7 +428,7 @@ def make_run_params(p, q, noisy_cycles, bp_iters, n_sweeps, pflip_mask, n_shots,
                      shot0=shot0, n_shots=n_shots, batch_shots=batch_shots, bp_tile=bp_tile,
                      subset_mask=subset_mask, bp_meta=int(bp_meta), cycle0=int(cycle0),
                      bp_path=int(bp_path), bp_warm=int(bp_warm), bp_damp=float(bp_damp),
-                     flags=int(flags))
+                     flags=int(flags), bp_occupancy=int(bp_occupancy))
 
 
 __all__.append("make_run_params")
@@ -468,15 +471,18 @@ def autotune_workspace_bytes(lat, prm: RunParams) -> int:
 
 
 def autotune(lat, prm: RunParams, ws, probe_cycles=2, stream=None):
-    """Times the candidate (bp_tile, batch_shots) settings on the first
-    probe_cycles cycles of prm's shots and writes the fastest into prm.
-    Returns the list of (bp_tile, batch_shots, ms) tried."""
+    """Times candidate settings of the knobs that never change results (BP
+    schedule, traversal tile, occupancy, batch) on the first probe_cycles
+    cycles of prm's shots and writes the fastest into prm. Returns the list of
+    dicts {bp_path, bp_tile, bp_occupancy, batch_shots, ms} tried."""
     out = (TuneChoice * 64)()
     n = ctypes.c_int32(0)
     _check(lib().tc3d_autotune(ctypes.byref(lat), ctypes.byref(prm), int(probe_cycles), _ptr(ws),
                                ws.numel() * ws.element_size(), out, 64, ctypes.byref(n),
                                _stream(stream)), "autotune")
-    return [(out[i].bp_tile, out[i].batch_shots, out[i].ms) for i in range(min(n.value, 64))]
+    return [dict(bp_path=out[i].bp_path, bp_tile=out[i].bp_tile,
+                 bp_occupancy=out[i].bp_occupancy, batch_shots=out[i].batch_shots,
+                 ms=out[i].ms) for i in range(min(n.value, 64))]
 
 
 __all__ += ["Job", "TuneChoice", "JOBS_CONCURRENT", "JOBS_GRAPH", "make_job",

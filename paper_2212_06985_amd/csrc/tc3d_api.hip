@@ -215,6 +215,7 @@ BpArgs make_bp_args(CPlane syn, const float* llr0, float l0, float K, int64_t nw
     a.path = path;
     a.ties = nullptr;
     a.damp = damp;
+    a.occupancy = 0;
     return a;
 }
 
@@ -236,7 +237,8 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
     if ((prm->bp_warm || prm->bp_damp > 0.0) && prm->bp_meta) return TC3D_EINVAL;
     // a warm start continues from stored messages, which one iteration never writes
     if (prm->bp_warm && prm->bp_iters == 1) return TC3D_EINVAL;
-    if ((prm->flags & ~(uint32_t)TC3D_RUN_GRAPH) != 0 || prm->reserved != 0) return TC3D_EINVAL;
+    if ((prm->flags & ~(uint32_t)TC3D_RUN_GRAPH) != 0) return TC3D_EINVAL;
+    if (prm->bp_occupancy < 0 || prm->bp_occupancy > 8) return TC3D_EINVAL;
     // cycle indices of this call stay below 2^32
     if ((uint64_t)prm->cycle0 + (uint64_t)prm->noisy_cycles + 1 > 0xffffffffull)
         return TC3D_EINVAL;
@@ -408,9 +410,9 @@ int run_impl(const tc3d_lattice* lat, const tc3d_run_params* prm, const void* pa
                                           (double*)nu0, (double*)nu1, C, nullptr)))
                         return rc;
                 } else {
-                    const BpArgs a = make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw,
-                                                  prm->bp_tile, prm->bp_path,
-                                                  (float)prm->bp_damp);
+                    BpArgs a = make_bp_args(cS, cnn ? llr : nullptr, l0, K, bw, prm->bp_tile,
+                                            prm->bp_path, (float)prm->bp_damp);
+                    a.occupancy = prm->bp_occupancy;
                     if ((rc = bp_run(c, g, a, prm->bp_iters, nu0, nu1, C, nullptr, warm,
                                      prm->bp_warm ? &warm : nullptr)))
                         return rc;
@@ -1004,6 +1006,7 @@ size_t tc3d_autotune_workspace_bytes(const tc3d_lattice* lat, const tc3d_run_par
     if (!lattice_ok(lat) || !prm || check_run(lat, prm) || prm->n_shots <= 0) return 0;
     tc3d_run_params p = *prm;
     p.batch_shots = 0;
+    p.bp_path = TC3D_BP_STREAMING;  // the candidate that needs the most
     return plane_bytes(lat, words_of(prm->n_shots)) + round_up((size_t)prm->n_shots, 256) +
            round_up(run_ws_bytes(lat, &p, nullptr, false), 256);
 }
@@ -1031,48 +1034,74 @@ int tc3d_autotune(const tc3d_lattice* lat, tc3d_run_params* prm, int32_t probe_c
     probe.noisy_cycles = probe_cycles;
     probe.perfect_final = 0;
     probe.batch_shots = 0;
-    int64_t nb_auto = 0;
-    (void)run_ws_bytes(lat, &probe, &nb_auto, false);
-    // candidates: traversal tiles, then batches of the automatic size, 1/2, 1/4
-    std::vector<int32_t> tiles{0};
-    if (prm->bp_iters > 0 && !prm->bp_meta)
-        for (int32_t t : {4, 8, 12, 16, 24, 32, -4, -8, -12, -16})
-            if ((t < 0 ? -t : t) < lat->L) tiles.push_back(t);
-    std::vector<int64_t> batches;
-    for (int64_t b : {nb_auto, nb_auto / 2, nb_auto / 4})
-        if (b >= 1 && (batches.empty() || b != batches.back())) batches.push_back(b);
+    probe.flags = 0;
     const Ctx plain{st, nullptr};
     // warm-up (first launches, code-object loading)
     if ((rc = launch_clear(plain, Plane{err, W}, lat->n_edges, W))) return rc;
     if ((rc = run_impl(lat, &probe, nullptr, err, mask, nullptr, rws, rws_bytes, plain)))
         return rc;
-    double best = 1e300;
-    int32_t best_tile = prm->bp_tile;
-    int64_t best_batch = prm->batch_shots;
     int32_t n = 0;
-    for (int64_t b : batches) {
-        for (int32_t t : tiles) {
-            probe.bp_tile = t;
-            probe.batch_shots = 64 * b;
-            if ((rc = launch_clear(plain, Plane{err, W}, lat->n_edges, W))) return rc;
-            Timer tm(st);
-            const Ctx c{st, &tm};
-            if ((rc = run_impl(lat, &probe, nullptr, err, mask, nullptr, rws, rws_bytes, c)))
-                return rc;
-            tc3d_timing tmg;
-            if ((rc = tm.finish(&tmg))) return rc;
-            if (n < max_out) out[n] = tc3d_tune_choice{t, 0, 64 * b, tmg.total_ms};
-            ++n;
-            if (tmg.total_ms < best) {
-                best = tmg.total_ms;
-                best_tile = t;
-                best_batch = 64 * b;
-            }
+    double best = 1e300;
+    tc3d_run_params best_prm = probe;
+    // times one candidate; keeps it when it is the fastest so far
+    auto trial = [&](const tc3d_run_params& cand) -> int {
+        if (run_ws_bytes(lat, &cand, nullptr, false) > rws_bytes) return TC3D_OK;  // skip
+        int r = launch_clear(plain, Plane{err, W}, lat->n_edges, W);
+        if (r) return r;
+        Timer tm(st);
+        const Ctx c{st, &tm};
+        if ((r = run_impl(lat, &cand, nullptr, err, mask, nullptr, rws, rws_bytes, c))) return r;
+        tc3d_timing tmg;
+        if ((r = tm.finish(&tmg))) return r;
+        if (n < max_out)
+            out[n] = tc3d_tune_choice{cand.bp_tile, cand.bp_path, cand.batch_shots, tmg.total_ms,
+                                      cand.bp_occupancy, 0};
+        ++n;
+        if (tmg.total_ms < best) {
+            best = tmg.total_ms;
+            best_prm = cand;
+        }
+        return TC3D_OK;
+    };
+    const bool bp = prm->bp_iters > 0 && !prm->bp_meta;
+    // 1. the BP iteration schedule: resident decode or streaming iterations
+    tc3d_run_params cand = probe;
+    if (bp && run_bp_resident(lat, &probe, false)) {
+        for (int32_t path : {TC3D_BP_AUTO, TC3D_BP_STREAMING}) {
+            cand.bp_path = path;
+            if ((rc = trial(cand))) return rc;
+        }
+    } else {
+        if ((rc = trial(cand))) return rc;
+    }
+    // 2.-3. the streaming kernels' traversal and occupancy
+    if (bp && !run_bp_resident(lat, &best_prm, false)) {
+        cand = best_prm;
+        for (int32_t t : {4, 8, 12, 16, 24, 32, -4, -8, -12, -16}) {
+            if ((t < 0 ? -t : t) >= lat->L) continue;
+            cand.bp_tile = t;
+            if ((rc = trial(cand))) return rc;
+        }
+        cand = best_prm;
+        for (int32_t occ : {3, 5, 6, 8}) {
+            cand.bp_occupancy = occ;
+            if ((rc = trial(cand))) return rc;
         }
     }
+    // 4. the batch
+    int64_t nb_auto = 0;
+    (void)run_ws_bytes(lat, &best_prm, &nb_auto, false);
+    cand = best_prm;
+    for (int64_t b : {nb_auto / 2, nb_auto / 4}) {
+        if (b < 1 || b == nb_auto) continue;
+        cand.batch_shots = 64 * b;
+        if ((rc = trial(cand))) return rc;
+    }
     if (n_out) *n_out = n;
-    prm->bp_tile = best_tile;
-    prm->batch_shots = best_batch;
+    prm->bp_tile = best_prm.bp_tile;
+    prm->bp_path = best_prm.bp_path;
+    prm->bp_occupancy = best_prm.bp_occupancy;
+    prm->batch_shots = best_prm.batch_shots ? best_prm.batch_shots : 64 * nb_auto;
     return TC3D_OK;
 }
 

@@ -547,6 +547,7 @@ static constexpr int kLoadPostBlocksPerCu = 6;
 static std::atomic<int> g_cu_lds[64];
 
 static size_t residency_lds(int blocks_per_cu) {
+    if (blocks_per_cu >= 8) return 0;  // no cap: the registers allow 8
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
     int per_cu = g_cu_lds[dev].load(std::memory_order_relaxed);
@@ -572,7 +573,8 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (rc) return rc;
     const Src S = make_src(g, a, nu_in);
     const dim3 grid((unsigned)blocks), block(kBlock);
-    const size_t lds = mode == NU_LOAD ? residency_lds(kLoadIterBlocksPerCu) : 0;
+    const size_t lds =
+        mode == NU_LOAD ? residency_lds(a.occupancy ? a.occupancy : kLoadIterBlocksPerCu) : 0;
     const float damp = a.damp;
     if (a.llr0) {
         if (damp != 0.0f) return TC3D_EINVAL;  // damping goes with the scalar prior

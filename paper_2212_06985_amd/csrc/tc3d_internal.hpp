@@ -109,6 +109,7 @@ struct BpArgs {
     int path;            // TC3D_BP_AUTO / _STREAMING / _RESIDENT
     unsigned long long* ties;  // device counter of posteriors |l| < 1e-3, or nullptr
     float damp;          // damping g: nu = (1 - g) nu_new + g nu_old (0: none)
+    int occupancy;       // workgroups per CU of the stored-message iterations (0: default)
 };
 
 // Fills the derived fields of BpArgs (in double precision, then rounded).

@@ -69,11 +69,13 @@ def decoder_params(decoder: str, n_a: int = 1, lambda_p: int = 0, bp_iters: int 
 
 def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=0,
                bp_iters=None, chunk_shots=None, shot0=0, q_dec=None, schedule=None, bp_meta=0,
-               cnn_weights=None, beta=0.5):
+               cnn_weights=None, beta=0.5, bp_warm=0, bp_damp=0.0):
     """Logical error statistics of `shots` independent memory runs.
 
     cnn_weights: path of a trained network (.npy); BP then starts from its
     per-edge prior, blended with the channel prior at strength beta.
+    bp_warm, bp_damp: readings of BP the paper leaves open (a warm start from
+    the previous cycle's messages; damped messages), both off by default.
     Returns the mask histogram (index = bit x | bit y << 1 | bit z << 2), the
     per-axis failure counts, the majority-vote ties and the GPU time."""
     import torch
@@ -102,7 +104,8 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
         n = min(chunk, shots - done)
         prm = tc.make_run_params(p, p, cycles, it, ns, mask_bits, n_shots=n, seed=seed,
                                  shot0=shot0 + done, perfect_final=0, q_dec=q_dec,
-                                 subset_mask=sub_bits, bp_meta=bp_meta)
+                                 subset_mask=sub_bits, bp_meta=bp_meta, bp_warm=bp_warm,
+                                 bp_damp=bp_damp)
         need = (tc.run_workspace_bytes(lat, prm) if packed is None
                 else tc.run_cnn_workspace_bytes(lat, prm))
         if ws is None or ws.numel() < need:
@@ -122,6 +125,7 @@ def memory_run(L, p, cycles, decoder="pbp", shots=4096, seed=1, n_a=1, lambda_p=
             "lambda_p": lambda_p, "bp_iters": it, "shots": shots, "seed": seed,
             "q_dec": p if q_dec is None else q_dec, "schedule": schedule, "bp_meta": bp_meta,
             "cnn_weights": cnn_weights, "beta": beta if cnn_weights else None,
+            "bp_warm": bp_warm, "bp_damp": bp_damp,
             "hist": hist.tolist(), "fails": fails, "ties": ties, "gpu_ms": ms,
             "qubit_cycles_per_s": 3 * L ** 3 * cycles * shots / (ms * 1e-3)}
 
@@ -189,13 +193,15 @@ def correlations(counts):
     return {"n": n, "rate": rate, "expected": expected, "ratio": ratio}
 
 
-def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec=None):
+def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec=None,
+           bp_warm=0, bp_damp=0.0):
     """Logical error configurations after 500 cycles of p-BP at L = 14,
     p = q = 0.0544, next to the paper's counts out of 1000 (Table 2).
     bp_iters and q_dec change the BP the decoder runs (default: 20 iterations,
     measurement-error rate q_dec = p)."""
     from scipy.stats import chi2_contingency
-    r = memory_run(L, p, cycles, "pbp", shots, seed, bp_iters=bp_iters, q_dec=q_dec)
+    r = memory_run(L, p, cycles, "pbp", shots, seed, bp_iters=bp_iters, q_dec=q_dec,
+                   bp_warm=bp_warm, bp_damp=bp_damp)
     ours = {format(k & 1, "d") + format((k >> 1) & 1, "d") + format((k >> 2) & 1, "d"):
             int(r["hist"][k]) for k in range(8)}
     keys = list(TABLE2_COUNTS)
@@ -208,14 +214,15 @@ def table2(shots=16384, seed=1, L=14, p=0.0544, cycles=500, bp_iters=None, q_dec
 
 def threshold(decoder, Ls, ps, cycles, shots, seed=1, n_a=1, lambda_p=0, bp_iters=None,
               pooled=False, log=print, q_dec=None, schedule=None, bp_meta=0, cnn_weights=None,
-              beta=0.5):
+              beta=0.5, bp_warm=0, bp_damp=0.0):
     rows = []
     for L in Ls:
         for p in ps:
             t0 = time.perf_counter()
             r = memory_run(L, p, cycles, decoder, shots, seed, n_a, lambda_p, bp_iters,
                            q_dec=q_dec, schedule=schedule, bp_meta=bp_meta,
-                           cnn_weights=cnn_weights, beta=beta)
+                           cnn_weights=cnn_weights, beta=beta, bp_warm=bp_warm,
+                           bp_damp=bp_damp)
             f, s = pfail_pooled(r) if pooled else pfail(r)
             r["pfail"], r["pfail_sigma"] = f, s
             rows.append(r)
@@ -249,6 +256,11 @@ def main():
     t2.add_argument("--q-dec", type=float, default=None,
                     help="measurement-error rate BP assumes (default: q = p)")
     th = sub.add_parser("threshold")
+    for a in (t2, th):
+        a.add_argument("--bp-warm", action="store_true",
+                       help="BP starts each cycle from the previous cycle's messages")
+        a.add_argument("--bp-damp", type=float, default=0.0,
+                       help="damping g of the BP messages: (1 - g) new + g old")
     th.add_argument("--decoder", choices=["flip", "bp", "pbp"], default="pbp")
     th.add_argument("--n-a", type=int, default=1)
     th.add_argument("--lambda-p", type=int, default=0)
@@ -275,15 +287,18 @@ def main():
     args = ap.parse_args()
     if args.cmd == "table2":
         print(json.dumps(table2(args.shots, args.seed, p=args.p, bp_iters=args.bp_iters,
-                                q_dec=args.q_dec)), flush=True)
+                                q_dec=args.q_dec, bp_warm=int(args.bp_warm),
+                                bp_damp=args.bp_damp)), flush=True)
         return
     res = threshold(args.decoder, args.L, args.p, args.cycles, args.shots, args.seed, args.n_a,
                     args.lambda_p, args.bp_iters, args.pooled,
                     log=lambda m: print(m, flush=True), q_dec=args.q_dec,
                     schedule=args.schedule, bp_meta=int(args.bp_meta),
-                    cnn_weights=args.cnn_weights, beta=args.beta)
+                    cnn_weights=args.cnn_weights, beta=args.beta, bp_warm=int(args.bp_warm),
+                    bp_damp=args.bp_damp)
     print(json.dumps({"fit": res["fit"], "decoder": res["decoder"], "n_a": res["n_a"],
                       "schedule": args.schedule, "bp_meta": bool(args.bp_meta),
+                      "bp_warm": bool(args.bp_warm), "bp_damp": args.bp_damp,
                       "lambda_p": res["lambda_p"], "cycles": res["cycles"]}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

@@ -83,21 +83,32 @@ def test_jobs_equal_single_runs(flags):
         _ = torch.ones(1 << 20, device="cuda").sum().item()  # unrelated eager work
 
 
-def test_autotune_choices_decode_identically():
+@pytest.mark.parametrize("L,S", [(12, 512), (16, 256)])
+def test_autotune_choices_decode_identically(L, S):
+    """Every candidate the tuner tried (BP schedule, traversal tile,
+    occupancy, batch) decodes the run bit for bit like the others, and the
+    choice written back is one of them."""
     import torch
-    L, S = 12, 512
     lat = tc.make_lattice(L)
     prm = tc.make_run_params(0.05, 0.05, 4, 20, 6, 0b001001, n_shots=S, seed=11)
     ws = tc.alloc_workspace(tc.autotune_workspace_bytes(lat, prm))
     tried = tc.autotune(lat, prm, ws, probe_cycles=1)
-    announce(f"  autotune tried {len(tried)}: " +
-             ", ".join(f"tile {t} batch {b}: {ms:.2f} ms" for t, b, ms in tried))
-    assert len(tried) >= 2
-    assert (prm.bp_tile, prm.batch_shots) in [(t, b) for t, b, _ in tried]
+    announce(f"  autotune L={L} tried {len(tried)}: " + ", ".join(
+        f"path {c['bp_path']} tile {c['bp_tile']} occ {c['bp_occupancy']} batch "
+        f"{c['batch_shots']}: {c['ms']:.2f} ms" for c in tried))
+    assert len(tried) >= 4
+    keys = ("bp_path", "bp_tile", "bp_occupancy")
+    chosen = tuple(getattr(prm, k) for k in keys)
+    assert chosen in [tuple(c[k] for k in keys) for c in tried]
+    if L == 16:  # beyond the resident decode: tiles and occupancies were tried
+        assert len({c["bp_tile"] for c in tried}) > 3
+        assert len({c["bp_occupancy"] for c in tried}) > 3
+    else:
+        assert {c["bp_path"] for c in tried} == {tc.BP_AUTO, tc.BP_STREAMING}
     results = []
-    for t, b, _ in tried:
+    for c in tried:
         p2 = tc.make_run_params(0.05, 0.05, 4, 20, 6, 0b001001, n_shots=S, seed=11,
-                                batch_shots=b, bp_tile=t)
+                                **{k: c[k] for k in keys + ("batch_shots",)})
         e, m, o = _buffers(L, S)
         w2 = tc.alloc_workspace(tc.run_workspace_bytes(lat, p2))
         tc.run_cycles(lat, p2, e, m, o, w2)
