@@ -301,7 +301,8 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
         p = cfg["ps"][step % len(cfg["ps"])]
         return tc.make_run_params(p, p, cfg["noisy"], cfg["bp"], cfg["sweeps"], cfg["mask"],
                                   n_shots=S, seed=1, shot0=64 * W * step, batch_shots=batch,
-                                  bp_tile=bp_tile, flags=tc.RUN_GRAPH if graph else 0)
+                                  bp_tile=bp_tile, flags=tc.RUN_GRAPH if graph else 0,
+                                  **RUN_KNOBS)
 
     nps = len(cfg["ps"])
     packs = [cnn_packed(p, beta, weights) for p in cfg["ps"]] if cnn else [None] * nps
@@ -387,22 +388,38 @@ def run_decoder(tc, lat, cfg, decoder, steps, warmup, S, batch, bp_tile, beta, w
     return wall, per_class, ler, resid
 
 
-def path_roofline(bp_iters, value, per_edge_prior=False, n_sites=None):
+def bp_message_bytes(bp_iters, per_edge_prior=False, fused=True):
+    """HBM bytes of BP messages per qubit and decode (4 FP32 messages = 16 B
+    per pass). Scalar prior: iteration 1 is implied by the syndrome, so
+    iteration 2 only writes, iterations 3..T read and write and the posterior
+    reads; fused, iteration T and the posterior are one pass that reads once.
+    Per-edge prior: the first iteration writes, every later one reads and
+    writes, the posterior reads, and every iteration reads the 4-byte prior."""
+    T = bp_iters
+    if T <= 0:
+        return 0.0
+    if per_edge_prior:
+        return 20.0 + 36.0 * (T - 1) + 16.0
+    if T == 1:
+        return 0.0
+    split = 16.0 + 32.0 * (T - 2) + 16.0
+    return split - 32.0 if fused else split
+
+
+def path_roofline(bp_iters, value, per_edge_prior=False, n_sites=None, fused=True):
     """Whole-path HBM model: algorithmic bytes per decoded qubit-cycle times the
-    qubit-cycles/s, against the HBM peak. Per qubit and cycle, BP streams its
-    four FP32 messages once per iteration (written by the first, read and
-    written by the others, read by the posterior: 32 B per iteration) and one
-    syndrome bit per iteration; with a per-edge prior each iteration also reads
-    the 4-byte prior. The bit planes (noise, syndrome, correction, sweeps,
-    apply) add about 32 bits. None without BP, where the path is bound by
-    integer ALU work and launches, and where the decode runs resident in LDS
-    (at most RESIDENT_MAX_SITES sites, scalar prior): its messages never reach
-    HBM, and the BP roofline (ALU) is the one that applies."""
+    qubit-cycles/s, against the HBM peak. Per qubit and cycle: BP's message
+    passes (bp_message_bytes), one syndrome bit per iteration and about 32 bits
+    of bit planes (noise, syndrome, correction, sweeps, apply). None without
+    BP, where the path is bound by integer ALU work and launches, and where the
+    decode runs resident in LDS (at most RESIDENT_MAX_SITES sites, scalar
+    prior): its messages never reach HBM, and the BP roofline (ALU) is the one
+    that applies."""
     if not bp_iters:
         return None
     if n_sites is not None and n_sites <= RESIDENT_MAX_SITES and not per_edge_prior:
         return None
-    per_unit = (32.0 + (4.0 if per_edge_prior else 0.0)) * bp_iters + bp_iters / 8.0 + 4.0
+    per_unit = bp_message_bytes(bp_iters, per_edge_prior, fused) + bp_iters / 8.0 + 4.0
     achieved = value * per_unit / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_unit": per_unit,
@@ -581,6 +598,11 @@ def run_c3(args, cfg, tc):
     }
 
 
+# kernel choices that never change a result (--bp-path, --bp-occupancy)
+RUN_KNOBS = {}
+BP_PATHS = {"auto": 0, "streaming": 1, "resident": 2, "split": 3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -591,6 +613,12 @@ def main():
     ap.add_argument("--shots", type=int, default=None, help="shots per step")
     ap.add_argument("--batch-shots", type=int, default=0)
     ap.add_argument("--bp-tile", type=int, default=0, help="BP traversal tile (0: auto)")
+    ap.add_argument("--bp-path", choices=sorted(BP_PATHS), default="auto",
+                    help="BP kernels: resident where it fits (auto), streaming with the last "
+                         "iteration fused into the posterior, resident, or split (the last "
+                         "iteration and the posterior launched separately)")
+    ap.add_argument("--bp-occupancy", type=int, default=0,
+                    help="workgroups per CU of the streaming BP iterations (0: default)")
     ap.add_argument("--noisy-cycles", type=int, default=None,
                     help="override the workload's noisy cycles (short counter runs)")
     ap.add_argument("--decoder", choices=["plain", "cnn"], default=None,
@@ -611,6 +639,7 @@ def main():
     ap.add_argument("--copy-calibrate", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter scaling)")
     args = ap.parse_args()
+    RUN_KNOBS.update(bp_path=BP_PATHS[args.bp_path], bp_occupancy=args.bp_occupancy)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (shots "
@@ -739,12 +768,12 @@ def main():
                                f"{' with the CNN prior' if decoder == 'cnn' else ''}",
                    "L": L, "shots_per_step": S, "batch_shots": batch, "shots_total": S * steps,
                    "cycles": cycles, "bp_iters": main_cfg["bp"], "schedule": cfg["sched"],
-                   "decoder": dec_name, "graph": graph,
+                   "decoder": dec_name, "graph": graph, "bp_path": args.bp_path,
                    "parallelism": "shots (bit-sliced 64 per word; one lane per shot in BP)"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "path_roofline": path_roofline(main_cfg["bp"], value, per_edge_prior=decoder == "cnn",
-                                       n_sites=lat.n_sites),
+                                       n_sites=lat.n_sites, fused=args.bp_path != "split"),
         "ler": ler,
         "mean_residual_syndrome": resid,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in per_class.items()},

@@ -152,12 +152,21 @@ size_t tc3d_bp_workspace_bytes(const tc3d_lattice* lat, int64_t n_shots);
  * +-40 nats).
  * bp_path picks the kernels; it never changes a result:
  *   TC3D_BP_AUTO       the resident kernel where it applies, else streaming;
- *   TC3D_BP_STREAMING  one launch per iteration over messages in HBM;
+ *   TC3D_BP_STREAMING  one launch per iteration over messages in HBM; with
+ *                      the scalar prior the last iteration and the posterior
+ *                      (E4) share one launch that stores no messages;
  *   TC3D_BP_RESIDENT   the whole decode of each shot inside one workgroup,
  *                      its messages in LDS: scalar prior and at most 3072
- *                      sites (L <= 14), else EINVAL. Bit-identical to the
- *                      streaming kernels. */
-enum { TC3D_BP_AUTO = 0, TC3D_BP_STREAMING = 1, TC3D_BP_RESIDENT = 2 };
+ *                      sites (L <= 14), else EINVAL;
+ *   TC3D_BP_STREAMING_SPLIT  as STREAMING, with the last iteration and the
+ *                      posterior launched separately.
+ * All four are bit-identical. */
+enum {
+    TC3D_BP_AUTO = 0,
+    TC3D_BP_STREAMING = 1,
+    TC3D_BP_RESIDENT = 2,
+    TC3D_BP_STREAMING_SPLIT = 3
+};
 int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots,
                    const float* llr0, float llr0_scalar, float meas_factor, int32_t iters,
                    int32_t bp_path, uint64_t* corr_out, float* post_out, void* ws,
@@ -250,8 +259,9 @@ typedef struct {
                                   after cycle k and resumed from its residual
                                   err_state with cycle0 = k equals the unsplit
                                   run bit for bit                             */
-    int32_t bp_path;           /* TC3D_BP_AUTO / _STREAMING / _RESIDENT (see
-                                  tc3d_bp_decode); never changes a result     */
+    int32_t bp_path;           /* TC3D_BP_AUTO / _STREAMING / _RESIDENT /
+                                  _STREAMING_SPLIT (see tc3d_bp_decode);
+                                  never changes a result                      */
     int32_t bp_warm;           /* 1: BP of every cycle but the call's first
                                   starts from the messages the previous
                                   cycle's BP ended with, 0: from the priors

@@ -22,6 +22,7 @@ __all__ = [
     "bp_decode", "bp_step", "logical_check", "run_workspace_bytes", "run_cycles",
     "run_cycles_timed", "n_words", "alloc_plane", "alloc_workspace", "KERNEL_CLASSES",
     "logical_check_workspace_bytes", "built_id", "BP_AUTO", "BP_STREAMING", "BP_RESIDENT",
+    "BP_STREAMING_SPLIT",
     "run_cycles_noalloc", "apply_correction", "RUN_GRAPH",
 ]
 
@@ -91,6 +92,7 @@ RUN_GRAPH = 1
 BP_AUTO = 0
 BP_STREAMING = 1
 BP_RESIDENT = 2
+BP_STREAMING_SPLIT = 3
 
 _lib = None
 

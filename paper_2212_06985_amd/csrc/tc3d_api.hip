@@ -179,7 +179,11 @@ int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, 
         nb ^= 1;
         mode = NU_LOAD;
     }
-    for (int32_t it = first; it <= iters; ++it) {
+    // the last iteration and the posterior in one pass, unless the caller
+    // keeps the final messages or asks for the two launches
+    const bool fuse = a.path != TC3D_BP_STREAMING_SPLIT && bp_final_fits(g, a) &&
+                      !final_state && iters >= first;
+    for (int32_t it = first; it <= iters - (fuse ? 1 : 0); ++it) {
         rc = launch_bp_iter(c, g, a, mode, cur, bufs[nb],
                             mode == NU_SIGMA ? TC3D_K_BP_FIRST : TC3D_K_BP_ITER);
         if (rc) return rc;
@@ -187,6 +191,7 @@ int bp_run(const Ctx& c, Geo g, const BpArgs& args, int32_t iters, float* buf0, 
         nb ^= 1;
         mode = NU_LOAD;
     }
+    if (fuse) return launch_bp_final(c, g, a, mode, cur, corr, post);
     if (final_state) *final_state = mode == NU_LOAD ? cur : nullptr;
     return launch_bp_post(c, g, a, mode, cur, corr, post);
 }
@@ -230,7 +235,7 @@ int check_run(const tc3d_lattice* lat, const tc3d_run_params* prm) {
         return TC3D_EINVAL;
     if (prm->perfect_final != 0 && prm->perfect_final != 1) return TC3D_EINVAL;
     if (prm->bp_meta != 0 && prm->bp_meta != 1) return TC3D_EINVAL;
-    if (prm->bp_path < TC3D_BP_AUTO || prm->bp_path > TC3D_BP_RESIDENT) return TC3D_EINVAL;
+    if (prm->bp_path < TC3D_BP_AUTO || prm->bp_path > TC3D_BP_STREAMING_SPLIT) return TC3D_EINVAL;
     if (prm->bp_warm != 0 && prm->bp_warm != 1) return TC3D_EINVAL;
     if (!(prm->bp_damp >= 0.0 && prm->bp_damp < 1.0)) return TC3D_EINVAL;
     // the readings of BP as damped or warm-started apply to the paper's BP
@@ -268,7 +273,8 @@ size_t llr_bytes(const tc3d_lattice* lat, int64_t nw) {
 // The paper's BP decoded by the resident kernel keeps its messages in LDS
 // and needs no BP state in the workspace.
 bool run_bp_resident(const tc3d_lattice* lat, const tc3d_run_params* prm, bool cnn) {
-    return prm->bp_iters > 0 && !prm->bp_meta && !cnn && prm->bp_path != TC3D_BP_STREAMING &&
+    return prm->bp_iters > 0 && !prm->bp_meta && !cnn &&
+           (prm->bp_path == TC3D_BP_AUTO || prm->bp_path == TC3D_BP_RESIDENT) &&
            !prm->bp_warm && prm->bp_damp == 0.0 && bp_resident_fits(geo_of(lat), nullptr, 1);
 }
 
@@ -641,7 +647,7 @@ int tc3d_bp_decode(const tc3d_lattice* lat, const uint64_t* syn, int64_t n_shots
                    int32_t bp_path, uint64_t* corr_out, float* post_out, void* ws,
                    size_t ws_bytes, void* stream) {
     if (!lattice_ok(lat) || n_shots < 0 || iters < 1 || !bp_scalars_ok(llr0_scalar, meas_factor) ||
-        bp_path < TC3D_BP_AUTO || bp_path > TC3D_BP_RESIDENT)
+        bp_path < TC3D_BP_AUTO || bp_path > TC3D_BP_STREAMING_SPLIT)
         return TC3D_EINVAL;
     if (bp_path == TC3D_BP_RESIDENT && !bp_resident_fits(geo_of(lat), llr0, 1)) return TC3D_EINVAL;
     if (n_shots == 0) return TC3D_OK;

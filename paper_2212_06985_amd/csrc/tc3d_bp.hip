@@ -371,6 +371,205 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
     }
 }
 
+// ------------------------------------------- last iteration with the posterior
+// The decision after iteration T needs, for each edge of site v, only the four
+// messages that iteration sends into the edge (E4): from two faces of v and
+// from one face each of v - unit(d) for the two other axes d. So iteration T
+// and the posterior can be one pass over the state of iteration T - 1: a
+// wavefront evaluates the check rule of v's three faces and, for the single
+// member it needs, of the six faces f(v-x, 1), f(v-x, 2), f(v-y, 0),
+// f(v-y, 2), f(v-z, 0), f(v-z, 1), each with its inputs formed by the same
+// products in the same order as k_bp_iter forms them at the face's own site.
+// The decision and posterior are bit-identical to k_bp_iter followed by
+// k_bp_post, while iteration T's messages (16 B per edge and shot) are
+// neither written nor read back; the price is about twice the loads, which
+// L2 serves, and the check rules of six more faces. Scalar prior, undamped.
+
+// Sites v + (dx, dy, dz), -2 <= d <= 1, as index and as byte offset of the
+// site's message rows inside one shot word (12 rows of 256 B). The wrapped
+// coordinates and their scaled forms are formed once per wavefront, so a
+// site costs two scalar adds per form.
+struct Site {
+    int v;
+    uint32_t off;
+};
+
+struct Pos {
+    int xs[4], ys[4], zs[4];        // wrapped coordinate c + d at [d + 2]
+    int yl[4], zl[4];               // L y', L^2 z'
+    uint32_t xo[4], yo[4], zo[4];   // byte offsets 3072 x', 3072 L y', 3072 L^2 z'
+};
+
+__device__ __forceinline__ int wrap(int t, int L) { return t < 0 ? t + L : (t >= L ? t - L : t); }
+
+__device__ __forceinline__ Pos pos_of_xy(int x, int y, int L) {
+    Pos p;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        p.xs[d] = wrap(x + d - 2, L);
+        p.ys[d] = wrap(y + d - 2, L);
+        p.yl[d] = L * p.ys[d];
+        p.xo[d] = 3072u * (uint32_t)p.xs[d];
+        p.yo[d] = 3072u * (uint32_t)p.yl[d];
+    }
+    return p;
+}
+
+__device__ __forceinline__ void set_z(Pos& p, int z, int L) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        p.zs[d] = wrap(z + d - 2, L);
+        p.zl[d] = L * L * p.zs[d];
+        p.zo[d] = 3072u * (uint32_t)p.zl[d];
+    }
+}
+
+__device__ __forceinline__ Site at(const Pos& p, int dx, int dy, int dz) {
+    return Site{p.xs[dx + 2] + p.yl[dy + 2] + p.zl[dz + 2],
+                p.xo[dx + 2] + p.yo[dy + 2] + p.zo[dz + 2]};
+}
+
+// Message loads of one shot word through a buffer resource: the site's byte
+// offset is the wave-uniform scalar offset, the lane's the vector offset and
+// the slot's the instruction's immediate. Needs L^3 * 3072 < 2^32 (L <= 111).
+struct BufReader {
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane4;
+    __device__ __forceinline__ float operator()(int slot, const Site& s) const {
+        return __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane4 + (uint32_t)slot * 256u, s.off, 0));
+    }
+};
+
+// The plain reader by site index (NU_SIGMA: the first iteration's messages
+// from the syndrome).
+template <int MODE>
+struct IdxReader {
+    Reader<MODE> R;
+    __device__ __forceinline__ float operator()(int slot, const Site& s) const {
+        return R(slot, s.v);
+    }
+};
+
+// e^{mu} of the four members of face f(u, n), u = v + (ox, oy, oz), as
+// k_bp_iter forms them at u with the scalar prior a0 = e^{l0}.
+template <class RD>
+__device__ __forceinline__ void face_inputs(const RD& R, const Pos& p, float a0, int ox, int oy,
+                                            int oz, int n, float a[4]) {
+    const Site u = at(p, ox, oy, oz);
+    const Site u_xm = at(p, ox - 1, oy, oz), u_ym = at(p, ox, oy - 1, oz),
+               u_zm = at(p, ox, oy, oz - 1);
+    if (n == 2) {  // members e(u,x), e(u+y,x), e(u,y), e(u+x,y)
+        const float px = a0 * (R(9, u_ym) * R(5, u_zm));
+        const float py = a0 * (R(11, u_xm) * R(1, u_zm));
+        const Site u_yp = at(p, ox, oy + 1, oz), u_xp = at(p, ox + 1, oy, oz);
+        a[0] = px * R(4, u);
+        a[1] = a0 * R(8, u_yp) * R(4, u_yp) * R(5, at(p, ox, oy + 1, oz - 1));
+        a[2] = py * R(0, u);
+        a[3] = a0 * R(10, u_xp) * R(0, u_xp) * R(1, at(p, ox + 1, oy, oz - 1));
+    } else if (n == 1) {  // members e(u,x), e(u+z,x), e(u,z), e(u+x,z)
+        const float px = a0 * (R(9, u_ym) * R(5, u_zm));
+        const float pz = a0 * (R(7, u_xm) * R(3, u_ym));
+        const Site u_zp = at(p, ox, oy, oz + 1), u_xp = at(p, ox + 1, oy, oz);
+        a[0] = px * R(8, u);
+        a[1] = a0 * R(8, u_zp) * R(4, u_zp) * R(9, at(p, ox, oy - 1, oz + 1));
+        a[2] = pz * R(2, u);
+        a[3] = a0 * R(6, u_xp) * R(2, u_xp) * R(3, at(p, ox + 1, oy - 1, oz));
+    } else {  // members e(u,y), e(u+z,y), e(u,z), e(u+y,z)
+        const float py = a0 * (R(11, u_xm) * R(1, u_zm));
+        const float pz = a0 * (R(7, u_xm) * R(3, u_ym));
+        const Site u_zp = at(p, ox, oy, oz + 1), u_yp = at(p, ox, oy + 1, oz);
+        a[0] = py * R(10, u);
+        a[1] = a0 * R(10, u_zp) * R(0, u_zp) * R(11, at(p, ox - 1, oy, oz + 1));
+        a[2] = pz * R(6, u);
+        a[3] = a0 * R(6, u_yp) * R(2, u_yp) * R(7, at(p, ox - 1, oy + 1, oz));
+    }
+}
+
+// New messages of face f(u, n) (the caller keeps the members it needs).
+template <class RD>
+__device__ __forceinline__ void face_messages(const RD& R, const Src& S, const Item& it,
+                                              const uint64_t* syn_w, const Pos& p, float K,
+                                              int ox, int oy, int oz, int n, float out[4]) {
+    float a[4];
+    face_inputs(R, p, S.a0, ox, oy, oz, n, a);
+    const Site u = at(p, ox, oy, oz);
+    const uint32_t s = shot_bit(syn_w + ((int64_t)n * S.N + u.v) * S.ld_syn, it.lane);
+    check_rule(a, s ? -K : K, out);
+}
+
+// A wavefront walks ZR consecutive planes of one (x, y) column: the messages
+// of f(v-z, 0) and f(v-z, 1) that a site needs are those its predecessor in
+// the column computed for its own faces, so only the first site of the run
+// recomputes them, and the column's addresses change by one plane per step.
+// Item z indexes the runs (ceil(L / ZR) per column).
+template <int MODE, int ZR>
+__global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
+                                                     uint64_t* __restrict__ corr, int64_t ld_c,
+                                                     float* __restrict__ post,
+                                                     unsigned long long* __restrict__ ties) {
+    const Item it = item_of(tl);
+    if (!it.ok) return;
+    const int L = tl.L;
+    const int z0 = it.z * ZR;
+    Pos p = pos_of_xy(it.x, it.y, L);
+    const uint64_t* syn_w = S.syn + it.w;
+    const float a0 = S.a0;
+    int n_ties = 0;
+    auto walk = [&](const auto& R) {
+        float t[4];
+        set_z(p, z0, L);
+        face_messages(R, S, it, syn_w, p, K, 0, 0, -1, 0, t);
+        float zc0 = t[1];  // message of f(v-z, 0) to e(v, y)
+        face_messages(R, S, it, syn_w, p, K, 0, 0, -1, 1, t);
+        float zc1 = t[1];  // message of f(v-z, 1) to e(v, x)
+#pragma unroll 1
+        for (int z = z0; z < z0 + ZR && z < L; ++z) {
+            if (z != z0) set_z(p, z, L);
+            float f0[4], f1[4], f2[4], xm1[4], xm2[4], ym0[4], ym2[4];
+            face_messages(R, S, it, syn_w, p, K, 0, 0, 0, 0, f0);
+            face_messages(R, S, it, syn_w, p, K, 0, 0, 0, 1, f1);
+            face_messages(R, S, it, syn_w, p, K, 0, 0, 0, 2, f2);
+            face_messages(R, S, it, syn_w, p, K, -1, 0, 0, 1, xm1);
+            face_messages(R, S, it, syn_w, p, K, -1, 0, 0, 2, xm2);
+            face_messages(R, S, it, syn_w, p, K, 0, -1, 0, 0, ym0);
+            face_messages(R, S, it, syn_w, p, K, 0, -1, 0, 2, ym2);
+            // the products k_bp_post forms from the stored slots 8 4 | 9 5,
+            // 10 0 | 11 1 and 6 2 | 7 3
+            float el[3];
+            el[0] = a0 * f2[0] * f1[0] * ym2[1] * zc1;
+            el[1] = a0 * f2[2] * f0[0] * xm2[3] * zc0;
+            el[2] = a0 * f1[2] * f0[2] * xm1[3] * ym0[3];
+            zc0 = f0[1];
+            zc1 = f1[1];
+            const int v = at(p, 0, 0, 0).v;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int64_t e = (int64_t)c * S.N + v;
+                if (post) {
+                    float* row = post + word_base(it.w, 3 * (int64_t)S.N) + e * 64;
+                    row[it.lane] = 0.69314718055994531f * __builtin_amdgcn_logf(el[c]);
+                }
+                const uint64_t flips = __ballot(el[c] < 1.0f);
+                if (corr && it.lane == 0) corr[e * ld_c + it.w] = flips;
+                if (ties) n_ties += __popcll(__ballot(near_tie(el[c])));
+            }
+        }
+    };
+    if constexpr (MODE == NU_LOAD) {
+        BufReader R;
+        const float* word = S.nu + word_base(it.w, 12 * (int64_t)S.N);
+        R.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(word), (short)0,
+                                                   (int)(3072u * (uint32_t)S.N), 0x00020000);
+        R.lane4 = (uint32_t)it.lane * 4u;
+        walk(R);
+    } else {
+        IdxReader<MODE> R{reader_of<MODE>(S, it)};
+        walk(R);
+    }
+    if (ties && n_ties && it.lane == 0) atomicAdd(ties, (unsigned long long)n_ties);
+}
+
 // ---------------------------------------------- one shot per workgroup in LDS
 // On small lattices the whole message state of one shot, 12 FP32 per site,
 // fits a CU's LDS (83 KB at L = 12, 132 KB at L = 14). A workgroup then runs
@@ -544,6 +743,7 @@ bool tiling_of(Geo g, const BpArgs& a, Tiling* out) {
 // and n + 1 do not. 0 (no cap) when the device cannot be queried.
 static constexpr int kLoadIterBlocksPerCu = 4;
 static constexpr int kLoadPostBlocksPerCu = 6;
+static constexpr int kLoadFinalBlocksPerCu = 4;
 static std::atomic<int> g_cu_lds[64];
 
 static size_t residency_lds(int blocks_per_cu) {
@@ -609,12 +809,71 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     return after_launch(c);
 }
 
+bool bp_final_fits(Geo g, const BpArgs& a) {
+    // scalar prior, undamped; one word's messages addressed by 32-bit offsets
+    return !a.llr0 && a.damp == 0.0f && (int64_t)g.N * 3072 < ((int64_t)1 << 32);
+}
+
+// Planes each wavefront of the fused last iteration walks.
+#ifndef TC3D_FINAL_ZR
+#define TC3D_FINAL_ZR 8
+#endif
+static constexpr int kFinalRun = TC3D_FINAL_ZR;
+
+namespace {
+// Work items of k_bp_final: (x, y, run of zr planes) per word, x fastest.
+bool final_tiling(Geo g, int64_t nw, int zr, Tiling* out) {
+    Tiling tl;
+    const int L = g.L;
+    const int64_t runs = (L + zr - 1) / zr;
+    const int64_t per_word = (int64_t)L * L * runs;
+    const int64_t n_sg = (per_word + kWaves - 1) / kWaves;
+    if (n_sg * nw > 0x7fffffff || per_word + kWaves > 0x7fffffff) return false;
+    tl.L = L;
+    tl.TX = tl.TY = L;
+    tl.nTX = tl.nTY = 1;
+    tl.per_word = (uint32_t)per_word;
+    tl.n_sg = fastdiv((uint32_t)n_sg);
+    tl.col = fastdiv((uint32_t)per_word);
+    tl.plane = fastdiv((uint32_t)(L * L));
+    tl.row = fastdiv((uint32_t)L);
+    tl.tiles_x = fastdiv(1u);
+    *out = tl;
+    return true;
+}
+}  // namespace
+
+int launch_bp_final(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
+                    float* post) {
+    if (!bp_final_fits(g, a)) return TC3D_EINVAL;
+    if (a.nw == 0) return TC3D_OK;
+    Tiling tl;
+    if (!final_tiling(g, a.nw, kFinalRun, &tl)) return TC3D_EINVAL;
+    const int64_t blocks = (int64_t)tl.n_sg.d * a.nw;
+    int rc = before_launch(c, TC3D_K_BP_POST);
+    if (rc) return rc;
+    const Src S = make_src(g, a, nu);
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    const size_t lds =
+        mode == NU_LOAD ? residency_lds(a.occupancy ? a.occupancy : kLoadFinalBlocksPerCu) : 0;
+    if (mode == NU_SIGMA)
+        k_bp_final<NU_SIGMA, kFinalRun>
+            <<<grid, block, 0, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
+    else if (mode == NU_LOAD)
+        k_bp_final<NU_LOAD, kFinalRun>
+            <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
+    else
+        return TC3D_EINVAL;
+    return after_launch(c);
+}
+
 bool bp_resident_fits(Geo g, const float* llr0, int64_t nw) {
     return !llr0 && g.N <= kLdsMaxSites && nw > 0 && nw <= (int64_t)1 << 24;
 }
 
 bool bp_resident_used(Geo g, const BpArgs& a) {
-    return a.path != TC3D_BP_STREAMING && a.damp == 0.0f && bp_resident_fits(g, a.llr0, a.nw);
+    return (a.path == TC3D_BP_AUTO || a.path == TC3D_BP_RESIDENT) && a.damp == 0.0f &&
+           bp_resident_fits(g, a.llr0, a.nw);
 }
 
 static std::atomic<int> g_lds_opted[64];  // 1: the kernels may use their LDS size there

@@ -106,7 +106,7 @@ struct BpArgs {
     int64_t s_pad;       // 64 * nw
     int tile;            // site-tile edge of the traversal order (0: automatic)
     bool fold;           // per-edge priors folded into the stored state (see tc3d_bp.hip)
-    int path;            // TC3D_BP_AUTO / _STREAMING / _RESIDENT
+    int path;            // TC3D_BP_AUTO / _STREAMING / _RESIDENT / _STREAMING_SPLIT
     unsigned long long* ties;  // device counter of posteriors |l| < 1e-3, or nullptr
     float damp;          // damping g: nu = (1 - g) nu_new + g nu_old (0: none)
     int occupancy;       // workgroups per CU of the stored-message iterations (0: default)
@@ -124,6 +124,13 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 // post (may be null) = posterior floats.
 int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
                    float* post);
+// One more iteration from the state (mode, nu) and the posterior of its
+// result, in one pass that stores no messages; bit-identical to
+// launch_bp_iter followed by launch_bp_post. Needs bp_final_fits: scalar
+// prior, undamped, L <= 111.
+bool bp_final_fits(Geo g, const BpArgs& a);
+int launch_bp_final(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
+                    float* post);
 // A whole decode (iters >= 1, scalar prior) with each shot's state in one
 // workgroup's LDS; bit-identical to the streaming kernels. Possible when
 // bp_resident_fits: L^3 <= 3072 and no per-edge prior; bp_resident_used adds

@@ -81,7 +81,8 @@ def test_invalid_parameters_are_rejected_before_any_launch(lib):
         dict(p_dec=0.0),                   # BP prior must be in (0, 0.5)
         dict(q_dec=0.5),
         dict(perfect_final=2),
-        dict(bp_path=3),                   # no such kernel choice
+        dict(bp_path=4),                   # no such kernel choice
+        dict(bp_path=-1),
         dict(cycle0=0xFFFFFFFF),           # cycle indices past 2^32
         dict(bp_damp=1.0),                 # damping in [0, 1)
         dict(bp_damp=-0.1),
@@ -108,7 +109,7 @@ def test_invalid_parameters_are_rejected_before_any_launch(lib):
                               None, 0, None) == -1  # meas_factor must be < 1
     assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 0, 0, None, None,
                               None, 0, None) == -1  # iters >= 1
-    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 20, 3, None, None,
+    assert lib.tc3d_bp_decode(ctypes.byref(lat), None, 64, None, 2.9, 0.9, 20, 4, None, None,
                               None, 0, None) == -1  # no such kernel choice
     big = tc.make_lattice(16)  # the resident kernel holds at most 3072 sites
     assert lib.tc3d_bp_decode(ctypes.byref(big), None, 64, None, 2.9, 0.9, 20, 2, None, None,

@@ -84,14 +84,22 @@ _HASHES = {k: bench.kernel_source_hash(k) for k in bench.KERNEL_SOURCES}
 
 
 def test_path_roofline_model():
-    # 20 BP iterations: 20 x 32 B of messages + 20 syndrome bits + 4 B of bit planes
+    # 20 BP iterations, scalar prior: iteration 2 writes 16 B, 3..19 read and
+    # write 32 B, iteration 20 fused with the posterior reads 16 B; plus 20
+    # syndrome bits and 4 B of bit planes
     r = bench.path_roofline(20, 1e10)
-    assert r["bytes_per_unit"] == 32.0 * 20 + 20 / 8 + 4 == 646.5
-    assert r["achieved"] == pytest.approx(1e10 * 646.5 / 1e9, rel=1e-6)
-    assert r["frac"] == pytest.approx(1e10 * 646.5 / 8e12, abs=1e-4)
-    # a per-edge prior adds its 4-byte read to every iteration
+    assert r["bytes_per_unit"] == 16 + 32.0 * 17 + 16 + 20 / 8 + 4 == 582.5
+    assert r["achieved"] == pytest.approx(1e10 * 582.5 / 1e9, rel=1e-6)
+    assert r["frac"] == pytest.approx(1e10 * 582.5 / 8e12, abs=1e-4)
+    # the last iteration and the posterior launched separately: 32 B more
+    assert bench.path_roofline(20, 1e10, fused=False)["bytes_per_unit"] == 614.5
+    # two iterations fused read only syndrome bits; one decodes from them
+    assert bench.bp_message_bytes(2) == 0.0 and bench.bp_message_bytes(1) == 0.0
+    assert bench.bp_message_bytes(2, fused=False) == 32.0
+    # a per-edge prior: the first iteration writes and reads the prior, each
+    # later one reads and writes, the posterior reads
     assert bench.path_roofline(6, 1e10, per_edge_prior=True)["bytes_per_unit"] == \
-        36.0 * 6 + 6 / 8 + 4
+        20 + 36.0 * 5 + 16 + 6 / 8 + 4
     # without BP there is no HBM model
     assert bench.path_roofline(0, 1e10) is None
 
@@ -118,4 +126,4 @@ def test_resident_bp_roofline_is_alu_bound():
 
 def test_path_roofline_is_none_for_a_resident_decode():
     assert bench.path_roofline(20, 1e10, n_sites=1728) is None
-    assert bench.path_roofline(20, 1e10, n_sites=48 ** 3)["bytes_per_unit"] == 646.5
+    assert bench.path_roofline(20, 1e10, n_sites=48 ** 3)["bytes_per_unit"] == 582.5

@@ -164,21 +164,23 @@ def test_bp_pflip_run_matches_oracle(L, S, p, noisy):
     assert abs(f_g - f_o) <= 3 * sig + 1e-12
 
 
-@pytest.mark.parametrize("resident", ["0", "1"])
-def test_timed_run_counts_launches(resident):
+@pytest.mark.parametrize("path", ["resident", "streaming", "split"])
+def test_timed_run_counts_launches(path):
     L, S = 5, 128
     prm = tc.make_run_params(0.05, 0.05, 2, 7, 6, PFFPFF, n_shots=S, seed=3,
-                             bp_path=tc.BP_RESIDENT if resident == "1" else tc.BP_STREAMING)
+                             bp_path={"resident": tc.BP_RESIDENT, "streaming": tc.BP_STREAMING,
+                                      "split": tc.BP_STREAMING_SPLIT}[path])
     m_a, _, e_a, t = gpu_run(L, prm, timed=True)
     m_b, _, e_b, _ = gpu_run(L, prm)
     assert np.array_equal(e_a, e_b) and np.array_equal(m_a, m_b)
     d = t.as_dict()
     cycles = 3
-    if resident == "1":  # one launch decodes each cycle's batch inside LDS
+    if path == "resident":  # one launch decodes each cycle's batch inside LDS
         assert d["bp_iter"]["launches"] == cycles
         assert d["bp_first"]["launches"] == 0 and d["bp_post"]["launches"] == 0
-    else:
-        assert d["bp_iter"]["launches"] == cycles * (7 - 2)
+    else:  # iteration 1 is implied by the syndrome; 2 reads only syndrome bits
+        fused = path == "streaming"  # iteration 7 shares the posterior's launch
+        assert d["bp_iter"]["launches"] == cycles * (7 - 2 - fused)
         assert d["bp_first"]["launches"] == cycles
         assert d["bp_post"]["launches"] == cycles
     assert d["sweep"]["launches"] == cycles * 6
@@ -188,6 +190,25 @@ def test_timed_run_counts_launches(resident):
     # class intervals are disjoint runs of launches inside the call's span
     assert sum(v["ms"] for v in d.values()) <= t.total_ms * 1.001 + 1e-3
     assert t.total_ms >= sum(v["ms"] for v in d.values()) * 0.5
+
+
+def test_fused_last_iteration_run_equals_split_run():
+    """A whole p-BP run at L = 16 (streaming kernels) with the last BP
+    iteration fused into the posterior against the same run with the two
+    launched separately: residuals, masks, odd counts and the near-tie
+    counts bit for bit."""
+    L, S = 16, 320
+    out = {}
+    for path in (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT):
+        prm = tc.make_run_params(0.06, 0.06, 4, 20, 6, PFFPFF, n_shots=S, seed=11,
+                                 bp_path=path)
+        m, o, e, t = gpu_run(L, prm, timed=True)
+        out[path] = (m, o, e, t.bp_near_ties, t.bp_decisions)
+    a, b = out[tc.BP_STREAMING], out[tc.BP_STREAMING_SPLIT]
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3:] == b[3:]
+    assert a[2].any()
 
 
 # ----------------------------------------------------------- full size

@@ -396,28 +396,53 @@ def test_bp_decode_per_edge_prior(L, n_shots):
                                               (8, 150, 20), (12, 128, 20), (14, 64, 20)])
 def test_bp_decode_resident_equals_streaming(L, n_shots, iters):
     """The whole-decode-in-LDS path (L <= 14, scalar prior) against the
-    streaming kernels on the same syndromes: corrections and posteriors bit for
-    bit, padding shots of the last word included."""
-    import torch
+    streaming kernels on the same syndromes, with the last iteration fused
+    into the posterior and launched separately: corrections and posteriors bit
+    for bit, padding shots of the last word included."""
     announce(f"resident BP L={L} S={n_shots} iters={iters}")
+    out = decode_paths(L, n_shots, iters, 300 + L, 0.15, 0.9,
+                       (tc.BP_RESIDENT, tc.BP_STREAMING, tc.BP_STREAMING_SPLIT))
+    res = out[tc.BP_RESIDENT]
+    for mode in (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT):
+        assert np.array_equal(res[0], out[mode][0])
+        assert np.array_equal(res[1], out[mode][1])
+    assert res[0].any()
+
+
+def decode_paths(L, n_shots, iters, seed, density, K, modes, l0=math.log(19.0)):
+    """tc3d_bp_decode of one random syndrome plane through each kernel path:
+    {path: (correction words, posterior bits as int32)}."""
+    import torch
     lat = tc.make_lattice(L)
     W = inputs.n_words(n_shots)
-    full = 64 * W
-    syn = inputs.random_bits(300 + L, full, 3 * L ** 3, 0.15)
+    syn = inputs.random_bits(seed, 64 * W, 3 * L ** 3, density)
     d_syn = dev_plane_of_bits(syn)
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     out = {}
-    for mode in (tc.BP_RESIDENT, tc.BP_STREAMING):
+    for mode in modes:
         corr = torch.full((3 * L ** 3, W), -1, dtype=torch.int64, device="cuda")
         post = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
-        tc.bp_decode(lat, d_syn, n_shots, None, math.log(19.0), 0.9, iters, corr, post, ws,
-                     path=mode)
+        tc.bp_decode(lat, d_syn, n_shots, None, l0, K, iters, corr, post, ws, path=mode)
         sync()
         out[mode] = (corr.cpu().numpy(), post.cpu().numpy().view(np.int32))
-    res, stream = out[tc.BP_RESIDENT], out[tc.BP_STREAMING]
-    assert np.array_equal(res[0], stream[0])
-    assert np.array_equal(res[1], stream[1])
-    assert res[0].any()
+    return out
+
+
+@pytest.mark.parametrize("L,n_shots,iters,density,K", [
+    (16, 64, 20, 0.05, 0.9), (16, 200, 2, 0.15, 0.9), (17, 130, 3, 0.1, 0.99),
+    (24, 64, 1, 0.05, 0.9), (24, 128, 20, 0.02, 0.99), (48, 64, 20, 0.01, 0.9)])
+def test_bp_last_iteration_fused_equals_split(L, n_shots, iters, density, K):
+    """The last iteration fused with the posterior (one pass that recomputes
+    the six neighbouring faces' messages) against the iteration and posterior
+    launched separately, on lattices too large for the resident kernel, odd L
+    included: corrections and posteriors bit for bit."""
+    announce(f"fused last BP iteration L={L} S={n_shots} iters={iters} K={K}")
+    out = decode_paths(L, n_shots, iters, 700 + L, density, K,
+                       (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT))
+    fused, split = out[tc.BP_STREAMING], out[tc.BP_STREAMING_SPLIT]
+    assert np.array_equal(fused[0], split[0])
+    assert np.array_equal(fused[1], split[1])
+    assert fused[0].any()
 
 
 def test_zero_syndrome_scalar_recursion_on_gpu():
