@@ -86,14 +86,16 @@ ALGO_BYTES = {
 # divided by its launches.
 CNN_FLOP_PER_SITE = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
 # BP with each shot's state in LDS (lattices of at most 3072 sites, scalar
-# prior) is bound by the vector ALU. Its algorithmic FP32 work per site and
-# iteration, in VALU issue slots of one lane: per check 8 clamps (min, max),
-# 8 (a -+ 1), 14 products and, for each of the 4 outputs, an add, a subtract,
-# a multiply (1 slot each) and a reciprocal (4 slots: transcendental ops run
-# at a quarter of the rate), 58 slots; per site 3 checks plus 30 products
-# forming the incoming e^mu. The posterior adds 12 products per site.
+# prior) is bound by the vector ALU. Its FP32 work per site and iteration, in
+# VALU issue cycles of one lane: per check 4 clamps (one min-max-median op
+# each), 8 (a -+ 1), 10 products forming N and D, and for each of the 4
+# outputs D +- N (two fused multiply-adds), a reciprocal and a product; a
+# reciprocal holds the VALU for two issue cycles (rocprofv3's
+# SQ_ACTIVE_INST_VALU), every other op for one: 42 cycles per check; per site
+# 3 checks plus 30 products forming the incoming e^mu. The posterior adds 12
+# products per site.
 RESIDENT_MAX_SITES = 3072
-RESIDENT_SLOTS_PER_SITE_ITER = 3 * (8 + 8 + 14 + 4 * (3 + 4)) + 30
+RESIDENT_SLOTS_PER_SITE_ITER = 3 * (4 + 8 + 10 + 4 * (2 + 2 + 1)) + 30
 RESIDENT_SLOTS_PER_SITE_POST = 12
 # one non-packed FP32 operation per lane per clock: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz (the 157.3 TFLOP/s vector peak counts packed FMAs, 4 FLOP
@@ -456,7 +458,7 @@ def roofline(per_class, n, batch, n_sites, workload, forwards=0, shots_padded=0,
         ops = per_site * n_sites * shots / n_batches
         achieved = ops / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_SLOTS_PEAK_T, 2),
-                "unit": "T VALU slots/s (FP32 lane-ops; a reciprocal takes 4 slots)",
+                "unit": "T VALU slots/s (FP32 lane-ops; a reciprocal takes 2 slots)",
                 "frac": round(achieved / VALU_SLOTS_PEAK_T, 4),
                 "traffic": stored_traffic("bp_resident", workload),
                 "kernel": "bp_resident (whole decode of a shot in one workgroup's LDS)",

@@ -109,9 +109,11 @@ def test_resident_bp_roofline_is_alu_bound():
     pc = _cls(bp_iter={"ms": 2.0, "launches": 1})
     r = bench.roofline(pc, 5184, 4096, 1728, "none", shots_padded=4096, bp_iters=20)
     assert r["bound"] == "alu" and r["kernel"].startswith("bp_resident")
-    # VALU issue slots per site and iteration: 3 checks of 30 one-slot ops and
-    # 4 outputs of 3 one-slot ops and a quarter-rate reciprocal, 30 products
-    per_site = (3 * (30 + 4 * (3 + 4)) + 30) * 19 + 12
+    # VALU issue cycles per site and iteration: per check 4 median clamps,
+    # 8 (a -+ 1), 10 products and per output 2 fused multiply-adds, a product
+    # and a reciprocal of two cycles; 30 products forming e^mu
+    per_site = (3 * (22 + 4 * (2 + 1 + 2)) + 30) * 19 + 12
+    assert per_site == 156 * 19 + 12
     assert r["algo_ops_per_unit"] == per_site
     assert r["algo_ops_per_launch"] == per_site * 1728 * 4096
     assert r["achieved"] == pytest.approx(per_site * 1728 * 4096 / 2e-3 / 1e12, abs=0.01)
