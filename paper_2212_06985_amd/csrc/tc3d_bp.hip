@@ -743,7 +743,10 @@ bool tiling_of(Geo g, const BpArgs& a, Tiling* out) {
 // and n + 1 do not. 0 (no cap) when the device cannot be queried.
 static constexpr int kLoadIterBlocksPerCu = 4;
 static constexpr int kLoadPostBlocksPerCu = 6;
-static constexpr int kLoadFinalBlocksPerCu = 4;
+#ifndef TC3D_FINAL_OCC
+#define TC3D_FINAL_OCC 4
+#endif
+static constexpr int kLoadFinalBlocksPerCu = TC3D_FINAL_OCC;
 static std::atomic<int> g_cu_lds[64];
 
 static size_t residency_lds(int blocks_per_cu) {

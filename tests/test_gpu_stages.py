@@ -430,12 +430,15 @@ def decode_paths(L, n_shots, iters, seed, density, K, modes, l0=math.log(19.0)):
 
 @pytest.mark.parametrize("L,n_shots,iters,density,K", [
     (16, 64, 20, 0.05, 0.9), (16, 200, 2, 0.15, 0.9), (17, 130, 3, 0.1, 0.99),
-    (24, 64, 1, 0.05, 0.9), (24, 128, 20, 0.02, 0.99), (48, 64, 20, 0.01, 0.9)])
+    (24, 64, 1, 0.05, 0.9), (24, 128, 20, 0.02, 0.99), (48, 64, 20, 0.01, 0.9),
+    (111, 64, 3, 0.01, 0.9), (112, 64, 2, 0.01, 0.9)])
 def test_bp_last_iteration_fused_equals_split(L, n_shots, iters, density, K):
     """The last iteration fused with the posterior (one pass that recomputes
-    the six neighbouring faces' messages) against the iteration and posterior
+    the neighbouring faces' messages) against the iteration and posterior
     launched separately, on lattices too large for the resident kernel, odd L
-    included: corrections and posteriors bit for bit."""
+    included: corrections and posteriors bit for bit. L = 111 is the largest
+    lattice whose word of messages (L^3 x 3072 B) the fused pass addresses
+    with 32-bit offsets; L = 112 falls back to the separate launches."""
     announce(f"fused last BP iteration L={L} S={n_shots} iters={iters} K={K}")
     out = decode_paths(L, n_shots, iters, 700 + L, density, K,
                        (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT))
