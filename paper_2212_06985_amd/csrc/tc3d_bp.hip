@@ -21,8 +21,9 @@
 // member k for the 64 shots of word w. A wavefront (64 lanes = the 64 shots
 // of one word at one site) reads and writes 256 contiguous bytes per row and
 // a site's rows are adjacent, so the accesses of a word spread over every L2
-// and HBM channel. Each access is a wave-uniform 64-bit site base (scalar
-// registers) plus a 32-bit per-lane row offset held in vector registers.
+// and HBM channel. Each access is a wave-uniform site base (scalar
+// registers) plus a per-lane row offset held in vector registers; neighbour
+// sites are v plus per-axis steps with the periodic wrap folded in.
 //
 // Per-edge priors (the learned prior) cost loads, not arithmetic: the check
 // rules of a site need the priors of its own three edges and of six edges of
@@ -191,32 +192,6 @@ __device__ __forceinline__ float prior(const Src& S, const Item& it, int c, int 
     return __builtin_amdgcn_exp2f(l * 1.4426950408889634f);
 }
 
-// Neighbour sites of v = (x,y,z) by offset.
-struct Nbr {
-    int xm, xp, ym, yp, zm, zp;                    // v -/+ unit
-    int yp_zm, zp_ym, xp_zm, zp_xm, xp_ym, yp_xm;  // diagonal
-};
-
-__device__ __forceinline__ Nbr neighbours(const Item& it, int L) {
-    const int x = it.x, y = it.y, z = it.z;
-    const int xm = dec(x, L), xp = inc(x, L), ym = dec(y, L), yp = inc(y, L);
-    const int zm = dec(z, L), zp = inc(z, L);
-    Nbr n;
-    n.xm = site_of(xm, y, z, L);
-    n.xp = site_of(xp, y, z, L);
-    n.ym = site_of(x, ym, z, L);
-    n.yp = site_of(x, yp, z, L);
-    n.zm = site_of(x, y, zm, L);
-    n.zp = site_of(x, y, zp, L);
-    n.yp_zm = site_of(x, yp, zm, L);
-    n.zp_ym = site_of(x, ym, zp, L);
-    n.xp_zm = site_of(xp, y, zm, L);
-    n.zp_xm = site_of(xm, y, zp, L);
-    n.xp_ym = site_of(xp, ym, z, L);
-    n.yp_xm = site_of(xm, yp, z, L);
-    return n;
-}
-
 // The check rule E2 of one face in multiplicative form: a[k] = e^{mu_k} of
 // its four members (clamped), out[k] = e^{nu_k} of the new messages.
 __device__ __forceinline__ void check_rule(const float a_in[4], float sK, float out[4]) {
@@ -251,54 +226,150 @@ __device__ __forceinline__ float damped(float b_new, float b_old, float g) {
                                   g * __builtin_amdgcn_logf(b_old));
 }
 
+// Sites v + (dx, dy, dz), -2 <= d <= 1, as index and as byte offset of the
+// site's message rows inside one shot word (12 rows of 256 B). The wrapped
+// coordinates and their scaled forms are formed once per wavefront, so a
+// site costs two scalar adds per form.
+struct Site {
+    int v;
+    uint32_t off;
+};
+
+struct Pos {
+    int xs[4], ys[4], zs[4];        // wrapped coordinate c + d at [d + 2]
+    int yl[4], zl[4];               // L y', L^2 z'
+    uint32_t xo[4], yo[4], zo[4];   // byte offsets 3072 x', 3072 L y', 3072 L^2 z'
+    __device__ __forceinline__ Site at(int dx, int dy, int dz) const {
+        return Site{xs[dx + 2] + yl[dy + 2] + zl[dz + 2], xo[dx + 2] + yo[dy + 2] + zo[dz + 2]};
+    }
+};
+
+// Sites v + (dx, dy, dz), |d| <= 1, for one site: v's index and row offset
+// plus, per axis, the step to the previous and the next site with the
+// periodic wrap folded in (offsets modulo 2^32).
+struct Steps {
+    int v;
+    uint32_t off;
+    int di[3][3];         // index step, [axis][d + 1]
+    uint32_t doff[3][3];  // 3072 x the index step
+    __device__ __forceinline__ Site at(int dx, int dy, int dz) const {
+        return Site{v + di[0][dx + 1] + di[1][dy + 1] + di[2][dz + 1],
+                    off + doff[0][dx + 1] + doff[1][dy + 1] + doff[2][dz + 1]};
+    }
+};
+
+__device__ __forceinline__ Steps steps_of(const Item& it, int L) {
+    Steps s;
+    const int c[3] = {it.x, it.y, it.z};
+    int stride = 1;
+    s.v = it.v;
+    s.off = 3072u * (uint32_t)it.v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.di[a][0] = c[a] == 0 ? (L - 1) * stride : -stride;
+        s.di[a][1] = 0;
+        s.di[a][2] = c[a] == L - 1 ? (1 - L) * stride : stride;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s.doff[a][d] = 3072u * (uint32_t)s.di[a][d];
+        stride *= L;
+    }
+    return s;
+}
+
+__device__ __forceinline__ int wrap(int t, int L) { return t < 0 ? t + L : (t >= L ? t - L : t); }
+
+__device__ __forceinline__ Pos pos_of_xy(int x, int y, int L) {
+    Pos p;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        p.xs[d] = wrap(x + d - 2, L);
+        p.ys[d] = wrap(y + d - 2, L);
+        p.yl[d] = L * p.ys[d];
+        p.xo[d] = 3072u * (uint32_t)p.xs[d];
+        p.yo[d] = 3072u * (uint32_t)p.yl[d];
+    }
+    return p;
+}
+
+__device__ __forceinline__ void set_z(Pos& p, int z, int L) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        p.zs[d] = wrap(z + d - 2, L);
+        p.zl[d] = L * L * p.zs[d];
+        p.zo[d] = 3072u * (uint32_t)p.zl[d];
+    }
+}
+
+// Message loads of one shot word by the site's 32-bit byte offset inside the
+// word (L^3 * 3072 < 2^32, i.e. L <= 111): a 64-bit word base plus the offset
+// (one 64-bit scalar add per site), the lane's offset in a vector register and
+// the slot's row. Buffer loads with the site's offset as their scalar offset
+// need fewer scalar instructions but ran 1% slower.
+struct OffReader {
+    const char* base;
+    uint32_t lane4;
+    __device__ __forceinline__ float operator()(int slot, const Site& s) const {
+        return *reinterpret_cast<const float*>(base + s.off + lane4 + slot * 256);
+    }
+};
+
+// The reader by site index: 64-bit site addresses (NU_LOAD) or the first
+// iteration's messages from the syndrome (NU_SIGMA).
+template <int MODE>
+struct IdxReader {
+    Reader<MODE> R;
+    __device__ __forceinline__ float operator()(int slot, const Site& s) const {
+        return R(slot, s.v);
+    }
+};
+
+// One site of one iteration: its three faces' check rules (E2) from the
+// incoming messages (E3), stored through W. LOC locates the neighbouring
+// sites (Steps or Pos), R reads the old state.
 // FOLD: 0 plain state in and out; 1 plain in, folded out (the first
 // iteration of a decode with per-edge priors); 2 folded in and out.
-template <int MODE, bool EP, int FOLD, bool DAMP = false>
-__global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K, float g,
-                                                    float* __restrict__ b_out) {
-    static_assert(FOLD == 0 || EP, "only per-edge priors are folded");
-    static_assert(!DAMP || (!EP && FOLD == 0), "damping goes with the scalar prior");
-    const Item it = item_of(tl);
-    if (!it.ok) return;
-    const Reader<MODE> R = reader_of<MODE>(S, it);
-    const Nbr nb = neighbours(it, tl.L);
-    const int v = it.v;
+template <int MODE, bool EP, int FOLD, bool DAMP, class LOC, class RD, class WR>
+__device__ __forceinline__ void iter_site(const Src& S, const Item& it, const LOC& p, const RD& R,
+                                          const WR& W, float K, float g) {
+    const Site v = p.at(0, 0, 0);
+    const Site xm = p.at(-1, 0, 0), xp = p.at(1, 0, 0), ym = p.at(0, -1, 0),
+               yp = p.at(0, 1, 0), zm = p.at(0, 0, -1), zp = p.at(0, 0, 1);
+    const Site yp_zm = p.at(0, 1, -1), zp_ym = p.at(0, -1, 1), xp_zm = p.at(1, 0, -1),
+               zp_xm = p.at(-1, 0, 1), xp_ym = p.at(1, -1, 0), yp_xm = p.at(-1, 1, 0);
     // syndrome bits of the three faces of v (read first, with the messages)
     uint32_t sbit[3];
 #pragma unroll
     for (int n = 0; n < 3; ++n)
-        sbit[n] = shot_bit(S.syn + ((int64_t)n * S.N + v) * S.ld_syn + it.w, it.lane);
+        sbit[n] = shot_bit(S.syn + ((int64_t)n * S.N + v.v) * S.ld_syn + it.w, it.lane);
     // own messages to the members k = 0, 2 of each face (the others are the
     // excluded message of the member-k check and are not needed)
     const float o0 = R(0, v), o2 = R(2, v), o4 = R(4, v), o6 = R(6, v), o8 = R(8, v),
                 o10 = R(10, v);
     // e^{l0} of the three edges at v, and the two incoming messages from
     // faces of other sites for each of them (each is a member of two of v's faces)
-    const float ex = prior<EP>(S, it, 0, v), ey = prior<EP>(S, it, 1, v),
-                ez = prior<EP>(S, it, 2, v);
-    const float fx = R(9, nb.ym) * R(5, nb.zm);
-    const float fy = R(11, nb.xm) * R(1, nb.zm);
-    const float fz = R(7, nb.xm) * R(3, nb.ym);
+    const float ex = prior<EP>(S, it, 0, v.v), ey = prior<EP>(S, it, 1, v.v),
+                ez = prior<EP>(S, it, 2, v.v);
+    const float fx = R(9, ym) * R(5, zm);
+    const float fy = R(11, xm) * R(1, zm);
+    const float fz = R(7, xm) * R(3, ym);
     const float px = ex * fx, py = ey * fy, pz = ez * fz;
     // e^{mu} of the six edges that are a member of one face of v
     float a_x_yp, a_x_zp, a_y_xp, a_y_zp, a_z_xp, a_z_yp;
     if constexpr (FOLD == 2) {  // slots 8, 10, 6 of each site carry its edges' priors
-        a_x_yp = R(8, nb.yp) * R(4, nb.yp) * R(5, nb.yp_zm);
-        a_x_zp = R(8, nb.zp) * R(4, nb.zp) * R(9, nb.zp_ym);
-        a_y_xp = R(10, nb.xp) * R(0, nb.xp) * R(1, nb.xp_zm);
-        a_y_zp = R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
-        a_z_xp = R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
-        a_z_yp = R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
+        a_x_yp = R(8, yp) * R(4, yp) * R(5, yp_zm);
+        a_x_zp = R(8, zp) * R(4, zp) * R(9, zp_ym);
+        a_y_xp = R(10, xp) * R(0, xp) * R(1, xp_zm);
+        a_y_zp = R(10, zp) * R(0, zp) * R(11, zp_xm);
+        a_z_xp = R(6, xp) * R(2, xp) * R(3, xp_ym);
+        a_z_yp = R(6, yp) * R(2, yp) * R(7, yp_xm);
     } else {
-        a_x_yp = prior<EP>(S, it, 0, nb.yp) * R(8, nb.yp) * R(4, nb.yp) * R(5, nb.yp_zm);
-        a_x_zp = prior<EP>(S, it, 0, nb.zp) * R(8, nb.zp) * R(4, nb.zp) * R(9, nb.zp_ym);
-        a_y_xp = prior<EP>(S, it, 1, nb.xp) * R(10, nb.xp) * R(0, nb.xp) * R(1, nb.xp_zm);
-        a_y_zp = prior<EP>(S, it, 1, nb.zp) * R(10, nb.zp) * R(0, nb.zp) * R(11, nb.zp_xm);
-        a_z_xp = prior<EP>(S, it, 2, nb.xp) * R(6, nb.xp) * R(2, nb.xp) * R(3, nb.xp_ym);
-        a_z_yp = prior<EP>(S, it, 2, nb.yp) * R(6, nb.yp) * R(2, nb.yp) * R(7, nb.yp_xm);
+        a_x_yp = prior<EP>(S, it, 0, yp.v) * R(8, yp) * R(4, yp) * R(5, yp_zm);
+        a_x_zp = prior<EP>(S, it, 0, zp.v) * R(8, zp) * R(4, zp) * R(9, zp_ym);
+        a_y_xp = prior<EP>(S, it, 1, xp.v) * R(10, xp) * R(0, xp) * R(1, xp_zm);
+        a_y_zp = prior<EP>(S, it, 1, zp.v) * R(10, zp) * R(0, zp) * R(11, zp_xm);
+        a_z_xp = prior<EP>(S, it, 2, xp.v) * R(6, xp) * R(2, xp) * R(3, xp_ym);
+        a_z_yp = prior<EP>(S, it, 2, yp.v) * R(6, yp) * R(2, yp) * R(7, yp_xm);
     }
-    char* outb = reinterpret_cast<char*>(b_out + word_base(it.w, 12 * (int64_t)S.N)) +
-                 (int64_t)v * R.site_bytes;
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
         float a[4];
@@ -329,9 +400,32 @@ __global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K, f
         // streaming stores: the new messages are read again only in the next
         // iteration, so they should not evict the neighbour rows from L2
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            __builtin_nontemporal_store(out[k], reinterpret_cast<float*>(outb + R.voff[4 * n + k]));
+        for (int k = 0; k < 4; ++k) W(out[k], 4 * n + k, v);
     }
+}
+
+// Stores by 64-bit site address.
+struct PtrWriter {
+    char* base;  // (char*)(b_out + 64 * 12 N w)
+    uint32_t lane4;
+    __device__ __forceinline__ void operator()(float x, int slot, const Site& s) const {
+        __builtin_nontemporal_store(
+            x, reinterpret_cast<float*>(base + (int64_t)s.v * 3072 + lane4 + slot * 256));
+    }
+};
+
+template <int MODE, bool EP, int FOLD, bool DAMP = false>
+__global__ __launch_bounds__(kBlock) void k_bp_iter(Src S, Tiling tl, float K, float g,
+                                                    float* __restrict__ b_out) {
+    static_assert(FOLD == 0 || EP, "only per-edge priors are folded");
+    static_assert(!DAMP || (!EP && FOLD == 0), "damping goes with the scalar prior");
+    const Item it = item_of(tl);
+    if (!it.ok) return;
+    const Steps p = steps_of(it, tl.L);
+    const PtrWriter W{reinterpret_cast<char*>(b_out + word_base(it.w, 12 * (int64_t)S.N)),
+                      (uint32_t)it.lane * 4u};
+    const IdxReader<MODE> R{reader_of<MODE>(S, it)};
+    iter_site<MODE, EP, FOLD, DAMP>(S, it, p, R, W, K, g);
 }
 
 template <int MODE, bool EP, bool FOLDED>
@@ -341,8 +435,9 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
                                                     unsigned long long* __restrict__ ties) {
     const Item it = item_of(tl);
     if (!it.ok) return;
-    const Reader<MODE> R = reader_of<MODE>(S, it);
-    const Nbr nb = neighbours(it, tl.L);
+    const IdxReader<MODE> R{reader_of<MODE>(S, it)};
+    const Steps p = steps_of(it, tl.L);
+    const Site sv = p.at(0, 0, 0), xm = p.at(-1, 0, 0), ym = p.at(0, -1, 0), zm = p.at(0, 0, -1);
     const int v = it.v;
     // e^l = e^{l0} times the four incoming messages (E4); in a folded state
     // slots 8, 10, 6 already carry the factor e^{l0}
@@ -350,9 +445,9 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
     const float ey = FOLDED ? 1.0f : prior<EP>(S, it, 1, v);
     const float ez = FOLDED ? 1.0f : prior<EP>(S, it, 2, v);
     float el[3];
-    el[0] = ex * R(8, v) * R(4, v) * R(9, nb.ym) * R(5, nb.zm);
-    el[1] = ey * R(10, v) * R(0, v) * R(11, nb.xm) * R(1, nb.zm);
-    el[2] = ez * R(6, v) * R(2, v) * R(7, nb.xm) * R(3, nb.ym);
+    el[0] = ex * R(8, sv) * R(4, sv) * R(9, ym) * R(5, zm);
+    el[1] = ey * R(10, sv) * R(0, sv) * R(11, xm) * R(1, zm);
+    el[2] = ez * R(6, sv) * R(2, sv) * R(7, xm) * R(3, ym);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int64_t e = (int64_t)c * S.N + v;
@@ -385,104 +480,38 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
 // neither written nor read back; the price is about twice the loads, which
 // L2 serves, and the check rules of six more faces. Scalar prior, undamped.
 
-// Sites v + (dx, dy, dz), -2 <= d <= 1, as index and as byte offset of the
-// site's message rows inside one shot word (12 rows of 256 B). The wrapped
-// coordinates and their scaled forms are formed once per wavefront, so a
-// site costs two scalar adds per form.
-struct Site {
-    int v;
-    uint32_t off;
-};
-
-struct Pos {
-    int xs[4], ys[4], zs[4];        // wrapped coordinate c + d at [d + 2]
-    int yl[4], zl[4];               // L y', L^2 z'
-    uint32_t xo[4], yo[4], zo[4];   // byte offsets 3072 x', 3072 L y', 3072 L^2 z'
-};
-
-__device__ __forceinline__ int wrap(int t, int L) { return t < 0 ? t + L : (t >= L ? t - L : t); }
-
-__device__ __forceinline__ Pos pos_of_xy(int x, int y, int L) {
-    Pos p;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        p.xs[d] = wrap(x + d - 2, L);
-        p.ys[d] = wrap(y + d - 2, L);
-        p.yl[d] = L * p.ys[d];
-        p.xo[d] = 3072u * (uint32_t)p.xs[d];
-        p.yo[d] = 3072u * (uint32_t)p.yl[d];
-    }
-    return p;
-}
-
-__device__ __forceinline__ void set_z(Pos& p, int z, int L) {
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        p.zs[d] = wrap(z + d - 2, L);
-        p.zl[d] = L * L * p.zs[d];
-        p.zo[d] = 3072u * (uint32_t)p.zl[d];
-    }
-}
-
-__device__ __forceinline__ Site at(const Pos& p, int dx, int dy, int dz) {
-    return Site{p.xs[dx + 2] + p.yl[dy + 2] + p.zl[dz + 2],
-                p.xo[dx + 2] + p.yo[dy + 2] + p.zo[dz + 2]};
-}
-
-// Message loads of one shot word through a buffer resource: the site's byte
-// offset is the wave-uniform scalar offset, the lane's the vector offset and
-// the slot's the instruction's immediate. Needs L^3 * 3072 < 2^32 (L <= 111).
-struct BufReader {
-    __amdgpu_buffer_rsrc_t rsrc;
-    uint32_t lane4;
-    __device__ __forceinline__ float operator()(int slot, const Site& s) const {
-        return __uint_as_float(
-            __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane4 + (uint32_t)slot * 256u, s.off, 0));
-    }
-};
-
-// The plain reader by site index (NU_SIGMA: the first iteration's messages
-// from the syndrome).
-template <int MODE>
-struct IdxReader {
-    Reader<MODE> R;
-    __device__ __forceinline__ float operator()(int slot, const Site& s) const {
-        return R(slot, s.v);
-    }
-};
-
 // e^{mu} of the four members of face f(u, n), u = v + (ox, oy, oz), as
 // k_bp_iter forms them at u with the scalar prior a0 = e^{l0}.
 template <class RD>
 __device__ __forceinline__ void face_inputs(const RD& R, const Pos& p, float a0, int ox, int oy,
                                             int oz, int n, float a[4]) {
-    const Site u = at(p, ox, oy, oz);
-    const Site u_xm = at(p, ox - 1, oy, oz), u_ym = at(p, ox, oy - 1, oz),
-               u_zm = at(p, ox, oy, oz - 1);
+    const Site u = p.at(ox, oy, oz);
+    const Site u_xm = p.at(ox - 1, oy, oz), u_ym = p.at(ox, oy - 1, oz),
+               u_zm = p.at(ox, oy, oz - 1);
     if (n == 2) {  // members e(u,x), e(u+y,x), e(u,y), e(u+x,y)
         const float px = a0 * (R(9, u_ym) * R(5, u_zm));
         const float py = a0 * (R(11, u_xm) * R(1, u_zm));
-        const Site u_yp = at(p, ox, oy + 1, oz), u_xp = at(p, ox + 1, oy, oz);
+        const Site u_yp = p.at(ox, oy + 1, oz), u_xp = p.at(ox + 1, oy, oz);
         a[0] = px * R(4, u);
-        a[1] = a0 * R(8, u_yp) * R(4, u_yp) * R(5, at(p, ox, oy + 1, oz - 1));
+        a[1] = a0 * R(8, u_yp) * R(4, u_yp) * R(5, p.at(ox, oy + 1, oz - 1));
         a[2] = py * R(0, u);
-        a[3] = a0 * R(10, u_xp) * R(0, u_xp) * R(1, at(p, ox + 1, oy, oz - 1));
+        a[3] = a0 * R(10, u_xp) * R(0, u_xp) * R(1, p.at(ox + 1, oy, oz - 1));
     } else if (n == 1) {  // members e(u,x), e(u+z,x), e(u,z), e(u+x,z)
         const float px = a0 * (R(9, u_ym) * R(5, u_zm));
         const float pz = a0 * (R(7, u_xm) * R(3, u_ym));
-        const Site u_zp = at(p, ox, oy, oz + 1), u_xp = at(p, ox + 1, oy, oz);
+        const Site u_zp = p.at(ox, oy, oz + 1), u_xp = p.at(ox + 1, oy, oz);
         a[0] = px * R(8, u);
-        a[1] = a0 * R(8, u_zp) * R(4, u_zp) * R(9, at(p, ox, oy - 1, oz + 1));
+        a[1] = a0 * R(8, u_zp) * R(4, u_zp) * R(9, p.at(ox, oy - 1, oz + 1));
         a[2] = pz * R(2, u);
-        a[3] = a0 * R(6, u_xp) * R(2, u_xp) * R(3, at(p, ox + 1, oy - 1, oz));
+        a[3] = a0 * R(6, u_xp) * R(2, u_xp) * R(3, p.at(ox + 1, oy - 1, oz));
     } else {  // members e(u,y), e(u+z,y), e(u,z), e(u+y,z)
         const float py = a0 * (R(11, u_xm) * R(1, u_zm));
         const float pz = a0 * (R(7, u_xm) * R(3, u_ym));
-        const Site u_zp = at(p, ox, oy, oz + 1), u_yp = at(p, ox, oy + 1, oz);
+        const Site u_zp = p.at(ox, oy, oz + 1), u_yp = p.at(ox, oy + 1, oz);
         a[0] = py * R(10, u);
-        a[1] = a0 * R(10, u_zp) * R(0, u_zp) * R(11, at(p, ox - 1, oy, oz + 1));
+        a[1] = a0 * R(10, u_zp) * R(0, u_zp) * R(11, p.at(ox - 1, oy, oz + 1));
         a[2] = pz * R(6, u);
-        a[3] = a0 * R(6, u_yp) * R(2, u_yp) * R(7, at(p, ox - 1, oy + 1, oz));
+        a[3] = a0 * R(6, u_yp) * R(2, u_yp) * R(7, p.at(ox - 1, oy + 1, oz));
     }
 }
 
@@ -493,7 +522,7 @@ __device__ __forceinline__ void face_messages(const RD& R, const Src& S, const I
                                               int ox, int oy, int oz, int n, float out[4]) {
     float a[4];
     face_inputs(R, p, S.a0, ox, oy, oz, n, a);
-    const Site u = at(p, ox, oy, oz);
+    const Site u = p.at(ox, oy, oz);
     const uint32_t s = shot_bit(syn_w + ((int64_t)n * S.N + u.v) * S.ld_syn, it.lane);
     check_rule(a, s ? -K : K, out);
 }
@@ -542,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
             el[2] = a0 * f1[2] * f0[2] * xm1[3] * ym0[3];
             zc0 = f0[1];
             zc1 = f1[1];
-            const int v = at(p, 0, 0, 0).v;
+            const int v = p.at(0, 0, 0).v;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int64_t e = (int64_t)c * S.N + v;
@@ -557,11 +586,8 @@ __global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
         }
     };
     if constexpr (MODE == NU_LOAD) {
-        BufReader R;
-        const float* word = S.nu + word_base(it.w, 12 * (int64_t)S.N);
-        R.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(word), (short)0,
-                                                   (int)(3072u * (uint32_t)S.N), 0x00020000);
-        R.lane4 = (uint32_t)it.lane * 4u;
+        const OffReader R{reinterpret_cast<const char*>(S.nu + word_base(it.w, 12 * (int64_t)S.N)),
+                          (uint32_t)it.lane * 4u};
         walk(R);
     } else {
         IdxReader<MODE> R{reader_of<MODE>(S, it)};
@@ -766,6 +792,17 @@ static size_t residency_lds(int blocks_per_cu) {
     return (size_t)b;
 }
 
+namespace {
+template <int MODE, bool EP, int FOLD, bool DAMP = false>
+void iter_kernel(dim3 grid, size_t lds, hipStream_t st, const Src& S, const Tiling& tl, float K,
+                 float damp, float* out) {
+    k_bp_iter<MODE, EP, FOLD, DAMP><<<grid, dim3(kBlock), lds, st>>>(S, tl, K, damp, out);
+}
+}  // namespace
+
+// One word of messages addressable with 32-bit offsets (L <= 111).
+static bool word_fits_32(Geo g) { return (int64_t)g.N * 3072 < ((int64_t)1 << 32); }
+
 int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu_in,
                    float* nu_out, int kclass) {
     if (a.nw == 0) return TC3D_OK;
@@ -775,46 +812,45 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     int rc = before_launch(c, kclass);
     if (rc) return rc;
     const Src S = make_src(g, a, nu_in);
-    const dim3 grid((unsigned)blocks), block(kBlock);
+    const dim3 grid((unsigned)blocks);
     const size_t lds =
         mode == NU_LOAD ? residency_lds(a.occupancy ? a.occupancy : kLoadIterBlocksPerCu) : 0;
     const float damp = a.damp;
+    const hipStream_t st = c.stream;
+    const float K = a.K;
     if (a.llr0) {
         if (damp != 0.0f) return TC3D_EINVAL;  // damping goes with the scalar prior
         if (mode == NU_ZERO && a.fold)
-            k_bp_iter<NU_ZERO, true, 1><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_ZERO, true, 1>(grid, 0, st, S, tl, K, damp, nu_out);
         else if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, true, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_ZERO, true, 0>(grid, 0, st, S, tl, K, damp, nu_out);
         else if (mode == NU_LOAD && a.fold)
-            k_bp_iter<NU_LOAD, true, 2><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_LOAD, true, 2>(grid, lds, st, S, tl, K, damp, nu_out);
         else if (mode == NU_LOAD)
-            k_bp_iter<NU_LOAD, true, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_LOAD, true, 0>(grid, lds, st, S, tl, K, damp, nu_out);
         else
             return TC3D_EINVAL;  // the syndrome-implied first state needs a scalar prior
     } else if (damp != 0.0f) {
         if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, false, 0, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp,
-                                                                            nu_out);
+            iter_kernel<NU_ZERO, false, 0, true>(grid, 0, st, S, tl, K, damp, nu_out);
         else if (mode == NU_SIGMA)
-            k_bp_iter<NU_SIGMA, false, 0, true><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp,
-                                                                             nu_out);
+            iter_kernel<NU_SIGMA, false, 0, true>(grid, 0, st, S, tl, K, damp, nu_out);
         else
-            k_bp_iter<NU_LOAD, false, 0, true><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp,
-                                                                              nu_out);
+            iter_kernel<NU_LOAD, false, 0, true>(grid, lds, st, S, tl, K, damp, nu_out);
     } else {
         if (mode == NU_ZERO)
-            k_bp_iter<NU_ZERO, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_ZERO, false, 0>(grid, 0, st, S, tl, K, damp, nu_out);
         else if (mode == NU_SIGMA)
-            k_bp_iter<NU_SIGMA, false, 0><<<grid, block, 0, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_SIGMA, false, 0>(grid, 0, st, S, tl, K, damp, nu_out);
         else
-            k_bp_iter<NU_LOAD, false, 0><<<grid, block, lds, c.stream>>>(S, tl, a.K, damp, nu_out);
+            iter_kernel<NU_LOAD, false, 0>(grid, lds, st, S, tl, K, damp, nu_out);
     }
     return after_launch(c);
 }
 
 bool bp_final_fits(Geo g, const BpArgs& a) {
     // scalar prior, undamped; one word's messages addressed by 32-bit offsets
-    return !a.llr0 && a.damp == 0.0f && (int64_t)g.N * 3072 < ((int64_t)1 << 32);
+    return !a.llr0 && a.damp == 0.0f && word_fits_32(g);
 }
 
 // Planes each wavefront of the fused last iteration walks.
