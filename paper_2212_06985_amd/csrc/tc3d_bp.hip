@@ -83,7 +83,16 @@ struct Tiling {
     uint32_t per_word;          // nTX * nTY * TX * TY * L logical sites
     FastDiv n_sg;               // site groups of kWaves per word
     FastDiv col, plane, row, tiles_x;  // TX*TY*L, TX*TY, TX, nTX
+    uint32_t xq, xr;            // grid size G: G / 8 and G % 8 (blocks per XCD)
 };
+
+// The grid of a launch over nw words (set before the launch).
+int64_t set_grid(Tiling& tl, int64_t nw) {
+    const int64_t blocks = (int64_t)tl.n_sg.d * nw;
+    tl.xq = (uint32_t)(blocks >> 3);
+    tl.xr = (uint32_t)(blocks & 7);
+    return blocks;
+}
 
 struct Src {
     const float* __restrict__ nu;    // NU_LOAD
@@ -105,19 +114,27 @@ struct Item {
 
 __device__ __forceinline__ Item item_of(const Tiling& tl) {
     Item it;
-    const uint32_t lb = (uint32_t)xcd_block(blockIdx.x, gridDim.x);
+    // hardware block b -> logical block: the blocks each XCD runs (b % 8) are
+    // a contiguous range (the 32-bit form of xcd_block, grid from the host)
+    const uint32_t b = blockIdx.x, j = b & 7, bi = b >> 3;
+    const uint32_t lb = j < tl.xr ? j * (tl.xq + 1) + bi : tl.xr + j * tl.xq + bi;
     const uint32_t w = div_of(lb, tl.n_sg);
     const uint32_t sg = lb - w * tl.n_sg.d;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     it.w = w;
     it.lane = (int)(threadIdx.x & 63);
     const uint32_t i = sg * kWaves + wave;
-    const uint32_t tile = div_of(i, tl.col);
-    const uint32_t r = i - tile * tl.col.d;
+    // tile columns (a uniform branch: whole planes need no tile index)
+    uint32_t tile = 0, r = i, tx = 0, ty = 0;
+    if (tl.nTX * tl.nTY != 1) {
+        tile = div_of(i, tl.col);
+        r = i - tile * tl.col.d;
+        ty = div_of(tile, tl.tiles_x);
+        tx = tile - ty * tl.tiles_x.d;
+    }
     const uint32_t z = div_of(r, tl.plane);
     const uint32_t r2 = r - z * tl.plane.d;
     const uint32_t yy = div_of(r2, tl.row), xx = r2 - yy * tl.row.d;
-    const uint32_t ty = div_of(tile, tl.tiles_x), tx = tile - ty * tl.tiles_x.d;
     it.z = (int)z;
     it.x = (int)(tx * tl.TX + xx);
     it.y = (int)(ty * tl.TY + yy);
@@ -808,7 +825,7 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (a.nw == 0) return TC3D_OK;
     Tiling tl;
     if (!tiling_of(g, a, &tl)) return TC3D_EINVAL;
-    const int64_t blocks = (int64_t)tl.n_sg.d * a.nw;
+    const int64_t blocks = set_grid(tl, a.nw);
     int rc = before_launch(c, kclass);
     if (rc) return rc;
     const Src S = make_src(g, a, nu_in);
@@ -888,7 +905,7 @@ int launch_bp_final(const Ctx& c, Geo g, const BpArgs& a, int mode, const float*
     if (a.nw == 0) return TC3D_OK;
     Tiling tl;
     if (!final_tiling(g, a.nw, kFinalRun, &tl)) return TC3D_EINVAL;
-    const int64_t blocks = (int64_t)tl.n_sg.d * a.nw;
+    const int64_t blocks = set_grid(tl, a.nw);
     int rc = before_launch(c, TC3D_K_BP_POST);
     if (rc) return rc;
     const Src S = make_src(g, a, nu);
@@ -964,7 +981,7 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
     if (a.nw == 0) return TC3D_OK;
     Tiling tl;
     if (!tiling_of(g, a, &tl)) return TC3D_EINVAL;
-    const int64_t blocks = (int64_t)tl.n_sg.d * a.nw;
+    const int64_t blocks = set_grid(tl, a.nw);
     int rc = before_launch(c, TC3D_K_BP_POST);
     if (rc) return rc;
     const Src S = make_src(g, a, nu);
