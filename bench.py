@@ -399,11 +399,15 @@ def bp_message_bytes(bp_iters, per_edge_prior=False, fused=True):
     iteration 2 only writes, iterations 3..T read and write and the posterior
     reads; fused, iteration T and the posterior are one pass that reads once.
     Per-edge prior: the first iteration writes, every later one reads and
-    writes, the posterior reads, and every iteration reads the 4-byte prior."""
+    writes, the posterior reads, and every iteration reads the 4-byte prior;
+    fused (T >= 2), iteration T and the posterior read the state and the
+    prior once."""
     T = bp_iters
     if T <= 0:
         return 0.0
     if per_edge_prior:
+        if fused and T >= 2:
+            return 20.0 + 36.0 * (T - 2) + 20.0
         return 20.0 + 36.0 * (T - 1) + 16.0
     if T == 1:
         return 0.0

@@ -495,50 +495,77 @@ __global__ __launch_bounds__(kBlock) void k_bp_post(Src S, Tiling tl,
 // The decision and posterior are bit-identical to k_bp_iter followed by
 // k_bp_post, while iteration T's messages (16 B per edge and shot) are
 // neither written nor read back; the price is about twice the loads, which
-// L2 serves, and the check rules of six more faces. Scalar prior, undamped.
+// L2 serves, and the check rules of the neighbouring faces. Undamped; per-edge
+// priors in the folded form of a whole decode.
 
 // e^{mu} of the four members of face f(u, n), u = v + (ox, oy, oz), as
-// k_bp_iter forms them at u with the scalar prior a0 = e^{l0}.
-template <class RD>
-__device__ __forceinline__ void face_inputs(const RD& R, const Pos& p, float a0, int ox, int oy,
-                                            int oz, int n, float a[4]) {
+// k_bp_iter forms them at u: with the scalar prior a0 = e^{l0} (EP false),
+// or (EP) from a folded state, where slots 8, 10, 6 carry the per-edge priors
+// and only the products px, py, pz need a prior of u's own edges.
+template <bool EP, class RD>
+__device__ __forceinline__ void face_inputs(const RD& R, const Src& S, const Item& it,
+                                            const Pos& p, int ox, int oy, int oz, int n,
+                                            float a[4]) {
+    const float a0 = S.a0;
     const Site u = p.at(ox, oy, oz);
     const Site u_xm = p.at(ox - 1, oy, oz), u_ym = p.at(ox, oy - 1, oz),
                u_zm = p.at(ox, oy, oz - 1);
+    // the products of the two incoming messages from faces of other sites
+    const float fx = R(9, u_ym) * R(5, u_zm);
+    const float fy = R(11, u_xm) * R(1, u_zm);
+    const float fz = R(7, u_xm) * R(3, u_ym);
     if (n == 2) {  // members e(u,x), e(u+y,x), e(u,y), e(u+x,y)
-        const float px = a0 * (R(9, u_ym) * R(5, u_zm));
-        const float py = a0 * (R(11, u_xm) * R(1, u_zm));
         const Site u_yp = p.at(ox, oy + 1, oz), u_xp = p.at(ox + 1, oy, oz);
-        a[0] = px * R(4, u);
-        a[1] = a0 * R(8, u_yp) * R(4, u_yp) * R(5, p.at(ox, oy + 1, oz - 1));
-        a[2] = py * R(0, u);
-        a[3] = a0 * R(10, u_xp) * R(0, u_xp) * R(1, p.at(ox + 1, oy, oz - 1));
+        const Site u_yp_zm = p.at(ox, oy + 1, oz - 1), u_xp_zm = p.at(ox + 1, oy, oz - 1);
+        if constexpr (EP) {
+            a[0] = (prior<true>(S, it, 0, u.v) * fx) * R(4, u);
+            a[1] = R(8, u_yp) * R(4, u_yp) * R(5, u_yp_zm);
+            a[2] = (prior<true>(S, it, 1, u.v) * fy) * R(0, u);
+            a[3] = R(10, u_xp) * R(0, u_xp) * R(1, u_xp_zm);
+        } else {
+            a[0] = (a0 * fx) * R(4, u);
+            a[1] = a0 * R(8, u_yp) * R(4, u_yp) * R(5, u_yp_zm);
+            a[2] = (a0 * fy) * R(0, u);
+            a[3] = a0 * R(10, u_xp) * R(0, u_xp) * R(1, u_xp_zm);
+        }
     } else if (n == 1) {  // members e(u,x), e(u+z,x), e(u,z), e(u+x,z)
-        const float px = a0 * (R(9, u_ym) * R(5, u_zm));
-        const float pz = a0 * (R(7, u_xm) * R(3, u_ym));
         const Site u_zp = p.at(ox, oy, oz + 1), u_xp = p.at(ox + 1, oy, oz);
-        a[0] = px * R(8, u);
-        a[1] = a0 * R(8, u_zp) * R(4, u_zp) * R(9, p.at(ox, oy - 1, oz + 1));
-        a[2] = pz * R(2, u);
-        a[3] = a0 * R(6, u_xp) * R(2, u_xp) * R(3, p.at(ox + 1, oy - 1, oz));
+        const Site u_zp_ym = p.at(ox, oy - 1, oz + 1), u_xp_ym = p.at(ox + 1, oy - 1, oz);
+        if constexpr (EP) {
+            a[0] = fx * R(8, u);
+            a[1] = R(8, u_zp) * R(4, u_zp) * R(9, u_zp_ym);
+            a[2] = (prior<true>(S, it, 2, u.v) * fz) * R(2, u);
+            a[3] = R(6, u_xp) * R(2, u_xp) * R(3, u_xp_ym);
+        } else {
+            a[0] = (a0 * fx) * R(8, u);
+            a[1] = a0 * R(8, u_zp) * R(4, u_zp) * R(9, u_zp_ym);
+            a[2] = (a0 * fz) * R(2, u);
+            a[3] = a0 * R(6, u_xp) * R(2, u_xp) * R(3, u_xp_ym);
+        }
     } else {  // members e(u,y), e(u+z,y), e(u,z), e(u+y,z)
-        const float py = a0 * (R(11, u_xm) * R(1, u_zm));
-        const float pz = a0 * (R(7, u_xm) * R(3, u_ym));
         const Site u_zp = p.at(ox, oy, oz + 1), u_yp = p.at(ox, oy + 1, oz);
-        a[0] = py * R(10, u);
-        a[1] = a0 * R(10, u_zp) * R(0, u_zp) * R(11, p.at(ox - 1, oy, oz + 1));
-        a[2] = pz * R(6, u);
-        a[3] = a0 * R(6, u_yp) * R(2, u_yp) * R(7, p.at(ox - 1, oy + 1, oz));
+        const Site u_zp_xm = p.at(ox - 1, oy, oz + 1), u_yp_xm = p.at(ox - 1, oy + 1, oz);
+        if constexpr (EP) {
+            a[0] = fy * R(10, u);
+            a[1] = R(10, u_zp) * R(0, u_zp) * R(11, u_zp_xm);
+            a[2] = fz * R(6, u);
+            a[3] = R(6, u_yp) * R(2, u_yp) * R(7, u_yp_xm);
+        } else {
+            a[0] = (a0 * fy) * R(10, u);
+            a[1] = a0 * R(10, u_zp) * R(0, u_zp) * R(11, u_zp_xm);
+            a[2] = (a0 * fz) * R(6, u);
+            a[3] = a0 * R(6, u_yp) * R(2, u_yp) * R(7, u_yp_xm);
+        }
     }
 }
 
 // New messages of face f(u, n) (the caller keeps the members it needs).
-template <class RD>
+template <bool EP, class RD>
 __device__ __forceinline__ void face_messages(const RD& R, const Src& S, const Item& it,
                                               const uint64_t* syn_w, const Pos& p, float K,
                                               int ox, int oy, int oz, int n, float out[4]) {
     float a[4];
-    face_inputs(R, p, S.a0, ox, oy, oz, n, a);
+    face_inputs<EP>(R, S, it, p, ox, oy, oz, n, a);
     const Site u = p.at(ox, oy, oz);
     const uint32_t s = shot_bit(syn_w + ((int64_t)n * S.N + u.v) * S.ld_syn, it.lane);
     check_rule(a, s ? -K : K, out);
@@ -549,7 +576,10 @@ __device__ __forceinline__ void face_messages(const RD& R, const Src& S, const I
 // the column computed for its own faces, so only the first site of the run
 // recomputes them, and the column's addresses change by one plane per step.
 // Item z indexes the runs (ceil(L / ZR) per column).
-template <int MODE, int ZR>
+// EP: the state is folded (per-edge priors); the new messages that a folded
+// state keeps with their edge's prior (slots 8, 10, 6) enter the posterior
+// with it, as k_bp_post<.., true, true> reads them.
+template <int MODE, int ZR, bool EP>
 __global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
                                                      uint64_t* __restrict__ corr, int64_t ld_c,
                                                      float* __restrict__ post,
@@ -565,30 +595,36 @@ __global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
     auto walk = [&](const auto& R) {
         float t[4];
         set_z(p, z0, L);
-        face_messages(R, S, it, syn_w, p, K, 0, 0, -1, 0, t);
+        face_messages<EP>(R, S, it, syn_w, p, K, 0, 0, -1, 0, t);
         float zc0 = t[1];  // message of f(v-z, 0) to e(v, y)
-        face_messages(R, S, it, syn_w, p, K, 0, 0, -1, 1, t);
+        face_messages<EP>(R, S, it, syn_w, p, K, 0, 0, -1, 1, t);
         float zc1 = t[1];  // message of f(v-z, 1) to e(v, x)
 #pragma unroll 1
         for (int z = z0; z < z0 + ZR && z < L; ++z) {
             if (z != z0) set_z(p, z, L);
             float f0[4], f1[4], f2[4], xm1[4], xm2[4], ym0[4], ym2[4];
-            face_messages(R, S, it, syn_w, p, K, 0, 0, 0, 0, f0);
-            face_messages(R, S, it, syn_w, p, K, 0, 0, 0, 1, f1);
-            face_messages(R, S, it, syn_w, p, K, 0, 0, 0, 2, f2);
-            face_messages(R, S, it, syn_w, p, K, -1, 0, 0, 1, xm1);
-            face_messages(R, S, it, syn_w, p, K, -1, 0, 0, 2, xm2);
-            face_messages(R, S, it, syn_w, p, K, 0, -1, 0, 0, ym0);
-            face_messages(R, S, it, syn_w, p, K, 0, -1, 0, 2, ym2);
+            face_messages<EP>(R, S, it, syn_w, p, K, 0, 0, 0, 0, f0);
+            face_messages<EP>(R, S, it, syn_w, p, K, 0, 0, 0, 1, f1);
+            face_messages<EP>(R, S, it, syn_w, p, K, 0, 0, 0, 2, f2);
+            face_messages<EP>(R, S, it, syn_w, p, K, -1, 0, 0, 1, xm1);
+            face_messages<EP>(R, S, it, syn_w, p, K, -1, 0, 0, 2, xm2);
+            face_messages<EP>(R, S, it, syn_w, p, K, 0, -1, 0, 0, ym0);
+            face_messages<EP>(R, S, it, syn_w, p, K, 0, -1, 0, 2, ym2);
             // the products k_bp_post forms from the stored slots 8 4 | 9 5,
             // 10 0 | 11 1 and 6 2 | 7 3
+            const int v = p.at(0, 0, 0).v;
             float el[3];
-            el[0] = a0 * f2[0] * f1[0] * ym2[1] * zc1;
-            el[1] = a0 * f2[2] * f0[0] * xm2[3] * zc0;
-            el[2] = a0 * f1[2] * f0[2] * xm1[3] * ym0[3];
+            if constexpr (EP) {  // slots 8, 10, 6 folded with their edge's prior
+                el[0] = 1.0f * (f2[0] * prior<true>(S, it, 0, v)) * f1[0] * ym2[1] * zc1;
+                el[1] = 1.0f * (f2[2] * prior<true>(S, it, 1, v)) * f0[0] * xm2[3] * zc0;
+                el[2] = 1.0f * (f1[2] * prior<true>(S, it, 2, v)) * f0[2] * xm1[3] * ym0[3];
+            } else {
+                el[0] = a0 * f2[0] * f1[0] * ym2[1] * zc1;
+                el[1] = a0 * f2[2] * f0[0] * xm2[3] * zc0;
+                el[2] = a0 * f1[2] * f0[2] * xm1[3] * ym0[3];
+            }
             zc0 = f0[1];
             zc1 = f1[1];
-            const int v = p.at(0, 0, 0).v;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int64_t e = (int64_t)c * S.N + v;
@@ -866,8 +902,9 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 }
 
 bool bp_final_fits(Geo g, const BpArgs& a) {
-    // scalar prior, undamped; one word's messages addressed by 32-bit offsets
-    return !a.llr0 && a.damp == 0.0f && word_fits_32(g);
+    // undamped, per-edge priors folded into the state; one word's messages
+    // addressed by 32-bit offsets
+    return (!a.llr0 || a.fold) && a.damp == 0.0f && word_fits_32(g);
 }
 
 // Planes each wavefront of the fused last iteration walks.
@@ -912,11 +949,16 @@ int launch_bp_final(const Ctx& c, Geo g, const BpArgs& a, int mode, const float*
     const dim3 grid((unsigned)blocks), block(kBlock);
     const size_t lds =
         mode == NU_LOAD ? residency_lds(a.occupancy ? a.occupancy : kLoadFinalBlocksPerCu) : 0;
-    if (mode == NU_SIGMA)
-        k_bp_final<NU_SIGMA, kFinalRun>
+    if (a.llr0 && mode == NU_LOAD)
+        k_bp_final<NU_LOAD, kFinalRun, true>
+            <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
+    else if (a.llr0)
+        return TC3D_EINVAL;  // a folded state is always stored
+    else if (mode == NU_SIGMA)
+        k_bp_final<NU_SIGMA, kFinalRun, false>
             <<<grid, block, 0, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
     else if (mode == NU_LOAD)
-        k_bp_final<NU_LOAD, kFinalRun>
+        k_bp_final<NU_LOAD, kFinalRun, false>
             <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
     else
         return TC3D_EINVAL;

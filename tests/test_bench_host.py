@@ -97,9 +97,13 @@ def test_path_roofline_model():
     assert bench.bp_message_bytes(2) == 0.0 and bench.bp_message_bytes(1) == 0.0
     assert bench.bp_message_bytes(2, fused=False) == 32.0
     # a per-edge prior: the first iteration writes and reads the prior, each
-    # later one reads and writes, the posterior reads
+    # later one reads and writes, the posterior reads; fused, the last
+    # iteration and the posterior read the state and the prior once
     assert bench.path_roofline(6, 1e10, per_edge_prior=True)["bytes_per_unit"] == \
+        20 + 36.0 * 4 + 20 + 6 / 8 + 4
+    assert bench.path_roofline(6, 1e10, per_edge_prior=True, fused=False)["bytes_per_unit"] == \
         20 + 36.0 * 5 + 16 + 6 / 8 + 4
+    assert bench.bp_message_bytes(1, per_edge_prior=True) == 36.0
     # without BP there is no HBM model
     assert bench.path_roofline(0, 1e10) is None
 

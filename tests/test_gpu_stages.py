@@ -409,20 +409,25 @@ def test_bp_decode_resident_equals_streaming(L, n_shots, iters):
     assert res[0].any()
 
 
-def decode_paths(L, n_shots, iters, seed, density, K, modes, l0=math.log(19.0)):
+def decode_paths(L, n_shots, iters, seed, density, K, modes, l0=math.log(19.0), llr=None):
     """tc3d_bp_decode of one random syndrome plane through each kernel path:
-    {path: (correction words, posterior bits as int32)}."""
+    {path: (correction words, posterior bits as int32)}. llr = (lo, hi): per-edge
+    priors drawn uniformly from that range instead of the scalar l0."""
     import torch
     lat = tc.make_lattice(L)
     W = inputs.n_words(n_shots)
     syn = inputs.random_bits(seed, 64 * W, 3 * L ** 3, density)
     d_syn = dev_plane_of_bits(syn)
+    d_llr = None
+    if llr is not None:
+        vals = inputs.random_llr(seed + 1, 64 * W, 3 * L ** 3, *llr)
+        d_llr = to_dev(inputs.rows_to_gpu(vals))
     ws = tc.alloc_workspace(tc.bp_workspace_bytes(lat, n_shots))
     out = {}
     for mode in modes:
         corr = torch.full((3 * L ** 3, W), -1, dtype=torch.int64, device="cuda")
         post = torch.zeros((W, 3 * L ** 3, 64), dtype=torch.float32, device="cuda")
-        tc.bp_decode(lat, d_syn, n_shots, None, l0, K, iters, corr, post, ws, path=mode)
+        tc.bp_decode(lat, d_syn, n_shots, d_llr, l0, K, iters, corr, post, ws, path=mode)
         sync()
         out[mode] = (corr.cpu().numpy(), post.cpu().numpy().view(np.int32))
     return out
@@ -442,6 +447,22 @@ def test_bp_last_iteration_fused_equals_split(L, n_shots, iters, density, K):
     announce(f"fused last BP iteration L={L} S={n_shots} iters={iters} K={K}")
     out = decode_paths(L, n_shots, iters, 700 + L, density, K,
                        (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT))
+    fused, split = out[tc.BP_STREAMING], out[tc.BP_STREAMING_SPLIT]
+    assert np.array_equal(fused[0], split[0])
+    assert np.array_equal(fused[1], split[1])
+    assert fused[0].any()
+
+
+@pytest.mark.parametrize("L,n_shots,iters,lo,hi", [
+    (5, 100, 2, -8.0, 8.0), (6, 130, 6, 0.5, 5.0), (16, 64, 6, -2.0, 6.0),
+    (17, 64, 20, -8.0, 8.0), (48, 64, 6, 1.0, 4.0)])
+def test_bp_fused_last_iteration_with_per_edge_priors(L, n_shots, iters, lo, hi):
+    """The fused last pass on a folded state (per-edge priors, as the CNN
+    prior gives them, negative ones included) against the iteration and
+    posterior launched separately: corrections and posteriors bit for bit."""
+    announce(f"fused last BP iteration, per-edge priors L={L} S={n_shots} iters={iters}")
+    out = decode_paths(L, n_shots, iters, 900 + L, 0.05, 0.9,
+                       (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT), l0=0.0, llr=(lo, hi))
     fused, split = out[tc.BP_STREAMING], out[tc.BP_STREAMING_SPLIT]
     assert np.array_equal(fused[0], split[0])
     assert np.array_equal(fused[1], split[1])
