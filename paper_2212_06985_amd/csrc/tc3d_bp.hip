@@ -822,10 +822,7 @@ bool tiling_of(Geo g, const BpArgs& a, Tiling* out) {
 // and n + 1 do not. 0 (no cap) when the device cannot be queried.
 static constexpr int kLoadIterBlocksPerCu = 4;
 static constexpr int kLoadPostBlocksPerCu = 6;
-#ifndef TC3D_FINAL_OCC
-#define TC3D_FINAL_OCC 4
-#endif
-static constexpr int kLoadFinalBlocksPerCu = TC3D_FINAL_OCC;
+static constexpr int kLoadFinalBlocksPerCu = 4;  // 3, 5, 6 and uncapped measured slower
 static std::atomic<int> g_cu_lds[64];
 
 static size_t residency_lds(int blocks_per_cu) {
@@ -907,11 +904,9 @@ bool bp_final_fits(Geo g, const BpArgs& a) {
     return (!a.llr0 || a.fold) && a.damp == 0.0f && word_fits_32(g);
 }
 
-// Planes each wavefront of the fused last iteration walks.
-#ifndef TC3D_FINAL_ZR
-#define TC3D_FINAL_ZR 8
-#endif
-static constexpr int kFinalRun = TC3D_FINAL_ZR;
+// Planes each wavefront of the fused last iteration walks (1, 2, 4 and 16
+// measured slower at L = 48; unrolling the walk by 2 too).
+static constexpr int kFinalRun = 8;
 
 namespace {
 // Work items of k_bp_final: (x, y, run of zr planes) per word, x fastest.
