@@ -144,6 +144,16 @@ def stored_ceiling(kernel: str, workload: str):
     return None
 
 
+def profile_key(workload: str, L=None, shots=None, batch_shots=0) -> str:
+    """The name the stored counter summaries of a run are looked up under: they
+    describe the workload's own launches, so with a lattice, shot count or
+    batch of its own no summary applies."""
+    base = WORKLOADS[workload]
+    if (L and L != base["L"]) or (shots and shots != base["shots"]) or batch_shots:
+        return workload + "_custom"
+    return workload
+
+
 def stored_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel sources."""
@@ -680,6 +690,7 @@ def main():
                                                args.cpu_seconds, tc)
         print(json.dumps(out), flush=True)
         return
+    prof_key = profile_key(args.workload, args.L, args.shots, args.batch_shots)
     if args.L:
         cfg["L"] = args.L
         if args.noisy_cycles is None:
@@ -719,14 +730,14 @@ def main():
                                               "main", graph=graph)
     qubit_cycles = n * cycles * S * steps
     value = qubit_cycles / wall
-    roof = roofline(per_class, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
+    roof = roofline(per_class, n, batch, lat.n_sites, prof_key, forwards=cycles * steps,
                     shots_padded=64 * W, per_edge_prior=decoder == "cnn",
                     bp_iters=main_cfg["bp"])
     # with the CNN prior, the conv launches' own (MFMA) roofline as well
     cnn_roof = None
     if decoder == "cnn" and per_class["cnn"]["launches"]:
         only = {k: (v if k == "cnn" else {"ms": 0.0, "launches": 0}) for k, v in per_class.items()}
-        cnn_roof = roofline(only, n, batch, lat.n_sites, args.workload, forwards=cycles * steps,
+        cnn_roof = roofline(only, n, batch, lat.n_sites, prof_key, forwards=cycles * steps,
                             shots_padded=64 * W)
 
     comparison = None
@@ -744,7 +755,7 @@ def main():
                       "value": n * cycles * S * c_steps / w2, "unit": "qubit-cycles/s",
                       "ms_per_step": w2 / c_steps * 1e3, "ler": ler2,
                       "mean_residual_syndrome": resid2,
-                      "roofline": roofline(pc2, n, batch, lat.n_sites, args.workload,
+                      "roofline": roofline(pc2, n, batch, lat.n_sites, prof_key,
                                            forwards=cycles * c_steps, shots_padded=64 * W,
                                            per_edge_prior=other == "cnn",
                                            bp_iters=other_cfg["bp"]),

@@ -133,3 +133,12 @@ def test_resident_bp_roofline_is_alu_bound():
 def test_path_roofline_is_none_for_a_resident_decode():
     assert bench.path_roofline(20, 1e10, n_sites=1728) is None
     assert bench.path_roofline(20, 1e10, n_sites=48 ** 3)["bytes_per_unit"] == 582.5
+
+
+def test_counter_summaries_apply_only_to_their_own_launches():
+    assert bench.profile_key("c5") == "c5"
+    assert bench.profile_key("c5", L=48, shots=2048) == "c5"
+    assert bench.profile_key("c4", L=16) == "c4_custom"
+    assert bench.profile_key("c5", shots=4096) == "c5_custom"
+    assert bench.profile_key("c2", batch_shots=4096) == "c2_custom"
+    assert bench.stored_traffic("cnn", bench.profile_key("c4", L=16)) is None
