@@ -99,7 +99,7 @@ RESIDENT_SLOTS_PER_SITE_ITER = 3 * (4 + 8 + 10 + 4 * (2 + 2 + 1)) + 30
 RESIDENT_SLOTS_PER_SITE_POST = 12
 # one non-packed FP32 operation per lane per clock: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz (the 157.3 TFLOP/s vector peak counts packed FMAs, 4 FLOP
-# per lane per clock, which this build does not use)
+# per lane per clock, which the library does not use)
 VALU_SLOTS_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2212_06985_amd", "weights", "cnn_L12_long.npy")
