@@ -39,8 +39,8 @@
  * 256-byte aligned.
  *
  * Execution: every call is asynchronous on `stream` (a hipStream_t; NULL is
- * the default stream) except tc3d_run_cycles_timed, tc3d_run_jobs and
- * tc3d_autotune, which block. Calls return TC3D_OK, or a negative TC3D_E*
+ * the default stream) except tc3d_run_cycles_timed, tc3d_run_jobs,
+ * tc3d_autotune and runs with the TC3D_RUN_GRAPH flag, which block. Calls return TC3D_OK, or a negative TC3D_E*
  * code for invalid arguments or a failed launch; faults during execution
  * surface at the caller's next synchronisation. No exception crosses the ABI.
  *
@@ -276,10 +276,11 @@ typedef struct {
                                   and waits for it (for runs of many short
                                   launches); never changes a result          */
     int32_t bp_occupancy;      /* workgroups per compute unit of the streaming
-                                  BP iterations that read stored messages:
-                                  0 = the library's choice (4), 1..8 = that
-                                  many (8: no cap); a tuning knob that never
-                                  changes a result                            */
+                                  BP passes that read stored messages (the
+                                  iterations and the fused last pass): 0 = the
+                                  library's choice (4), 1..8 = that many (8: no
+                                  cap); a tuning knob that never changes a
+                                  result                                      */
 } tc3d_run_params;
 
 enum { TC3D_RUN_GRAPH = 1 };
