@@ -3,6 +3,9 @@
 * L = 12, p = q in {4, 5, 5.5, 6}%, 12 noisy cycles + 1 perfect, BP 20 +
   P F F P F F, 1024 shots per p; and the same at p = 8%, where many shots
   fail, so that the logical error rates compare non-trivially.
+* L = 12 at 5.5% with the workload's full 100,032 shots in one batch:
+  resident and streaming kernels identical on every shot, sampled shots
+  against the oracle.
 * L = 48, p = q = 5%, all 48 noisy cycles + 1 perfect, in the benchmark's
   launch configuration (2048 shots in one batch): 16 shots spread over the
   words, each against the oracle's run of that shot.
@@ -83,6 +86,38 @@ def test_l12_pbp_config_per_shot(p):
     assert n_div <= S // 20
     if p == 0.08:  # the failing regime: the comparison is not of two zeros
         assert (m_o != 0).mean() > 0.2
+
+
+def test_l12_full_size_run():
+    """L = 12 at p = q = 5.5% with the workload's full 100,032 shots in one
+    batch (its launch configuration: each shot decoded in one workgroup's LDS),
+    12 + 1 cycles: the same run through the streaming kernels (stored messages,
+    fused last pass) ends identically for every shot, and 16 shots spread over
+    the 1563 words (word boundaries, the ragged last word) equal the oracle's
+    runs of those shots."""
+    L, S, p = 12, 100_032, 0.055
+    kw = dict(p=p, q=p, noisy_cycles=12, bp_iters=20, n_sweeps=6, pflip_mask=PFFPFF,
+              n_shots=S, seed=1)
+    announce(f"L={L} p=q={p} 12+1 cycles, {S} shots in one batch, resident and streaming")
+    m_r, odd_r, e_r = gpu_run(L, kw)
+    m_s, odd_s, e_s = gpu_run(L, dict(kw, bp_path=tc.BP_STREAMING))
+    assert np.array_equal(m_r, m_s) and np.array_equal(odd_r, odd_s)
+    assert np.array_equal(e_r, e_s)
+    samples = [0, 1, 63, 64, 4095, 20000, 31999, 50000, 64000, 77777, 90000, 99967, 99968,
+               100000, 100030, 100031]
+    o = Oracle(L)
+    prm_o = make_params(p, p, 12, 20, 6, PFFPFF, seed=1)
+    res = {}
+    with cf.ThreadPoolExecutor(min(len(samples), workers())) as ex:
+        futs = {ex.submit(o.run_cycles, prm_o, 1, s): s for s in samples}
+        for f in cf.as_completed(futs):
+            res[futs[f]] = f.result()
+    m_o = np.array([res[s][0][0] for s in samples])
+    e_o = np.array([res[s][2][0] for s in samples])
+    n_div = compare_runs(o, L, kw, m_r[samples], e_r[samples], m_o, e_o, samples)
+    announce(f"  resident == streaming on all {S} shots; sampled shots diverged "
+             f"{n_div}/{len(samples)}; LER any axis {(m_r != 0).mean():.5f}")
+    assert n_div <= 1
 
 
 def test_l48_full_run_sampled_shots():
