@@ -244,9 +244,11 @@ typedef struct {
                                   0 picks a size that keeps the workspace near
                                   24 GiB                                         */
     int32_t bp_tile;           /* BP traversal (a tuning knob that never changes
-                                  results): 0 = whole x-y planes in memory
-                                  order; T > 0: T x T site columns; T < 0:
-                                  bands of whole x rows, -T rows high          */
+                                  results): 0 = the library's choice (whole
+                                  x-y planes in memory order up to L = 64,
+                                  bands of 8 rows above); T > 0: T x T site
+                                  columns; T < 0: bands of whole x rows, -T
+                                  rows high (-L: whole planes)                */
     uint32_t subset_mask;      /* bit k set: sweep k is a subset p-flip sweep
                                   (see tc3d_subset_pflip_sweep); the j-th of the
                                   m such sweeps of cycle t acts on edge class

@@ -211,6 +211,23 @@ def test_fused_last_iteration_run_equals_split_run():
     assert a[2].any()
 
 
+def test_large_lattice_traversals_decode_alike():
+    """From L = 72 the default traversal of the stored-message BP iterations
+    is bands of 8 rows; whole planes (bp_tile = -L), 16 x 16 columns and the
+    default decode every shot identically (p = q = 5%, 2 + 1 cycles)."""
+    L, S = 72, 64
+    out = []
+    for tile in (0, -L, 16):
+        prm = tc.make_run_params(0.05, 0.05, 2, 20, 6, PFFPFF, n_shots=S, seed=5,
+                                 bp_tile=tile)
+        m, o, e, _ = gpu_run(L, prm)
+        out.append((m, o, e))
+    for m, o, e in out[1:]:
+        assert np.array_equal(m, out[0][0]) and np.array_equal(o, out[0][1])
+        assert np.array_equal(e, out[0][2])
+    assert out[0][2].any()
+
+
 # ----------------------------------------------------------- full size
 def test_full_size_sampled_shots_and_invariants():
     """L = 48, p = q = 0.05, BP 20 + P F F P F F, 2048 shots in one batch (the
