@@ -579,7 +579,9 @@ __device__ __forceinline__ void face_messages(const RD& R, const Src& S, const I
 // EP: the state is folded (per-edge priors); the new messages that a folded
 // state keeps with their edge's prior (slots 8, 10, 6) enter the posterior
 // with it, as k_bp_post<.., true, true> reads them.
-template <int MODE, int ZR, bool EP>
+// OFF: stored messages read by 32-bit offsets inside a word (L <= 111), else
+// by 64-bit site addresses.
+template <int MODE, int ZR, bool EP, bool OFF>
 __global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
                                                      uint64_t* __restrict__ corr, int64_t ld_c,
                                                      float* __restrict__ post,
@@ -638,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_bp_final(Src S, Tiling tl, float K,
             }
         }
     };
-    if constexpr (MODE == NU_LOAD) {
+    if constexpr (MODE == NU_LOAD && OFF) {
         const OffReader R{reinterpret_cast<const char*>(S.nu + word_base(it.w, 12 * (int64_t)S.N)),
                           (uint32_t)it.lane * 4u};
         walk(R);
@@ -906,9 +908,9 @@ int launch_bp_iter(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 }
 
 bool bp_final_fits(Geo g, const BpArgs& a) {
-    // undamped, per-edge priors folded into the state; one word's messages
-    // addressed by 32-bit offsets
-    return (!a.llr0 || a.fold) && a.damp == 0.0f && word_fits_32(g);
+    // undamped, per-edge priors folded into the state
+    (void)g;
+    return (!a.llr0 || a.fold) && a.damp == 0.0f;
 }
 
 // Planes each wavefront of the fused last iteration walks (1, 2, 4 and 16
@@ -951,16 +953,23 @@ int launch_bp_final(const Ctx& c, Geo g, const BpArgs& a, int mode, const float*
     const dim3 grid((unsigned)blocks), block(kBlock);
     const size_t lds =
         mode == NU_LOAD ? residency_lds(a.occupancy ? a.occupancy : kLoadFinalBlocksPerCu) : 0;
-    if (a.llr0 && mode == NU_LOAD)
-        k_bp_final<NU_LOAD, kFinalRun, true>
+    const bool off = word_fits_32(g);
+    if (a.llr0 && mode == NU_LOAD && off)
+        k_bp_final<NU_LOAD, kFinalRun, true, true>
+            <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
+    else if (a.llr0 && mode == NU_LOAD)
+        k_bp_final<NU_LOAD, kFinalRun, true, false>
             <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
     else if (a.llr0)
         return TC3D_EINVAL;  // a folded state is always stored
     else if (mode == NU_SIGMA)
-        k_bp_final<NU_SIGMA, kFinalRun, false>
+        k_bp_final<NU_SIGMA, kFinalRun, false, false>
             <<<grid, block, 0, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
+    else if (mode == NU_LOAD && off)
+        k_bp_final<NU_LOAD, kFinalRun, false, true>
+            <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
     else if (mode == NU_LOAD)
-        k_bp_final<NU_LOAD, kFinalRun, false>
+        k_bp_final<NU_LOAD, kFinalRun, false, false>
             <<<grid, block, lds, c.stream>>>(S, tl, a.K, corr.p, corr.ld, post, a.ties);
     else
         return TC3D_EINVAL;

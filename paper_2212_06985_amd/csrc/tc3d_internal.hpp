@@ -127,8 +127,7 @@ int launch_bp_post(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* 
 // One more iteration from the state (mode, nu) and the posterior of its
 // result, in one pass that stores no messages; bit-identical to
 // launch_bp_iter followed by launch_bp_post. Needs bp_final_fits: undamped,
-// per-edge priors folded into the state (as a whole decode keeps them),
-// L <= 111.
+// per-edge priors folded into the state (as a whole decode keeps them).
 bool bp_final_fits(Geo g, const BpArgs& a);
 int launch_bp_final(const Ctx& c, Geo g, const BpArgs& a, int mode, const float* nu, Plane corr,
                     float* post);

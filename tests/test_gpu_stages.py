@@ -443,7 +443,7 @@ def test_bp_last_iteration_fused_equals_split(L, n_shots, iters, density, K):
     launched separately, on lattices too large for the resident kernel, odd L
     included: corrections and posteriors bit for bit. L = 111 is the largest
     lattice whose word of messages (L^3 x 3072 B) the fused pass addresses
-    with 32-bit offsets; L = 112 falls back to the separate launches."""
+    with 32-bit offsets; from L = 112 it uses 64-bit site addresses."""
     announce(f"fused last BP iteration L={L} S={n_shots} iters={iters} K={K}")
     out = decode_paths(L, n_shots, iters, 700 + L, density, K,
                        (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT))
