@@ -455,11 +455,12 @@ def test_bp_last_iteration_fused_equals_split(L, n_shots, iters, density, K):
 
 @pytest.mark.parametrize("L,n_shots,iters,lo,hi", [
     (5, 100, 2, -8.0, 8.0), (6, 130, 6, 0.5, 5.0), (16, 64, 6, -2.0, 6.0),
-    (17, 64, 20, -8.0, 8.0), (48, 64, 6, 1.0, 4.0)])
+    (17, 64, 20, -8.0, 8.0), (48, 64, 6, 1.0, 4.0), (112, 64, 3, -8.0, 8.0)])
 def test_bp_fused_last_iteration_with_per_edge_priors(L, n_shots, iters, lo, hi):
     """The fused last pass on a folded state (per-edge priors, as the CNN
     prior gives them, negative ones included) against the iteration and
-    posterior launched separately: corrections and posteriors bit for bit."""
+    posterior launched separately: corrections and posteriors bit for bit
+    (L = 112: 64-bit site addresses)."""
     announce(f"fused last BP iteration, per-edge priors L={L} S={n_shots} iters={iters}")
     out = decode_paths(L, n_shots, iters, 900 + L, 0.05, 0.9,
                        (tc.BP_STREAMING, tc.BP_STREAMING_SPLIT), l0=0.0, llr=(lo, hi))
